@@ -1,0 +1,294 @@
+"""Seeded generators for the synthetic workloads of the short-range tree force.
+
+The paper's own initial conditions (galaxy collision, LCDM with gas,
+collapsing gas sphere; Croker, ngravs, Appendix A) are not available, so the
+workloads below stand in for them: uniform boxes, and clustered boxes made of
+Plummer spheres plus a uniform background. Species are assigned independently
+of position, as the paper does when it redistributes collisionless particles
+evenly over the extra types (Appendix A).
+
+Force-factor tables are inputs of the method (the paper lets the user supply
+real-space tables for every species pair, section 2): they are built here
+from the Newtonian TreePM short-range factor (section 2.4.1) and, for the
+modified laws, from that factor times a Yukawa modulation of the form of
+Eq. (2).
+
+Everything is deterministic given the seed (numpy PCG64).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+from scipy.special import erfc
+
+__all__ = [
+    "Problem", "GRID_R", "GRID_R2", "largest_remainder", "exact_species",
+    "uniform_positions", "uniform_lattice", "clustered_positions",
+    "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
+    "sample_table", "scaled_params", "random_laws", "c1", "c2", "c3",
+    "clustered_problem", "uniform_problem", "batch_box",
+]
+
+GRID_R = "r"     # table samples uniform in r on [0, r_cut]
+GRID_R2 = "r2"   # table samples uniform in r^2 on [0, r_cut^2]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One force evaluation: particles, laws and walk parameters.
+
+    Positions are given either as float64 ``pos`` (shape (3, n), 0 <= x < box)
+    or as 64-bit lattice coordinates ``lattice`` (shape (3, n), uint64, the
+    point X * 2**-64 * box). Exactly one of the two is set.
+    ``G[a, b]`` and ``tables[a, b]`` act on a sink of species a from a source
+    of species b.
+    """
+    name: str
+    n: int
+    D: int
+    box: float
+    species: np.ndarray            # (n,) uint8
+    mass: np.ndarray               # (n,) float64
+    G: np.ndarray                  # (D, D) float64
+    tables: np.ndarray             # (D, D, ntab) float64
+    grid: str
+    r_s: float
+    r_cut: float
+    eps: float
+    theta: float
+    leaf_size: int = 16
+    group_size: int = 64
+    pos: Optional[np.ndarray] = None       # (3, n) float64
+    lattice: Optional[np.ndarray] = None   # (3, n) uint64
+    seed: int = 0
+
+    @property
+    def ntab(self) -> int:
+        return int(self.tables.shape[-1])
+
+
+# ----------------------------------------------------------------- species --
+def largest_remainder(total: int, fractions) -> np.ndarray:
+    """Integer counts summing to ``total`` in the given proportions."""
+    f = np.asarray(fractions, dtype=np.float64)
+    f = f / f.sum()
+    raw = f * total
+    base = np.floor(raw).astype(np.int64)
+    rest = total - int(base.sum())
+    order = np.argsort(-(raw - base), kind="stable")
+    base[order[:rest]] += 1
+    return base
+
+
+def exact_species(n: int, fractions, rng: np.random.Generator) -> np.ndarray:
+    """Species ids with exact counts, placed by a seeded random permutation."""
+    counts = largest_remainder(n, fractions)
+    s = np.repeat(np.arange(len(counts), dtype=np.uint8), counts)
+    return s[rng.permutation(n)]
+
+
+# --------------------------------------------------------------- positions --
+def uniform_positions(n: int, box: float, rng: np.random.Generator) -> np.ndarray:
+    x = rng.random((3, n)) * box
+    x[x >= box] = 0.0
+    return x
+
+
+def uniform_lattice(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Raw uniform 64-bit lattice coordinates, shape (3, n)."""
+    return rng.integers(0, np.iinfo(np.uint64).max, size=(3, n),
+                        dtype=np.uint64, endpoint=True)
+
+
+def _plummer_radii(m: int, a: np.ndarray, rng: np.random.Generator) -> np.ndarray:
+    """Plummer-sphere radii for scale radii ``a`` (length m), truncated at 10a."""
+    r = np.empty(m)
+    todo = np.arange(m)
+    while todo.size:
+        u = rng.random(todo.size)
+        u = np.maximum(u, 1e-300)
+        rr = a[todo] / np.sqrt(u ** (-2.0 / 3.0) - 1.0 + 1e-300)
+        ok = rr <= 10.0 * a[todo]
+        r[todo[ok]] = rr[ok]
+        todo = todo[~ok]
+    return r
+
+
+def clustered_positions(n: int, box: float, rng: np.random.Generator, *,
+                        f_cl: float = 0.7, halos: int = 2000,
+                        a_min: float = 0.002, a_max: float = 0.02,
+                        slope: float = -1.9, w_max: float = 1e3) -> np.ndarray:
+    """A fraction ``f_cl`` of the particles in Plummer spheres, the rest uniform.
+
+    Halo centres are uniform; scale radii are log-uniform in [a_min, a_max]
+    (units of the box); occupancy weights follow p(w) ~ w**slope on [1, w_max].
+    """
+    halos = max(1, int(halos))
+    n_cl = int(round(f_cl * n))
+    centres = rng.random((halos, 3)) * box
+    a = np.exp(rng.uniform(math.log(a_min), math.log(a_max), halos)) * box
+    u = rng.random(halos)
+    e = 1.0 + slope
+    w = (1.0 + u * (w_max ** e - 1.0)) ** (1.0 / e)
+    occ = largest_remainder(n_cl, w) if n_cl > 0 else np.zeros(halos, np.int64)
+    hid = np.repeat(np.arange(halos), occ)
+    r = _plummer_radii(hid.size, a[hid], rng)
+    d = rng.normal(size=(hid.size, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    p_cl = centres[hid] + r[:, None] * d
+    p_un = rng.random((n - n_cl, 3)) * box
+    p = np.concatenate([p_cl, p_un], axis=0)
+    p = np.mod(p, box)
+    p[p >= box] = 0.0
+    p = p[rng.permutation(n)]
+    return np.ascontiguousarray(p.T)
+
+
+# ------------------------------------------------------------------ tables --
+def newtonian_treepm_factor(r, r_s: float):
+    """Short-range modulation of the Newtonian force for a Gaussian split of
+    scale r_s (section 2.4.1): erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2)."""
+    r = np.asarray(r, dtype=np.float64)
+    return erfc(r / (2.0 * r_s)) + r / (r_s * math.sqrt(math.pi)) * np.exp(-r * r / (4.0 * r_s * r_s))
+
+
+def yukawa_product_factor(r, r_s: float, alpha: float, lam: float):
+    """Newtonian short-range factor times the force modulation of a Yukawa
+    correction of strength alpha and range lam (the Eq. (2) law with C = 1)."""
+    r = np.asarray(r, dtype=np.float64)
+    return newtonian_treepm_factor(r, r_s) * (1.0 + alpha * (1.0 + r / lam) * np.exp(-r / lam))
+
+
+def table_abscissae(ntab: int, r_cut: float, grid: str) -> np.ndarray:
+    """Radii of the table samples: uniform in r, or uniform in r^2."""
+    k = np.arange(ntab, dtype=np.float64)
+    if grid == GRID_R:
+        return k * (r_cut / (ntab - 1))
+    if grid == GRID_R2:
+        return np.sqrt(k * (r_cut * r_cut / (ntab - 1)))
+    raise ValueError(grid)
+
+
+def sample_table(fn, ntab: int, r_cut: float, grid: str) -> np.ndarray:
+    return np.asarray(fn(table_abscissae(ntab, r_cut, grid)), dtype=np.float64)
+
+
+def scaled_params(n: int, box: float = 1.0):
+    """r_s, r_cut, eps scaled from the 4096-particle setting by mean spacing."""
+    s = (4096.0 / n) ** (1.0 / 3.0) * box
+    r_s = 1.25 / 64.0 * s
+    return r_s, 4.5 * r_s, s / 640.0
+
+
+def random_laws(D: int, ntab: int, r_s: float, r_cut: float, grid: str,
+                rng: np.random.Generator, lam_range=(0.003, 0.03), box: float = 1.0):
+    """Random symmetric G in [-1, 2] and a random mix of Newtonian and
+    Yukawa-product tables (one law per unordered species pair)."""
+    G = np.zeros((D, D))
+    tables = np.zeros((D, D, ntab))
+    for a in range(D):
+        for b in range(a, D):
+            g = rng.uniform(-1.0, 2.0)
+            if rng.random() < 0.5:
+                t = sample_table(lambda r: newtonian_treepm_factor(r, r_s), ntab, r_cut, grid)
+            else:
+                lam = math.exp(rng.uniform(math.log(lam_range[0]), math.log(lam_range[1]))) * box
+                alpha = rng.uniform(-0.5, 1.0)
+                t = sample_table(lambda r: yukawa_product_factor(r, r_s, alpha, lam), ntab, r_cut, grid)
+            G[a, b] = G[b, a] = g
+            tables[a, b] = tables[b, a] = t
+    return G, tables
+
+
+# ----------------------------------------------------------------- configs --
+def c1(seed: int = 1) -> Problem:
+    """4096 uniform particles, two equal species, Newtonian short-range laws."""
+    n, D, box = 4096, 2, 1.0
+    rng = np.random.default_rng(seed)
+    lat = uniform_lattice(n, rng)
+    species = exact_species(n, [1, 1], rng)
+    r_s = 1.25 / 64.0
+    r_cut = 4.5 * r_s
+    ntab = 1024
+    t = sample_table(lambda r: newtonian_treepm_factor(r, r_s), ntab, r_cut, GRID_R)
+    return Problem(name=f"uniform-4096-D2-seed{seed}", n=n, D=D, box=box,
+                   species=species, mass=np.full(n, 1.0 / n), G=np.ones((D, D)),
+                   tables=np.broadcast_to(t, (D, D, ntab)).copy(), grid=GRID_R,
+                   r_s=r_s, r_cut=r_cut, eps=1.0 / (40.0 * 16.0), theta=0.5,
+                   lattice=lat, seed=seed)
+
+
+def c2(seed: int = 2, n: int = 2 ** 21) -> Problem:
+    """Clustered box, three species (50/30/20), Yukawa-modified laws and a
+    repulsive self-interaction of the third species."""
+    D, box = 3, 1.0
+    rng = np.random.default_rng(seed)
+    halos = max(1, int(round(2000 * n / 2 ** 21)))
+    pos = clustered_positions(n, box, rng, f_cl=0.7, halos=halos)
+    species = exact_species(n, [0.5, 0.3, 0.2], rng)
+    r_s, r_cut, eps = scaled_params(n, box)
+    ntab = 2048
+    lam = 0.01
+    alpha = np.array([[0, 0.5, 0], [0.5, 1, -0.3], [0, -0.3, 0]], dtype=np.float64)
+    tables = np.zeros((D, D, ntab))
+    for a in range(D):
+        for b in range(D):
+            tables[a, b] = sample_table(lambda r: yukawa_product_factor(r, r_s, alpha[a, b], lam),
+                                        ntab, r_cut, GRID_R)
+    G = np.ones((D, D))
+    G[2, 2] = -1.0
+    return Problem(name=f"clustered-{n}-D3-yukawa-seed{seed}", n=n, D=D, box=box,
+                   species=species, mass=np.full(n, 1.0 / n), G=G, tables=tables,
+                   grid=GRID_R, r_s=r_s, r_cut=r_cut, eps=eps, theta=0.5, pos=pos, seed=seed)
+
+
+def clustered_problem(n: int, D: int, seed: int, *, f_cl: float = 0.7,
+                      grid: str = GRID_R2, ntab: int = 2048, theta: float = 0.5,
+                      halos: Optional[int] = None, leaf_size: int = 16,
+                      group_size: int = 64, box: float = 1.0) -> Problem:
+    """Clustered box with D equal species and random laws."""
+    rng = np.random.default_rng(seed)
+    if halos is None:
+        halos = max(1, int(round(2000 * n / 2 ** 21)))
+    pos = clustered_positions(n, box, rng, f_cl=f_cl, halos=halos)
+    species = exact_species(n, np.ones(D), rng)
+    r_s, r_cut, eps = scaled_params(n, box)
+    G, tables = random_laws(D, ntab, r_s, r_cut, grid, rng, box=box)
+    return Problem(name=f"clustered-{n}-D{D}-seed{seed}", n=n, D=D, box=box,
+                   species=species, mass=np.full(n, 1.0 / n), G=G, tables=tables,
+                   grid=grid, r_s=r_s, r_cut=r_cut, eps=eps, theta=theta,
+                   leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed)
+
+
+def c3(seed: int = 3, n: int = 2 ** 24) -> Problem:
+    """Clustered box at scale: six species, random G and random mixed laws."""
+    p = clustered_problem(n, 6, seed, grid=GRID_R2, ntab=2048)
+    p.name = f"clustered-{n}-D6-seed{seed}"
+    return p
+
+
+def uniform_problem(n: int, D: int, seed: int, *, grid: str = GRID_R,
+                    ntab: int = 1024, theta: float = 0.5, leaf_size: int = 16,
+                    group_size: int = 64, box: float = 1.0) -> Problem:
+    rng = np.random.default_rng(seed)
+    pos = uniform_positions(n, box, rng)
+    species = exact_species(n, np.ones(D), rng)
+    r_s, r_cut, eps = scaled_params(n, box)
+    G, tables = random_laws(D, ntab, r_s, r_cut, grid, rng, box=box)
+    return Problem(name=f"uniform-{n}-D{D}-seed{seed}", n=n, D=D, box=box,
+                   species=species, mass=np.full(n, 1.0 / n), G=G, tables=tables,
+                   grid=grid, r_s=r_s, r_cut=r_cut, eps=eps, theta=theta,
+                   leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed)
+
+
+def batch_box(k: int) -> Problem:
+    """Box k of the many-box workload: N log-uniform in [2^12, 2^18], D in
+    {1..4}, clustered fraction in [0, 0.8], its own laws."""
+    rng = np.random.default_rng(4000 + k)
+    n = int(round(2.0 ** rng.uniform(12, 18)))
+    D = int(rng.integers(1, 5))
+    f_cl = float(rng.uniform(0.0, 0.8))
+    return clustered_problem(n, D, 4000 + k, f_cl=f_cl, grid=GRID_R2, ntab=2048)
