@@ -1,0 +1,226 @@
+/*
+ * ngravs-mi355x: periodic short-range Barnes-Hut tree force with one
+ * monopole per species in every node, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of K. A. S. Croker, "ngravs: Distinct gravitational
+ * interactions in GADGET-2" (Computer Physics Communications): D <= 6
+ * gravitating species (section 2), a per-pair force law f_ab given as a
+ * table of the short-range modulation of the Newtonian force (section 2.4.1,
+ * TreePM short-range forces), the active mass as a multiplier and the
+ * passive mass divided out (section 2.1 and Eq. (1)), and a tree whose
+ * nodes carry a mass and a centre of mass per species (section 2.2).
+ *
+ * The acceleration of particle i of species a is
+ *
+ *     a_i = sum_b sum_{sources j of species b, |d| < r_cut}
+ *               G_ab * mu_j * f_ab(|d|) * d / (|d|^2 + eps^2)^(3/2)
+ *
+ * with d the minimum-image offset source - sink in the periodic box, where a
+ * source is either another particle (mu_j its mass) or a node monopole of
+ * species b accepted by the opening test (mu_j the node's species-b mass).
+ * G_ab * f_ab > 0 attracts.
+ *
+ * Calling convention
+ *   - Every function returns an ngr_status and never aborts or throws.
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary CPU memory. All arrays are structure of
+ *     arrays: a 3 x n array is x[0..n), then y[0..n), then z[0..n).
+ *   - Pointers passed in are owned by the caller and only read (or, for
+ *     outputs, written) during the call. The tree copies what it needs.
+ *   - Calls run on the context's stream and return after their work is
+ *     complete (the stream is synchronised before returning).
+ *   - After a HIP error the context is poisoned: that call and every later
+ *     call on it return NGR_EDEVICE. Use ngr_last_error() for the text.
+ */
+#ifndef NGRAVS_H
+#define NGRAVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ngr_status;
+#define NGR_OK        0   /* success                                                  */
+#define NGR_EINVAL   (-1) /* invalid argument, detected before any output is written   */
+#define NGR_ENOMEM   (-2) /* device memory or a fixed device limit exhausted            */
+#define NGR_EDEVICE  (-3) /* a HIP error; the context is poisoned                       */
+#define NGR_ESTATE   (-4) /* wrong call order, e.g. force before monopoles              */
+
+#define NGR_MAX_SPECIES 6      /* section 2: 1 <= D <= 6                                */
+#define NGR_GRID_R      0      /* table samples uniform in r   on [0, r_cut], both ends */
+#define NGR_GRID_R2     1      /* table samples uniform in r^2 on [0, r_cut^2]          */
+#define NGR_MAX_TABLE   12288  /* D * ntab must not exceed this (one sink species' D
+                                  tables are held on chip during the walk)              */
+
+typedef struct ngr_context ngr_context;
+typedef struct ngr_tree ngr_tree;
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to
+ * run on, or NULL to create a private stream. The context owns a caching pool
+ * of device memory. */
+ngr_status ngr_context_create(int device, void* hip_stream, ngr_context** out);
+void ngr_context_destroy(ngr_context* ctx);
+/* Text of the last error on this context ("" when none). Valid until the
+ * next call on the context. */
+const char* ngr_last_error(const ngr_context* ctx);
+
+/* One particle set in a periodic cube of side `box`.
+ *   n        number of particles, 0 <= n < 2^32 (n == 0 is valid and empty)
+ *   D        number of species, 1..6
+ *   pos      device, 3 x n float64 positions (taken modulo box), or NULL
+ *   lattice  device, 3 x n uint64 lattice coordinates X (the point is
+ *            X * 2^-64 * box), or NULL. Exactly one of pos / lattice is set.
+ *   species  device, n uint8 ids in [0, D)
+ *   mass     device, n float64 masses, finite and >= 0                     */
+typedef struct {
+    uint64_t n;
+    uint32_t D;
+    double box;
+    const double* pos;
+    const uint64_t* lattice;
+    const uint8_t* species;
+    const double* mass;
+} ngr_particles;
+
+/* leaf_size: a node is a leaf once it holds at most this many particles of
+ * all species together (1..64; 0 means 16), or at the deepest level (20). */
+typedef struct {
+    uint32_t leaf_size;
+} ngr_tree_params;
+
+/*
+ * Build the tree (section 2: recursive halving of the box; section 2.4: one
+ * sort by species and then along the space-filling curve; section 2.2: the
+ * tree spans all species and every node records, per species, where its
+ * particles start and how many there are, N_perp).
+ * Steps on the device: positions -> 64-bit lattice, keys species<<60 |
+ * Morton60, stable radix sort, gather, breadth-first octree.
+ * Errors: NGR_EINVAL for D outside 1..6, box <= 0 or not finite, n >= 2^32,
+ * leaf_size > 64, missing pointers, both or neither of pos / lattice, a
+ * species id >= D, a mass < 0 or not finite, a position not finite.
+ * On success *out owns device memory until ngr_tree_free.
+ */
+ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p,
+                          const ngr_tree_params* tp, ngr_tree** out);
+
+/*
+ * Per-node, per-species monopoles (section 2.2): mass M_b (float64) and
+ * centre of mass (float64), reduced bottom-up level by level. Must precede
+ * ngr_tree_force. `track_counts` is accepted for the N_perp option of
+ * section 2.2; counts are always available from the build.
+ */
+ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_counts);
+
+/* Force-law and walk parameters.
+ *   G        host, D x D float64, row = sink species a, column = source b
+ *   tables   host, D x D x ntab float64 samples of f_ab on `grid`, or NULL
+ *            for the Newtonian short-range factor
+ *            erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2) for every pair
+ *   ntab     samples per table, >= 2, D * ntab <= NGR_MAX_TABLE
+ *   grid     NGR_GRID_R or NGR_GRID_R2; f between samples is the straight
+ *            line through the two neighbours, f = 0 for r >= r_cut
+ *   r_s      split scale, used only when tables == NULL (> 0 then)
+ *   r_cut    cut-off radius, 0 < r_cut < box / 2
+ *   eps      Plummer softening, >= 0
+ *   theta    opening angle, > 0
+ *   group_size  sinks per walk, 16, 32 or 64 (0 means 64)
+ */
+typedef struct {
+    const double* G;
+    const double* tables;
+    uint32_t ntab;
+    uint32_t grid;
+    double r_s;
+    double r_cut;
+    double eps;
+    double theta;
+    uint32_t group_size;
+} ngr_force_params;
+
+/* Filled by ngr_tree_force (host). An interaction is one evaluation of the
+ * pair term on an interaction-list entry: a particle of an opened leaf
+ * (sink itself excluded) or a non-empty species monopole of an accepted
+ * node, whether or not it falls inside r_cut. */
+typedef struct {
+    uint64_t interactions_pp;
+    uint64_t interactions_pn;
+    uint64_t n_nodes;
+    uint64_t n_leaves;
+    uint64_t n_groups;
+    uint32_t group_size;
+    uint32_t depth;
+    double ms_groups;
+    double ms_walk;
+} ngr_force_stats;
+
+/*
+ * Short-range tree force (the walk of section 2.2 restricted to short range
+ * as in section 2.4.1), one walk per species-pure group of sinks.
+ *   acc   device, 3 x n float64, written in input order.
+ *   st    host, may be NULL.
+ * Opening test, on the exact integer key lattice: with d_min the smallest
+ * periodic distance between a node's cell and the group's bounding box and
+ * d_max an upper bound on the largest, the node is skipped when
+ * d_min >= r_cut, used as monopoles when side < theta * d_min and
+ * d_max < r_cut, and opened otherwise.
+ * Errors: NGR_EINVAL for bad parameters (see ngr_force_params), non-finite
+ * G or table entries, NULL acc with n > 0; NGR_ESTATE without monopoles.
+ */
+ngr_status ngr_tree_force(ngr_context* ctx, const ngr_tree* tree,
+                          const ngr_force_params* fp, double* acc,
+                          ngr_force_stats* st);
+
+/* Release a tree. NULL is accepted. */
+ngr_status ngr_tree_free(ngr_context* ctx, ngr_tree* tree);
+
+/* ---- inspection (for tests and tools; all outputs are host arrays) ---- */
+
+/* Sizes: particles, nodes, tree depth (deepest level). */
+ngr_status ngr_tree_info(const ngr_tree* tree, uint64_t* n, uint64_t* n_nodes,
+                         uint32_t* D, uint32_t* depth);
+
+/* Copy the build's results to host arrays (any may be NULL):
+ *   perm   n uint32, sorted position -> input index
+ *   keys   n uint64, sorted keys species<<60 | Morton60
+ *   lattice 3 x n uint64 in sorted order
+ *   level  n_nodes uint8;  prefix n_nodes uint64 (3*level bits of the key)
+ *   parent n_nodes int32 (-1 for the root); first_child n_nodes int32 (-1 for
+ *          a leaf); n_child n_nodes uint8
+ *   start, count  D x n_nodes uint32: first sorted index and number of the
+ *          node's particles of each species
+ * Nodes are breadth first: ordered by level, then by prefix. */
+ngr_status ngr_tree_export(ngr_context* ctx, const ngr_tree* tree,
+                           uint32_t* perm, uint64_t* keys, uint64_t* lattice,
+                           uint8_t* level, uint64_t* prefix, int32_t* parent,
+                           int32_t* first_child, uint8_t* n_child,
+                           uint32_t* start, uint32_t* count);
+
+/* Monopoles to host: M D x n_nodes, com D x 3 x n_nodes (positions in
+ * [0, box)). */
+ngr_status ngr_monopoles_export(ngr_context* ctx, const ngr_tree* tree,
+                                double* M, double* com);
+
+/* Sink groups for a group size (see ngr_force_params.group_size), to host.
+ * Call once with species == NULL to get *n_groups, then with arrays of that
+ * size: species uint8, start/count uint32 (sorted positions), lo/hi 3 x
+ * n_groups uint32 (bounding box on the 20-bit key lattice, hi exclusive). */
+ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree,
+                             uint32_t group_size, uint64_t* n_groups,
+                             uint8_t* species, uint32_t* start, uint32_t* count,
+                             uint32_t* lo, uint32_t* hi);
+
+/* As ngr_tree_force, and also write per-group counts to the host array
+ * group_counts (4 x n_groups uint64 per group: accepted nodes, opened
+ * leaves, pn interactions, pp interactions), groups in the order of
+ * ngr_groups_export. */
+ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree,
+                                 const ngr_force_params* fp, double* acc,
+                                 ngr_force_stats* st, uint64_t* group_counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -160,8 +160,11 @@ class Tree:
 
     def __del__(self):
         t = getattr(self, "_t", None)
-        if t:
-            lib().orc_tree_free(t)
+        if t and _lib is not None:
+            try:
+                _lib.orc_tree_free(t)
+            except Exception:
+                pass
             self._t = None
 
     def nodes(self) -> dict:

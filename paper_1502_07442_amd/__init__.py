@@ -1,0 +1,234 @@
+"""Python binding of libngravs (include/ngravs.h): argument marshalling only.
+
+Every step of the force computation runs in the HIP kernels of the shared
+library; this module only turns torch device tensors and numpy host arrays
+into the pointers and sizes of the C-ABI, on torch's current HIP stream.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libngravs.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
+GRID_R, GRID_R2 = 0, 1
+GRIDS = {"r": GRID_R, "r2": GRID_R2, GRID_R: GRID_R, GRID_R2: GRID_R2}
+MAX_SPECIES = 6
+EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_tree_build",
+            "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_free",
+            "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export"]
+
+
+class NgravsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ngravs status {status}: {msg}")
+        self.status = status
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("D", C.c_uint32), ("box", C.c_double), ("pos", C.c_void_p),
+                ("lattice", C.c_void_p), ("species", C.c_void_p), ("mass", C.c_void_p)]
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("leaf_size", C.c_uint32)]
+
+
+class ForceParams(C.Structure):
+    _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32), ("grid", C.c_uint32),
+                ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
+                ("group_size", C.c_uint32)]
+
+
+class ForceStats(C.Structure):
+    _fields_ = [("interactions_pp", C.c_uint64), ("interactions_pn", C.c_uint64), ("n_nodes", C.c_uint64),
+                ("n_leaves", C.c_uint64), ("n_groups", C.c_uint64), ("group_size", C.c_uint32),
+                ("depth", C.c_uint32), ("ms_groups", C.c_double), ("ms_walk", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libngravs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32
+        sig = {
+            "ngr_context_create": (i32, [C.c_int, P, P]),
+            "ngr_context_destroy": (None, [P]),
+            "ngr_last_error": (C.c_char_p, [P]),
+            "ngr_tree_build": (i32, [P, P, P, P]),
+            "ngr_compute_monopoles": (i32, [P, P, C.c_int]),
+            "ngr_tree_force": (i32, [P, P, P, P, P]),
+            "ngr_tree_force_counts": (i32, [P, P, P, P, P, P]),
+            "ngr_tree_free": (i32, [P, P]),
+            "ngr_tree_info": (i32, [P, P, P, P, P]),
+            "ngr_tree_export": (i32, [P] * 12),
+            "ngr_monopoles_export": (i32, [P] * 4),
+            "ngr_groups_export": (i32, [P, P, u32, P, P, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _ = u64
+        _lib = L
+    return _lib
+
+
+def _np(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """A library context on one HIP device, bound to a HIP stream (default:
+    torch's current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = stream if isinstance(stream, int) else stream.cuda_stream
+        self._h = C.c_void_p()
+        self._check(lib().ngr_context_create(device, C.c_void_p(handle), C.byref(self._h)), "context create")
+        self.device = device
+
+    def _check(self, status: int, what: str):
+        if status != OK:
+            msg = lib().ngr_last_error(self._h).decode() if getattr(self, "_h", None) else what
+            raise NgravsError(status, msg or what)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ngr_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, handle: C.c_void_p):
+        self.ctx, self._h = ctx, handle
+        n, nn, D, depth = C.c_uint64(), C.c_uint64(), C.c_uint32(), C.c_uint32()
+        lib().ngr_tree_info(handle, C.byref(n), C.byref(nn), C.byref(D), C.byref(depth))
+        self.n, self.n_nodes, self.D, self.depth = n.value, nn.value, D.value, depth.value
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def tree_build(ctx: Context, *, D: int, box: float, species, mass, pos=None, lattice=None,
+               leaf_size: int = 16) -> Tree:
+    """ngr_tree_build: device tensors species (uint8, n), mass (float64, n) and
+    either pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n)."""
+    n = int(species.shape[0])
+    p = Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
+    tp = TreeParams(leaf_size)
+    h = C.c_void_p()
+    ctx._check(lib().ngr_tree_build(ctx.handle, C.byref(p), C.byref(tp), C.byref(h)), "tree build")
+    return Tree(ctx, h)
+
+
+def compute_monopoles(ctx: Context, tree: Tree, track_counts: bool = True):
+    ctx._check(lib().ngr_compute_monopoles(ctx.handle, tree.handle, int(track_counts)), "monopoles")
+
+
+def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None):
+    G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
+    if tables is not None:
+        tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
+        ntab = tables.shape[-1]
+    fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS[grid],
+                     float(r_s), float(r_cut), float(eps), float(theta), int(group_size))
+    fp._keep = (G, tables)
+    return fp
+
+
+def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
+               group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False):
+    """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
+    G (D x D) and tables (D x D x ntab, or None) are host arrays. Returns the
+    statistics as a dict (and per-group counts when asked)."""
+    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab)
+    st = ForceStats()
+    if group_counts:
+        ng = groups_count(ctx, tree, group_size)
+        gc = np.zeros((max(ng, 1), 4), np.uint64)
+        ctx._check(lib().ngr_tree_force_counts(ctx.handle, tree.handle, C.byref(fp), C.c_void_p(_dev(acc)),
+                                               C.byref(st), _np(gc)), "tree force")
+        return st.as_dict(), gc[:ng]
+    ctx._check(lib().ngr_tree_force(ctx.handle, tree.handle, C.byref(fp), C.c_void_p(_dev(acc)), C.byref(st)),
+               "tree force")
+    return st.as_dict()
+
+
+def tree_free(ctx: Context, tree: Tree):
+    if tree._h:
+        ctx._check(lib().ngr_tree_free(ctx.handle, tree.handle), "tree free")
+        tree._h = None
+
+
+def tree_export(ctx: Context, tree: Tree) -> dict:
+    n, nn, D = tree.n, tree.n_nodes, tree.D
+    out = dict(perm=np.empty(n, np.uint32), keys=np.empty(n, np.uint64), lattice=np.empty((3, n), np.uint64),
+               level=np.empty(nn, np.uint8), prefix=np.empty(nn, np.uint64), parent=np.empty(nn, np.int32),
+               first_child=np.empty(nn, np.int32), n_child=np.empty(nn, np.uint8),
+               start=np.empty((D, nn), np.uint32), count=np.empty((D, nn), np.uint32))
+    ctx._check(lib().ngr_tree_export(ctx.handle, tree.handle, *[_np(out[k]) for k in
+                                     ("perm", "keys", "lattice", "level", "prefix", "parent", "first_child",
+                                      "n_child", "start", "count")]), "tree export")
+    return out
+
+
+def monopoles_export(ctx: Context, tree: Tree):
+    M = np.empty((tree.D, tree.n_nodes))
+    com = np.empty((tree.D, 3, tree.n_nodes))
+    ctx._check(lib().ngr_monopoles_export(ctx.handle, tree.handle, _np(M), _np(com)), "monopoles export")
+    return M, com
+
+
+def groups_count(ctx: Context, tree: Tree, group_size: int = 64) -> int:
+    ng = C.c_uint64()
+    ctx._check(lib().ngr_groups_export(ctx.handle, tree.handle, group_size, C.byref(ng), None, None, None, None,
+                                       None), "groups export")
+    return ng.value
+
+
+def groups_export(ctx: Context, tree: Tree, group_size: int = 64) -> dict:
+    ng = groups_count(ctx, tree, group_size)
+    out = dict(species=np.empty(ng, np.uint8), start=np.empty(ng, np.uint32), count=np.empty(ng, np.uint32),
+               lo=np.empty((3, ng), np.uint32), hi=np.empty((3, ng), np.uint32))
+    n2 = C.c_uint64()
+    ctx._check(lib().ngr_groups_export(ctx.handle, tree.handle, group_size, C.byref(n2),
+                                       *[_np(out[k]) for k in ("species", "start", "count", "lo", "hi")]),
+               "groups export")
+    return out

@@ -1,0 +1,460 @@
+// The C-ABI of libngravs: argument checks on the host before any device
+// work, error statuses, and the context's stream and memory.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "ngr_internal.hpp"
+
+#define NGR_API extern "C" __attribute__((visibility("default")))
+
+struct ngr_context : ngr::Context {};
+struct ngr_tree : ngr::Tree {};
+
+namespace ngr {
+
+void fail(ngr_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line)
+{
+    if (e == hipSuccess) return;
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    fail(e == hipErrorOutOfMemory ? NGR_ENOMEM : NGR_EDEVICE, buf);
+}
+
+void* Context::alloc(size_t bytes)
+{
+    size_t cls = 256;
+    while (cls < bytes) cls += cls < (1u << 20) ? cls : (cls >> 2);   // 256 B doubling, then 25 % steps
+    auto it = free_blocks.lower_bound(cls);
+    if (it != free_blocks.end() && it->first <= cls + (cls >> 1)) {
+        void* p = it->second;
+        live_blocks[p] = it->first;
+        free_blocks.erase(it);
+        return p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        // give cached blocks back and try once more
+        sync();
+        for (auto& kv : free_blocks) (void)hipFree(kv.second);
+        free_blocks.clear();
+        e = hipMalloc(&p, cls);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            fail(NGR_ENOMEM, "device memory exhausted");
+        }
+    }
+    hip_check(e, "hipMalloc", __FILE__, __LINE__);
+    live_blocks[p] = cls;
+    return p;
+}
+
+void Context::release(void* p)
+{
+    if (!p) return;
+    auto it = live_blocks.find(p);
+    if (it == live_blocks.end()) fail(NGR_EDEVICE, "release of a block the pool does not own");
+    free_blocks.emplace(it->second, p);
+    live_blocks.erase(it);
+}
+
+void Context::free_all()
+{
+    for (auto& kv : free_blocks) (void)hipFree(kv.second);
+    for (auto& kv : live_blocks) (void)hipFree(kv.first);
+    free_blocks.clear();
+    live_blocks.clear();
+}
+
+void Context::ensure(DevMem& m, size_t bytes)
+{
+    if (m.bytes >= bytes) return;
+    release(m.p);
+    m.p = alloc(bytes);
+    m.bytes = bytes;
+}
+
+void Context::stage(const char* what)
+{
+    if (trace) {
+        std::fprintf(stderr, "[ngravs] %s\n", what);
+        std::fflush(stderr);
+    }
+}
+
+void Context::read_words(uint64_t* host, const void* dev, size_t words)
+{
+    if (words > kPinnedWords) fail(NGR_EINVAL, "read_words: too many words");
+    hip_check(hipMemcpyAsync(pinned, dev, words * sizeof(uint64_t), hipMemcpyDeviceToHost, stream),
+              "hipMemcpyAsync", __FILE__, __LINE__);
+    sync();
+    std::memcpy(host, pinned, words * sizeof(uint64_t));
+}
+
+void Context::write_words(void* dev, const uint64_t* host, size_t words)
+{
+    if (words > kPinnedWords) fail(NGR_EINVAL, "write_words: too many words");
+    sync();
+    std::memcpy(pinned, host, words * sizeof(uint64_t));
+    hip_check(hipMemcpyAsync(dev, pinned, words * sizeof(uint64_t), hipMemcpyHostToDevice, stream),
+              "hipMemcpyAsync", __FILE__, __LINE__);
+    sync();
+}
+
+void Context::to_host(void* host, const void* dev, size_t bytes)
+{
+    if (!bytes) return;
+    sync();
+    hip_check(hipMemcpy(host, dev, bytes, hipMemcpyDeviceToHost), "hipMemcpy", __FILE__, __LINE__);
+}
+
+void Context::to_device(void* dev, const void* host, size_t bytes)
+{
+    if (!bytes) return;
+    sync();
+    hip_check(hipMemcpy(dev, host, bytes, hipMemcpyHostToDevice), "hipMemcpy", __FILE__, __LINE__);
+}
+
+void Context::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize", __FILE__, __LINE__); }
+
+}  // namespace ngr
+
+namespace {
+
+template <class F>
+ngr_status guarded(ngr_context* ctx, F&& f)
+{
+    if (!ctx) return NGR_EINVAL;
+    if (ctx->poisoned) return NGR_EDEVICE;
+    try {
+        ngr::hip_check(hipSetDevice(ctx->device), "hipSetDevice", __FILE__, __LINE__);
+        f();
+        ctx->err.clear();
+        return NGR_OK;
+    } catch (const ngr::Error& e) {
+        ctx->err = e.msg;
+        if (e.status == NGR_EDEVICE) ctx->poisoned = true;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host memory exhausted";
+        return NGR_ENOMEM;
+    }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+void free_tree_memory(ngr::Context& c, ngr::Tree& t)
+{
+    c.release(t.X);
+    c.release(t.mass);
+    c.release(t.perm);
+    c.release(t.keys);
+    c.release(t.level);
+    c.release(t.prefix);
+    c.release(t.parent);
+    c.release(t.first_child);
+    c.release(t.n_child);
+    c.release(t.cell);
+    c.release(t.start);
+    c.release(t.count);
+    c.release(t.mono);
+}
+
+void check_force_params(const ngr::Tree& t, const ngr_force_params* fp, uint32_t* group_size)
+{
+    using ngr::fail;
+    if (!fp) fail(NGR_EINVAL, "force params are NULL");
+    if (!fp->G) fail(NGR_EINVAL, "G is NULL");
+    const uint32_t D = t.D;
+    if (fp->ntab < 2) fail(NGR_EINVAL, "ntab must be >= 2");
+    if ((uint64_t)D * fp->ntab > NGR_MAX_TABLE) fail(NGR_EINVAL, "D * ntab exceeds NGR_MAX_TABLE");
+    if (fp->grid != NGR_GRID_R && fp->grid != NGR_GRID_R2) fail(NGR_EINVAL, "grid must be NGR_GRID_R or NGR_GRID_R2");
+    if (!finite_pos(fp->r_cut)) fail(NGR_EINVAL, "r_cut must be finite and > 0");
+    if (!(fp->r_cut < 0.5 * t.box)) fail(NGR_EINVAL, "r_cut must be < box / 2");
+    if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, "eps must be finite and >= 0");
+    if (!finite_pos(fp->theta)) fail(NGR_EINVAL, "theta must be finite and > 0");
+    if (!fp->tables && !finite_pos(fp->r_s)) fail(NGR_EINVAL, "r_s must be finite and > 0 when tables is NULL");
+    uint32_t gs = fp->group_size ? fp->group_size : 64;
+    if (gs != 16 && gs != 32 && gs != 64) fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
+    for (uint32_t k = 0; k < D * D; ++k)
+        if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, "G has a non-finite entry");
+    if (fp->tables)
+        for (uint64_t k = 0; k < (uint64_t)D * D * fp->ntab; ++k)
+            if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, "a table entry is not finite");
+    *group_size = gs;
+}
+
+ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
+                      ngr_force_stats* st, uint64_t* group_counts_host)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!tree) fail(NGR_EINVAL, "tree is NULL");
+        if (!tree->has_monopoles) fail(NGR_ESTATE, "ngr_compute_monopoles must precede ngr_tree_force");
+        uint32_t gs = 64;
+        check_force_params(*tree, fp, &gs);
+        if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
+        ngr::Context& c = *ctx;
+        ngr::Groups g;
+        ngr::Law law;
+        ngr::WalkOut wo;
+        uint64_t* gc = nullptr;
+        hipEvent_t e0, e1;
+        ngr::hip_check(hipEventCreate(&e0), "hipEventCreate", __FILE__, __LINE__);
+        ngr::hip_check(hipEventCreate(&e1), "hipEventCreate", __FILE__, __LINE__);
+        try {
+            ngr::hip_check(hipEventRecord(e0, c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::make_groups(c, *tree, gs, g);
+            ngr::hip_check(hipEventRecord(e1, c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::upload_law(c, *fp, tree->D, law);
+            if (group_counts_host && g.ng) gc = static_cast<uint64_t*>(c.alloc(g.ng * 4 * sizeof(uint64_t)));
+            ngr::walk_force(c, *tree, g, law, acc, gc, wo);
+            if (gc) c.to_host(group_counts_host, gc, g.ng * 4 * sizeof(uint64_t));
+            c.sync();
+        } catch (...) {
+            c.release(gc);
+            c.release(law.table);
+            g.free(c);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        float ms_groups = 0.0f;
+        ngr::hip_check(hipEventElapsedTime(&ms_groups, e0, e1), "hipEventElapsedTime", __FILE__, __LINE__);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st) {
+            std::memset(st, 0, sizeof *st);
+            st->interactions_pp = wo.pp;
+            st->interactions_pn = wo.pn;
+            st->n_nodes = tree->nn;
+            st->n_leaves = tree->n_leaves;
+            st->n_groups = g.ng;
+            st->group_size = gs;
+            st->depth = tree->depth;
+            st->ms_groups = ms_groups;
+            st->ms_walk = wo.ms_walk;
+        }
+        c.release(gc);
+        c.release(law.table);
+        g.free(c);
+    });
+}
+
+}  // namespace
+
+NGR_API ngr_status ngr_context_create(int device, void* hip_stream, ngr_context** out)
+{
+    if (!out) return NGR_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return device < 0 ? NGR_EINVAL : NGR_EDEVICE;
+    ngr_context* c = new (std::nothrow) ngr_context();
+    if (!c) return NGR_ENOMEM;
+    c->device = device;
+    try {
+        ngr::hip_check(hipSetDevice(device), "hipSetDevice", __FILE__, __LINE__);
+        hipDeviceProp_t prop;
+        ngr::hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties", __FILE__, __LINE__);
+        c->num_cu = prop.multiProcessorCount;
+        if (hip_stream) {
+            c->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            ngr::hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate", __FILE__,
+                           __LINE__);
+            c->own_stream = true;
+        }
+        ngr::hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), ngr::Context::kPinnedWords * sizeof(uint64_t),
+                                     hipHostMallocDefault),
+                       "hipHostMalloc", __FILE__, __LINE__);
+        const char* tr = std::getenv("NGR_TRACE");
+        c->trace = tr && tr[0] && tr[0] != '0';
+        c->lds_per_block = prop.sharedMemPerBlock;
+    } catch (const ngr::Error& e) {
+        delete c;
+        return e.status;
+    }
+    *out = c;
+    return NGR_OK;
+}
+
+NGR_API void ngr_context_destroy(ngr_context* ctx)
+{
+    if (!ctx) return;
+    if (!ctx->poisoned) (void)hipStreamSynchronize(ctx->stream);
+    ctx->free_all();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+NGR_API const char* ngr_last_error(const ngr_context* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+NGR_API ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p, const ngr_tree_params* tp, ngr_tree** out)
+{
+    if (out) *out = nullptr;
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!p || !out) fail(NGR_EINVAL, "particles or out is NULL");
+        if (p->D < 1 || p->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, "D must be in 1..6");
+        if (!finite_pos(p->box)) fail(NGR_EINVAL, "box must be finite and > 0");
+        if (p->n >= (1ull << 32) - 1) fail(NGR_EINVAL, "n must be < 2^32 - 1");
+        uint32_t B = tp && tp->leaf_size ? tp->leaf_size : 16;
+        if (B > 64) fail(NGR_EINVAL, "leaf_size must be in 1..64");
+        if (p->n) {
+            if (!p->species || !p->mass) fail(NGR_EINVAL, "species or mass is NULL");
+            if ((p->pos == nullptr) == (p->lattice == nullptr)) fail(NGR_EINVAL, "exactly one of pos and lattice must be set");
+        }
+        ngr_tree* t = new ngr_tree();
+        try {
+            ngr::build_tree(*ctx, *p, B, *t);
+            ctx->sync();
+        } catch (...) {
+            try {
+                free_tree_memory(*ctx, *t);
+            } catch (...) {
+            }
+            delete t;
+            throw;
+        }
+        *out = t;
+    });
+}
+
+NGR_API ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_counts)
+{
+    (void)track_counts;
+    return guarded(ctx, [&] {
+        if (!tree) ngr::fail(NGR_EINVAL, "tree is NULL");
+        ngr::compute_monopoles(*ctx, *tree);
+        ctx->sync();
+    });
+}
+
+NGR_API ngr_status ngr_tree_force(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
+                                  ngr_force_stats* st)
+{
+    return force_impl(ctx, tree, fp, acc, st, nullptr);
+}
+
+NGR_API ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp,
+                                         double* acc, ngr_force_stats* st, uint64_t* group_counts)
+{
+    return force_impl(ctx, tree, fp, acc, st, group_counts);
+}
+
+NGR_API ngr_status ngr_tree_free(ngr_context* ctx, ngr_tree* tree)
+{
+    if (!tree) return NGR_OK;
+    if (!ctx) return NGR_EINVAL;
+    ngr_status s = guarded(ctx, [&] {
+        free_tree_memory(*ctx, *tree);
+        ctx->sync();
+    });
+    delete tree;
+    return s;
+}
+
+NGR_API ngr_status ngr_tree_info(const ngr_tree* tree, uint64_t* n, uint64_t* n_nodes, uint32_t* D, uint32_t* depth)
+{
+    if (!tree) return NGR_EINVAL;
+    if (n) *n = tree->n;
+    if (n_nodes) *n_nodes = tree->nn;
+    if (D) *D = tree->D;
+    if (depth) *depth = tree->depth;
+    return NGR_OK;
+}
+
+namespace {
+template <class T>
+void copy_out(ngr::Context& c, T* host, const T* dev, uint64_t count)
+{
+    if (host && count) c.to_host(host, dev, count * sizeof(T));
+}
+}  // namespace
+
+NGR_API ngr_status ngr_tree_export(ngr_context* ctx, const ngr_tree* tree, uint32_t* perm, uint64_t* keys,
+                                   uint64_t* lattice, uint8_t* level, uint64_t* prefix, int32_t* parent,
+                                   int32_t* first_child, uint8_t* n_child, uint32_t* start, uint32_t* count)
+{
+    return guarded(ctx, [&] {
+        if (!tree) ngr::fail(NGR_EINVAL, "tree is NULL");
+        const uint64_t n = tree->n, nn = tree->nn, D = tree->D;
+        copy_out(*ctx, perm, tree->perm, n);
+        copy_out(*ctx, keys, tree->keys, n);
+        copy_out(*ctx, lattice, tree->X, 3 * n);
+        copy_out(*ctx, level, tree->level, nn);
+        copy_out(*ctx, prefix, tree->prefix, nn);
+        copy_out(*ctx, parent, tree->parent, nn);
+        copy_out(*ctx, first_child, tree->first_child, nn);
+        copy_out(*ctx, n_child, tree->n_child, nn);
+        std::vector<uint32_t> tmp;
+        for (int which = 0; which < 2; ++which) {
+            uint32_t* dst = which ? count : start;
+            if (!dst || !nn) continue;
+            tmp.resize(nn * D);
+            copy_out(*ctx, tmp.data(), which ? tree->count : tree->start, nn * D);
+            ctx->sync();
+            for (uint64_t i = 0; i < nn; ++i)
+                for (uint64_t b = 0; b < D; ++b) dst[b * nn + i] = tmp[i * D + b];
+        }
+        ctx->sync();
+    });
+}
+
+NGR_API ngr_status ngr_monopoles_export(ngr_context* ctx, const ngr_tree* tree, double* M, double* com)
+{
+    return guarded(ctx, [&] {
+        if (!tree) ngr::fail(NGR_EINVAL, "tree is NULL");
+        if (!tree->has_monopoles) ngr::fail(NGR_ESTATE, "no monopoles");
+        const uint64_t nn = tree->nn, D = tree->D;
+        std::vector<double4> h(nn * D);
+        copy_out(*ctx, h.data(), tree->mono, nn * D);
+        ctx->sync();
+        for (uint64_t b = 0; b < D; ++b)
+            for (uint64_t i = 0; i < nn; ++i) {
+                const double4 r = h[b * nn + i];
+                if (M) M[b * nn + i] = r.w;
+                if (com) {
+                    com[(b * 3 + 0) * nn + i] = r.x * tree->box;
+                    com[(b * 3 + 1) * nn + i] = r.y * tree->box;
+                    com[(b * 3 + 2) * nn + i] = r.z * tree->box;
+                }
+            }
+    });
+}
+
+NGR_API ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree, uint32_t group_size, uint64_t* n_groups,
+                                     uint8_t* species, uint32_t* start, uint32_t* count, uint32_t* lo, uint32_t* hi)
+{
+    return guarded(ctx, [&] {
+        if (!tree || !n_groups) ngr::fail(NGR_EINVAL, "tree or n_groups is NULL");
+        uint32_t gs = group_size ? group_size : 64;
+        if (gs != 16 && gs != 32 && gs != 64) ngr::fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
+        ngr::Groups g;
+        try {
+            ngr::make_groups(*ctx, *tree, gs, g);
+            *n_groups = g.ng;
+            if (species) {
+                for (uint32_t a = 0; a < tree->D; ++a)
+                    for (uint64_t k = g.first[a]; k < g.first[a + 1]; ++k) species[k] = (uint8_t)a;
+                copy_out(*ctx, start, g.start, g.ng);
+                copy_out(*ctx, count, g.count, g.ng);
+                copy_out(*ctx, lo, g.lo, 3 * g.ng);
+                copy_out(*ctx, hi, g.hi, 3 * g.ng);
+            }
+            ctx->sync();
+        } catch (...) {
+            g.free(*ctx);
+            throw;
+        }
+        g.free(*ctx);
+        ctx->sync();
+    });
+}

@@ -1,0 +1,692 @@
+// Sink groups and the short-range group tree walk.
+//
+// Paper: Croker, ngravs (CPC). Eq. (1) and section 2.1: the pair force of a
+// sink of species a and a source of species b is a per-pair law f_ab times
+// the Newtonian force, with the active mass as a multiplier and the passive
+// mass divided out. Section 2.2: one walk vectorised over the species'
+// monopoles of each node; in the limit of one particle per monopole the walk
+// reproduces the direct sum. Section 2.4.1: in TreePM mode the walk is
+// restricted to short range and the force is modulated by a table of N_TAB
+// samples of the short-range factor.
+//
+// Design (gfx950): one wavefront walks the tree for one species-pure group of
+// at most 64 sinks (one sink per lane). The traversal is breadth-first in
+// batches of 64 nodes, one node per lane, on a per-wave stack in device
+// memory; nodes whose monopoles are accepted and leaves that are opened are
+// buffered in LDS. Full buffers are expanded, one source species at a time,
+// into LDS records {offset from the group centre (float64 x3), G_ab * mass}
+// that every lane reads by broadcast while it evaluates the pair term for its
+// own sink. The sink species' D force-factor tables sit in LDS as
+// (value, slope) pairs and are read by a per-lane gather.
+//
+// Arithmetic per pair: offsets, r^2 and the accumulation in float64 (full
+// rate on the vector ALU, like unpacked float32), the table interpolation in
+// float32, and (r^2 + eps^2)^(-3/2) from the float32 reciprocal square root
+// refined by one float64 correction step.
+#include <algorithm>
+#include <cmath>
+
+#include "ngr_internal.hpp"
+
+namespace ngr {
+namespace {
+
+// ------------------------------------------------------------- groups ----
+// One thread per (node, species a). For a node holding more than Ng particles
+// of species a: a leaf is cut into chunks of Ng; an internal node groups runs
+// of consecutive children whose species-a counts add up to at most Ng
+// (children with more than Ng are handled by their own thread). The root
+// forms one group when it holds at most Ng. Every group start is flagged.
+__global__ void mark_group_starts(uint64_t nn, uint32_t D, uint32_t Ng, const uint32_t* __restrict__ start,
+                                  const uint32_t* __restrict__ count, const int32_t* __restrict__ first_child,
+                                  const uint8_t* __restrict__ n_child, uint32_t* __restrict__ flags)
+{
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * D) return;
+    uint64_t i = t / D;
+    uint32_t a = (uint32_t)(t % D);
+    uint32_t na = count[i * D + a];
+    if (na == 0) return;
+    if (na <= Ng) {
+        if (i == 0) flags[start[a]] = 1;
+        return;
+    }
+    if (n_child[i] == 0) {
+        uint32_t s0 = start[i * D + a];
+        for (uint32_t k = 0; k < na; k += Ng) flags[s0 + k] = 1;
+        return;
+    }
+    uint32_t run = 0;
+    uint64_t c0 = (uint64_t)first_child[i], c1 = c0 + n_child[i];
+    for (uint64_t c = c0; c < c1; ++c) {
+        uint32_t nc = count[c * D + a];
+        if (nc == 0) continue;
+        if (nc > Ng) {
+            run = 0;
+            continue;
+        }
+        if (run + nc > Ng) run = 0;
+        if (run == 0) flags[start[c * D + a]] = 1;
+        run += nc;
+    }
+}
+
+__global__ void scatter_group_starts(uint64_t n, const uint32_t* __restrict__ flags,
+                                     const uint32_t* __restrict__ gidx, uint32_t* __restrict__ gstart)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flags[i]) gstart[gidx[i]] = (uint32_t)i;
+}
+
+// Count and integer bounding box (20-bit key lattice, hi exclusive) of each
+// group; a group ends where the next one starts.
+__global__ void finish_groups(uint64_t ng, uint64_t n, uint32_t Ng, const uint32_t* __restrict__ gstart,
+                              uint32_t* __restrict__ gcount, uint32_t* __restrict__ glo, uint32_t* __restrict__ ghi,
+                              const uint64_t* __restrict__ X, uint32_t* __restrict__ error_flag)
+{
+    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    uint64_t s = gstart[g], e = (g + 1 < ng) ? gstart[g + 1] : n;
+    if (e <= s || e - s > Ng || e > n) {   // groups hold 1..Ng consecutive particles
+        atomicOr(error_flag, 1u);
+        gcount[g] = 0;
+        return;
+    }
+    gcount[g] = (uint32_t)(e - s);
+    for (int a = 0; a < 3; ++a) {
+        uint32_t lo = 0xffffffffu, hi = 0;
+        for (uint64_t j = s; j < e; ++j) {
+            uint32_t k = (uint32_t)(X[a * n + j] >> 44);
+            lo = min(lo, k);
+            hi = max(hi, k + 1);
+        }
+        glo[a * ng + g] = lo;
+        ghi[a * ng + g] = hi;
+    }
+}
+
+__global__ void read_positions(const uint32_t* __restrict__ v, const uint64_t* __restrict__ pos, uint32_t k,
+                               uint64_t n, uint32_t total_if_end, uint32_t* __restrict__ out)
+{
+    uint32_t t = threadIdx.x;
+    if (t < k) out[t] = pos[t] < n ? v[pos[t]] : total_if_end;
+}
+
+// --------------------------------------------------------------- walk ----
+constexpr uint32_t kPrune = 0, kAccept = 1, kOpen = 2;
+constexpr int kBuf = 128;              // node / leaf buffer entries per wave
+constexpr int kWaveLds = 64 * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
+constexpr int kMaxWaves = 8;           // waves per workgroup
+constexpr size_t kLdsLimit = 65536;    // LDS per workgroup used by the walk
+// Table layouts in LDS. PAIR: per interval (value, slope to the next sample),
+// with a (0, 0) entry that the clamped index reaches for r >= r_cut. VALUE:
+// the samples only (plus one pad), the slope taken from the next sample and
+// r >= r_cut zeroed by a compare; half the LDS for twice the tables.
+enum TableMode { kPair = 0, kValue = 1 };
+
+struct WalkArgs {
+    const uint4* cell;
+    const int32_t* first_child;
+    const uint8_t* n_child;
+    const uint32_t* start;
+    const uint32_t* count;
+    const double4* mono;
+    uint64_t nn;
+    const uint64_t* X;
+    const double* mass;
+    const uint32_t* perm;
+    uint64_t n;
+    const uint32_t* gstart;
+    const uint32_t* gcount;
+    const uint32_t* glo;
+    const uint32_t* ghi;
+    uint64_t ng;
+    uint32_t g0, g1;
+    uint32_t D, a, ntab;
+    const float2* table;       // PAIR layout, D x D x ntab
+    const float* table_v;      // VALUE layout, D x D x (ntab + 1)
+    double G[NGR_MAX_SPECIES];
+    double box, inv_box, eps2, R2, theta2;
+    uint32_t wrap_limit;
+    float tscale, toff, tmax;
+    double* acc;
+    unsigned long long* stats;
+    unsigned long long* gcounts;
+    uint32_t* stacks;
+    uint32_t stack_cap;
+    uint32_t* error_flag;
+    uint32_t max_steps;        // traversal batches per group never exceed the node count
+};
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint32_t wave_incl(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+__device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pair terms of this lane's sink with nrec LDS records of one source species.
+template <int GRID, int TAB, bool EPS0, bool WRAP>
+__device__ inline void eval_records(const WalkArgs& A, const double4* __restrict__ rec, uint32_t nrec,
+                                    const void* __restrict__ tbv, double ox, double oy, double oz, double& ax,
+                                    double& ay, double& az)
+{
+    const double eps2 = A.eps2;
+    const float tscale = A.tscale, toff = A.toff, tmax = A.tmax;
+#pragma unroll 2
+    for (uint32_t r = 0; r < nrec; ++r) {
+        const double4 s = rec[r];
+        double dx = s.x - ox, dy = s.y - oy, dz = s.z - oz;
+        if (WRAP) {
+            dx -= A.box * rint(dx * A.inv_box);
+            dy -= A.box * rint(dy * A.inv_box);
+            dz -= A.box * rint(dz * A.inv_box);
+        }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double re2 = r2 + eps2;
+        const float sf = (float)re2;
+        const float z = __builtin_amdgcn_rsqf(sf);
+        const double zd = (double)z;
+        const double z2 = zd * zd;
+        const double e = fma(-re2, z2, 1.0);          // 1 - re2 z^2 = -2 (relative error of z)
+        const double z3 = z2 * zd;
+        float t;
+        if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);
+        else t = __builtin_sqrtf((float)r2) * tscale;
+        t = __builtin_amdgcn_fmed3f(t, 0.0f, tmax);
+        const int k = (int)t;
+        const float w = t - (float)k;
+        float f;
+        if (TAB == kPair) {
+            const float2 T = static_cast<const float2*>(tbv)[k];
+            f = fmaf(w, T.y, T.x);
+        } else {
+            const float* tv = static_cast<const float*>(tbv);
+            const float t0 = tv[k], t1 = tv[k + 1];
+            f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
+        }
+        const double p = (double)f * s.w * z3;
+        double coef = fma(p, 1.5 * e, p);              // (r^2+eps^2)^(-3/2) to ~1e-13
+        if (EPS0) coef = r2 > 0.0 ? coef : 0.0;
+        ax = fma(coef, dx, ax);
+        ay = fma(coef, dy, ay);
+        az = fma(coef, dz, az);
+    }
+}
+
+// Bytes of LDS the tables of one sink species take in a layout.
+__host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t ntab)
+{
+    const uint32_t raw = mode == kPair ? D * ntab * 8u : D * (ntab + 1u) * 4u;
+    return (raw + 255u) & ~255u;
+}
+
+template <int GRID, int TAB, bool EPS0>
+__global__ __launch_bounds__(kMaxWaves * 64, 2) void walk_kernel(WalkArgs A)
+{
+    HIP_DYNAMIC_SHARED(unsigned char, smem);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const uint32_t D = A.D, ntab = A.ntab;
+    const uint32_t tstride = TAB == kPair ? ntab : ntab + 1;   // entries per table
+    if (TAB == kPair) {
+        float2* tab = reinterpret_cast<float2*>(smem);
+        const float2* src = A.table + (uint64_t)A.a * D * ntab;
+        for (uint32_t k = threadIdx.x; k < D * ntab; k += blockDim.x) tab[k] = src[k];
+    } else {
+        float* tab = reinterpret_cast<float*>(smem);
+        const float* src = A.table_v + (uint64_t)A.a * D * (ntab + 1);
+        for (uint32_t k = threadIdx.x; k < D * (ntab + 1); k += blockDim.x) tab[k] = src[k];
+    }
+    __syncthreads();
+    const uint32_t tab_bytes = table_bytes(TAB, D, ntab);
+    unsigned char* wb = smem + tab_bytes + wave * kWaveLds;
+    double4* rec = reinterpret_cast<double4*>(wb);
+    uint32_t* pnb = reinterpret_cast<uint32_t*>(wb + 64 * 32);
+    uint32_t* ppb = pnb + kBuf;
+    uint32_t* scanb = ppb + kBuf;        // 68 entries
+    uint32_t* pst = scanb + 68;          // 64 entries
+    uint32_t* stack = A.stacks + ((uint64_t)blockIdx.x * nwaves + wave) * A.stack_cap;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const double scale = A.box * 0x1p-64;
+    const uint64_t n = A.n;
+
+    // Groups are dealt round robin to the waves of the grid. The wave's index
+    // is the same in all of its lanes, so every loop exit below depends only
+    // on wave-uniform values and the lanes of a wave stay together.
+    const uint32_t wave_id = uniform(blockIdx.x * (uint32_t)nwaves + (uint32_t)wave);
+    const uint32_t wave_count = gridDim.x * (uint32_t)nwaves;
+    unsigned long long tot_pp = 0, tot_pn = 0;
+    bool any_overflow = false;
+    for (uint32_t g = A.g0 + wave_id; g < A.g1; g += wave_count) {
+        const uint32_t s0 = A.gstart[g], ns = A.gcount[g];
+        uint32_t lo[3], hi[3];
+        bool wrap = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = A.glo[k * A.ng + g];
+            hi[k] = A.ghi[k * A.ng + g];
+            wrap |= (hi[k] - lo[k]) > A.wrap_limit;
+        }
+        // group centre: lattice units and box fraction
+        const uint64_t C0 = (uint64_t)(lo[0] + hi[0]) << 43, C1 = (uint64_t)(lo[1] + hi[1]) << 43,
+                       C2 = (uint64_t)(lo[2] + hi[2]) << 43;
+        const double cf0 = (double)(lo[0] + hi[0]) * 0x1p-21, cf1 = (double)(lo[1] + hi[1]) * 0x1p-21,
+                     cf2 = (double)(lo[2] + hi[2]) * 0x1p-21;
+        double ox = 0.0, oy = 0.0, oz = 0.0;
+        if ((uint32_t)lane < ns) {
+            uint64_t i = s0 + lane;
+            ox = (double)(int64_t)(A.X[i] - C0) * scale;
+            oy = (double)(int64_t)(A.X[n + i] - C1) * scale;
+            oz = (double)(int64_t)(A.X[2 * n + i] - C2) * scale;
+        }
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
+
+        auto eval = [&](uint32_t b, uint32_t nrec) {
+            const unsigned char* tb = smem + (TAB == kPair ? 8u : 4u) * b * tstride;
+            if (wrap) eval_records<GRID, TAB, EPS0, true>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else eval_records<GRID, TAB, EPS0, false>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+        };
+
+        // Accepted nodes: one record per non-empty species monopole.
+        auto flush_nodes = [&](uint32_t k) {
+            for (uint32_t b = 0; b < D; ++b) {
+                double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+                if ((uint32_t)lane < k) r = A.mono[(uint64_t)b * A.nn + pnb[lane]];
+                const bool v = (uint32_t)lane < k && r.w > 0.0;
+                const uint64_t m = __ballot(v);
+                const uint32_t nrec = (uint32_t)__popcll(m);
+                if (v) {
+                    double d0 = r.x - cf0, d1 = r.y - cf1, d2 = r.z - cf2;
+                    d0 -= rint(d0);
+                    d1 -= rint(d1);
+                    d2 -= rint(d2);
+                    rec[__popcll(m & lt)] = make_double4(d0 * A.box, d1 * A.box, d2 * A.box, A.G[b] * r.w);
+                }
+                wave_sync();
+                if (nrec) eval(b, nrec);
+                pn_src += nrec;
+                wave_sync();
+            }
+        };
+
+        // Opened leaves: every particle, one source species at a time.
+        auto flush_leaves = [&](uint32_t k) {
+            for (uint32_t b = 0; b < D; ++b) {
+                uint32_t c = 0, st = 0;
+                if ((uint32_t)lane < k) {
+                    uint32_t leaf = ppb[lane];
+                    c = A.count[(uint64_t)leaf * D + b];
+                    st = A.start[(uint64_t)leaf * D + b];
+                }
+                const uint32_t incl = wave_incl(c, lane);
+                const uint32_t T = uniform(__shfl(incl, 63, 64));
+                if (T == 0) continue;
+                scanb[lane + 1] = incl;
+                scanb[0] = 0;                  // every lane stores the same value
+                pst[lane] = st;
+                wave_sync();
+                for (uint32_t base = 0; base < T; base += 64) {
+                    const uint32_t r = base + lane;
+                    if (r < T) {
+                        // leaf q with scanb[q] <= r < scanb[q+1]
+                        uint32_t lo2 = 0, hi2 = k;
+                        while (hi2 - lo2 > 1) {
+                            uint32_t mid = (lo2 + hi2) >> 1;
+                            if (scanb[mid] <= r) lo2 = mid;
+                            else hi2 = mid;
+                        }
+                        const uint64_t j = pst[lo2] + (r - scanb[lo2]);
+                        rec[lane] = make_double4((double)(int64_t)(A.X[j] - C0) * scale,
+                                                 (double)(int64_t)(A.X[n + j] - C1) * scale,
+                                                 (double)(int64_t)(A.X[2 * n + j] - C2) * scale,
+                                                 A.G[b] * A.mass[j]);
+                    }
+                    wave_sync();
+                    eval(b, min(64u, T - base));
+                    wave_sync();
+                }
+                pp_src += T;
+            }
+        };
+
+        // breadth-first traversal in batches of 64 nodes
+        uint32_t sp = 1, npn = 0, npp = 0;
+        stack[0] = 0;                      // the root; every lane stores the same value
+        wave_sync();
+        bool overflow = false;
+        uint32_t steps = 0;
+        while (sp > 0) {
+            if (++steps > A.max_steps) {   // a node enters a group's stack at most once
+                overflow = true;
+                break;
+            }
+            const uint32_t take = min(sp, 64u);
+            sp -= take;
+            uint32_t node = 0, dec = kPrune, nc = 0;
+            int32_t fc = 0;
+            if ((uint32_t)lane < take) {
+                node = stack[sp + lane];
+                const uint4 cl = A.cell[node];
+                const int32_t S = 1 << (kLevels - (int)cl.w);
+                const uint32_t cc[3] = {cl.x, cl.y, cl.z};
+                double D2 = 0.0, D2m = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int32_t w = (int32_t)(hi[k] - lo[k]);
+                    int32_t d = (2 * (int32_t)cc[k] + S) - (int32_t)(lo[k] + hi[k]);
+                    d = ((d + (1 << 20)) & ((1 << 21) - 1)) - (1 << 20);
+                    const int32_t ad = d < 0 ? -d : d;
+                    int32_t gp = 0;
+                    if (S + w < (1 << 20)) gp = max(ad - (S + w), 0);
+                    const int32_t gm = ad + S + w;
+                    D2 += (double)gp * (double)gp;
+                    D2m += (double)gm * (double)gm;
+                }
+                if (D2 >= A.R2) dec = kPrune;
+                else if ((double)(4ll * S * S) < A.theta2 * D2 && D2m < A.R2) dec = kAccept;
+                else {
+                    dec = kOpen;
+                    nc = A.n_child[node];
+                    fc = A.first_child[node];
+                }
+            }
+            const uint64_t macc = __ballot(dec == kAccept);
+            const uint64_t mleaf = __ballot(dec == kOpen && nc == 0);
+            if (dec == kAccept) pnb[npn + __popcll(macc & lt)] = node;
+            if (dec == kOpen && nc == 0) ppb[npp + __popcll(mleaf & lt)] = node;
+            npn += (uint32_t)__popcll(macc);
+            npp += (uint32_t)__popcll(mleaf);
+            n_acc += (uint32_t)__popcll(macc);
+            n_leaf += (uint32_t)__popcll(mleaf);
+            const uint32_t myc = (dec == kOpen) ? nc : 0u;
+            const uint32_t incl = wave_incl(myc, lane);
+            const uint32_t tot = uniform(__shfl(incl, 63, 64));
+            if (sp + tot > A.stack_cap) {
+                overflow = true;
+                break;
+            }
+            for (uint32_t k = 0; k < myc; ++k) stack[sp + incl - myc + k] = (uint32_t)fc + k;
+            sp += tot;
+            wave_sync();
+            if (npn >= 64) {
+                flush_nodes(64);
+                uint32_t rest = npn - 64, v = 0;
+                if ((uint32_t)lane < rest) v = pnb[64 + lane];
+                wave_sync();
+                if ((uint32_t)lane < rest) pnb[lane] = v;
+                npn = rest;
+                wave_sync();
+            }
+            if (npp >= 64) {
+                flush_leaves(64);
+                uint32_t rest = npp - 64, v = 0;
+                if ((uint32_t)lane < rest) v = ppb[64 + lane];
+                wave_sync();
+                if ((uint32_t)lane < rest) ppb[lane] = v;
+                npp = rest;
+                wave_sync();
+            }
+        }
+        any_overflow |= overflow;
+        if (!overflow) {
+            if (npn) flush_nodes(npn);
+            if (npp) flush_leaves(npp);
+        }
+        if ((uint32_t)lane < ns) {
+            const uint32_t p = A.perm[s0 + lane];
+            A.acc[p] = ax;
+            A.acc[n + p] = ay;
+            A.acc[2 * n + p] = az;
+        }
+        const unsigned long long pn = pn_src * ns, pp = pp_src * ns - ns;
+        tot_pp += pp;
+        tot_pn += pn;
+        if (A.gcounts && (uint32_t)lane < 4u) {
+            const unsigned long long v[4] = {n_acc, n_leaf, pn, pp};
+            A.gcounts[4ull * g + lane] = v[lane];
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], tot_pp);
+        atomicAdd(&A.stats[1], tot_pn);
+        if (any_overflow) atomicOr(A.error_flag, 1u);
+    }
+}
+
+inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
+
+}  // namespace
+
+void Groups::free(Context& ctx)
+{
+    ctx.release(start);
+    ctx.release(count);
+    ctx.release(lo);
+    ctx.release(hi);
+    start = count = lo = hi = nullptr;
+    ng = 0;
+}
+
+void make_groups(Context& ctx, const Tree& t, uint32_t group_size, Groups& g)
+{
+    g.size = group_size;
+    const uint64_t n = t.n;
+    g.ng = 0;
+    for (int a = 0; a <= NGR_MAX_SPECIES; ++a) g.first[a] = 0;
+    if (n == 0) return;
+    ctx.stage("groups: mark");
+    uint32_t* flags = static_cast<uint32_t*>(ctx.alloc(n * sizeof(uint32_t) * 2 + 64));
+    uint32_t* gidx = flags + n;
+    uint32_t* total = gidx + n;
+    HIP_CHECK(hipMemsetAsync(flags, 0, n * sizeof(uint32_t), ctx.stream));
+    hipLaunchKernelGGL(mark_group_starts, dim3(blocks_for(t.nn * t.D, 256)), dim3(256), 0, ctx.stream, t.nn, t.D,
+                       group_size, t.start, t.count, t.first_child, t.n_child, flags);
+    LAUNCH_CHECK("mark_group_starts");
+    scan_exclusive(ctx, flags, gidx, n, total);
+    uint64_t w = 0;
+    ctx.read_words(&w, total, 1);
+    const uint32_t ngh = (uint32_t)(w & 0xffffffffu);
+    if (ngh == 0 || ngh > n) fail(NGR_EDEVICE, "group formation produced an impossible group count");
+    // first group of each species: the group index at the species segment start
+    uint64_t* segd = static_cast<uint64_t*>(ctx.alloc(16 * sizeof(uint64_t)));
+    uint32_t* outd = reinterpret_cast<uint32_t*>(segd + 8);
+    uint32_t* errd = outd + 8;
+    ctx.write_words(segd, t.seg, NGR_MAX_SPECIES + 1);
+    HIP_CHECK(hipMemsetAsync(errd, 0, sizeof(uint32_t), ctx.stream));
+    hipLaunchKernelGGL(read_positions, dim3(1), dim3(64), 0, ctx.stream, gidx, segd, t.D + 1, n, ngh, outd);
+    LAUNCH_CHECK("read_positions");
+    g.ng = ngh;
+    g.start = static_cast<uint32_t*>(ctx.alloc((uint64_t)ngh * sizeof(uint32_t)));
+    g.count = static_cast<uint32_t*>(ctx.alloc((uint64_t)ngh * sizeof(uint32_t)));
+    g.lo = static_cast<uint32_t*>(ctx.alloc(3ull * ngh * sizeof(uint32_t)));
+    g.hi = static_cast<uint32_t*>(ctx.alloc(3ull * ngh * sizeof(uint32_t)));
+    ctx.stage("groups: boxes");
+    hipLaunchKernelGGL(scatter_group_starts, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, flags, gidx,
+                       g.start);
+    LAUNCH_CHECK("scatter_group_starts");
+    hipLaunchKernelGGL(finish_groups, dim3(blocks_for(ngh, 256)), dim3(256), 0, ctx.stream, (uint64_t)ngh, n,
+                       group_size, g.start, g.count, g.lo, g.hi, t.X, errd);
+    LAUNCH_CHECK("finish_groups");
+    uint64_t words[8];
+    ctx.read_words(words, outd, 8);
+    const uint32_t* firsts = reinterpret_cast<const uint32_t*>(words);
+    if (firsts[8]) fail(NGR_EDEVICE, "group formation produced an inconsistent group");
+    for (uint32_t a = 0; a <= t.D; ++a) g.first[a] = firsts[a];
+    for (uint32_t a = t.D + 1; a <= NGR_MAX_SPECIES; ++a) g.first[a] = ngh;
+    ctx.release(flags);
+    ctx.release(segd);
+}
+
+// Tables of every pair (a, b), in both LDS layouts (see TableMode): PAIR as
+// (value, slope to the next sample) for the ntab - 1 intervals plus a (0, 0)
+// entry; VALUE as the ntab samples plus a zero pad.
+void upload_law(Context& ctx, const ngr_force_params& fp, uint32_t D, Law& law)
+{
+    law.D = D;
+    law.ntab = fp.ntab;
+    law.grid = fp.grid;
+    law.r_cut = fp.r_cut;
+    law.eps = fp.eps;
+    law.theta = fp.theta;
+    for (uint32_t k = 0; k < D * D; ++k) law.G[k] = fp.G[k];
+    const uint32_t ntab = fp.ntab;
+    std::vector<double> def;
+    const double* T = fp.tables;
+    if (!T) {
+        def.resize((size_t)ntab);
+        for (uint32_t k = 0; k < ntab; ++k) {
+            double r = fp.grid == NGR_GRID_R ? k * (fp.r_cut / (ntab - 1))
+                                             : std::sqrt(k * (fp.r_cut * fp.r_cut / (ntab - 1)));
+            double x = r / (2.0 * fp.r_s);
+            def[k] = std::erfc(x) + r / (fp.r_s * std::sqrt(M_PI)) * std::exp(-x * x);
+        }
+    }
+    const size_t np = (size_t)D * D * ntab, nv = (size_t)D * D * (ntab + 1);
+    std::vector<float2> hp(np);
+    std::vector<float> hv(nv);
+    for (uint32_t ab = 0; ab < D * D; ++ab) {
+        const double* src = T ? T + (size_t)ab * ntab : def.data();
+        float2* dp = hp.data() + (size_t)ab * ntab;
+        float* dv = hv.data() + (size_t)ab * (ntab + 1);
+        for (uint32_t k = 0; k + 1 < ntab; ++k) dp[k] = make_float2((float)src[k], (float)(src[k + 1] - src[k]));
+        dp[ntab - 1] = make_float2(0.0f, 0.0f);
+        for (uint32_t k = 0; k < ntab; ++k) dv[k] = (float)src[k];
+        dv[ntab] = 0.0f;
+    }
+    law.table = static_cast<float2*>(ctx.alloc(np * sizeof(float2) + nv * sizeof(float)));
+    law.table_v = reinterpret_cast<float*>(law.table + np);
+    ctx.to_device(law.table, hp.data(), np * sizeof(float2));
+    ctx.to_device(law.table_v, hv.data(), nv * sizeof(float));
+}
+
+void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, double* acc,
+                uint64_t* group_counts_dev, WalkOut& out)
+{
+    out = WalkOut{};
+    if (t.n == 0 || g.ng == 0) return;
+    const uint32_t D = t.D;
+    // layout and workgroup shape: at most 64 KiB of LDS per workgroup
+    int mode = kPair;
+    size_t tab_bytes = table_bytes(kPair, D, law.ntab);
+    if (tab_bytes + 4 * (size_t)kWaveLds > kLdsLimit) {
+        mode = kValue;
+        tab_bytes = table_bytes(kValue, D, law.ntab);
+    }
+    if (tab_bytes + kWaveLds > kLdsLimit) fail(NGR_EINVAL, "force tables do not fit in LDS");
+    const int waves = (int)std::min<size_t>(kMaxWaves, (kLdsLimit - tab_bytes) / kWaveLds);
+    const size_t lds = tab_bytes + (size_t)waves * kWaveLds;
+    const size_t per_cu = ctx.lds_per_block >= 2 * lds ? ctx.lds_per_block / lds : 1;
+    const int blocks = ctx.num_cu * (int)std::min<size_t>(per_cu, 4);
+    const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
+    ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
+    ctx.ensure(ctx.counters, 4096);
+    unsigned long long* stats = static_cast<unsigned long long*>(ctx.counters.p);
+    uint32_t* err = reinterpret_cast<uint32_t*>(stats + 4);
+    HIP_CHECK(hipMemsetAsync(ctx.counters.p, 0, 4096, ctx.stream));
+
+    WalkArgs A{};
+    A.cell = t.cell;
+    A.first_child = t.first_child;
+    A.n_child = t.n_child;
+    A.start = t.start;
+    A.count = t.count;
+    A.mono = t.mono;
+    A.nn = t.nn;
+    A.X = t.X;
+    A.mass = t.mass;
+    A.perm = t.perm;
+    A.n = t.n;
+    A.gstart = g.start;
+    A.gcount = g.count;
+    A.glo = g.lo;
+    A.ghi = g.hi;
+    A.ng = g.ng;
+    A.D = D;
+    A.ntab = law.ntab;
+    A.table = law.table;
+    A.table_v = law.table_v;
+    A.box = t.box;
+    A.inv_box = 1.0 / t.box;
+    A.eps2 = law.eps * law.eps;
+    {
+        double q = law.r_cut / t.box * 2097152.0;
+        A.R2 = q * q;
+    }
+    A.theta2 = law.theta * law.theta;
+    {
+        double wl = std::floor(1048576.0 * (1.0 - 2.0 * law.r_cut / t.box)) - 1.0;
+        A.wrap_limit = wl < 0.0 ? 0u : (uint32_t)wl;
+    }
+    const double rc2 = law.r_cut * law.r_cut;
+    if (law.grid == NGR_GRID_R2) {
+        A.tscale = (float)((law.ntab - 1) / rc2);
+        A.toff = (float)(-A.eps2 * ((law.ntab - 1) / rc2));
+    } else {
+        A.tscale = (float)((law.ntab - 1) / law.r_cut);
+        A.toff = 0.0f;
+    }
+    A.tmax = (float)(law.ntab - 1);
+    A.acc = acc;
+    A.stats = stats;
+    A.gcounts = reinterpret_cast<unsigned long long*>(group_counts_dev);
+    A.stacks = static_cast<uint32_t*>(ctx.stacks.p);
+    A.stack_cap = stack_cap;
+    A.error_flag = err;
+    A.max_steps = (uint32_t)std::min<uint64_t>(t.nn + 1, 0xffffffffull);
+
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventRecord(e0, ctx.stream));
+    const bool eps0 = law.eps == 0.0;
+    for (uint32_t a = 0; a < D; ++a) {
+        if (g.first[a + 1] <= g.first[a]) continue;
+        A.a = a;
+        A.g0 = (uint32_t)g.first[a];
+        A.g1 = (uint32_t)g.first[a + 1];
+        for (uint32_t b = 0; b < D; ++b) A.G[b] = law.G[a * D + b];
+        ctx.stage("walk: launch");
+        auto launch = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(blocks), dim3(waves * 64), lds, ctx.stream, A);
+            LAUNCH_CHECK("walk_kernel");
+        };
+        const int sel = (law.grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
+        switch (sel) {
+        case 0: launch(walk_kernel<NGR_GRID_R, kPair, false>); break;
+        case 1: launch(walk_kernel<NGR_GRID_R, kPair, true>); break;
+        case 2: launch(walk_kernel<NGR_GRID_R, kValue, false>); break;
+        case 3: launch(walk_kernel<NGR_GRID_R, kValue, true>); break;
+        case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false>); break;
+        case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true>); break;
+        case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false>); break;
+        default: launch(walk_kernel<NGR_GRID_R2, kValue, true>); break;
+        }
+    }
+    HIP_CHECK(hipEventRecord(e1, ctx.stream));
+    uint64_t words[40];
+    ctx.read_words(words, ctx.counters.p, 40);
+    ctx.stage("walk: done");
+    float ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    HIP_CHECK(hipEventDestroy(e0));
+    HIP_CHECK(hipEventDestroy(e1));
+    const uint32_t herr = reinterpret_cast<const uint32_t*>(words)[2 * 4];
+    if (herr) fail(NGR_ENOMEM, "walk stack or step capacity exceeded");
+    out.pp = words[0];
+    out.pn = words[1];
+    out.ms_walk = ms;
+}
+
+}  // namespace ngr

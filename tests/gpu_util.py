@@ -1,0 +1,48 @@
+"""Helpers shared by the GPU tests: move a synthetic problem to the device,
+run the C-ABI pipeline, and compare with the oracle."""
+import numpy as np
+
+import oracle
+import paper_1502_07442_amd as ngr
+
+
+def device_inputs(p):
+    import torch
+    dev = torch.device("cuda", 0)
+    species = torch.from_numpy(np.ascontiguousarray(p.species, np.uint8)).to(dev)
+    mass = torch.from_numpy(np.ascontiguousarray(p.mass, np.float64)).to(dev)
+    pos = lat = None
+    if p.lattice is not None:
+        lat = torch.from_numpy(np.ascontiguousarray(p.lattice).view(np.int64)).to(dev)
+    else:
+        pos = torch.from_numpy(np.ascontiguousarray(p.pos, np.float64)).to(dev)
+    return dict(species=species, mass=mass, pos=pos, lattice=lat)
+
+
+def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None):
+    """Build, monopoles and force on the GPU. Returns (acc (3, n) numpy,
+    stats, per-group counts or None, tree or None)."""
+    import torch
+    t = device_inputs(p)
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    gs = p.group_size if group_size is None else group_size
+    res = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
+                         theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts)
+    st, gc = (res if group_counts else (res, None))
+    out = acc.cpu().numpy()
+    if not keep_tree:
+        ngr.tree_free(ctx, tree)
+        tree = None
+    return out, st, gc, tree
+
+
+def force_gate(acc_gpu, acc_orc, slack, rel=1e-5):
+    """Per-particle gate |a_gpu - a_orc| <= rel * rms|a_orc| + slack. Returns
+    (ok, worst ratio, rms|a|, max |da| / rms)."""
+    rms = float(np.sqrt(np.mean(np.sum(acc_orc ** 2, axis=0))))
+    da = np.linalg.norm(acc_gpu - acc_orc, axis=0)
+    allowed = rel * rms + slack
+    worst = float(np.max(da / allowed)) if da.size else 0.0
+    return worst <= 1.0, worst, rms, float(np.max(da) / rms) if da.size else 0.0
