@@ -58,9 +58,10 @@ typedef int32_t ngr_status;
 typedef struct ngr_context ngr_context;
 typedef struct ngr_tree ngr_tree;
 
-/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to
- * run on, or NULL to create a private stream. The context owns a caching pool
- * of device memory. */
+/* Create a context on HIP device `device`. `hip_stream` is the hipStream_t
+ * the context's work runs on; NULL means the default (null) stream, which is
+ * ordered with all other blocking streams of the device. The context owns a
+ * caching pool of device memory and a small pinned host staging area. */
 ngr_status ngr_context_create(int device, void* hip_stream, ngr_context** out);
 void ngr_context_destroy(ngr_context* ctx);
 /* Text of the last error on this context ("" when none). Valid until the

@@ -167,7 +167,7 @@ def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=N
     if tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
         ntab = tables.shape[-1]
-    fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS[grid],
+    fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS.get(grid, grid),
                      float(r_s), float(r_cut), float(eps), float(theta), int(group_size))
     fp._keep = (G, tables)
     return fp

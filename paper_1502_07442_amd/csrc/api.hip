@@ -263,13 +263,8 @@ NGR_API ngr_status ngr_context_create(int device, void* hip_stream, ngr_context*
         hipDeviceProp_t prop;
         ngr::hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties", __FILE__, __LINE__);
         c->num_cu = prop.multiProcessorCount;
-        if (hip_stream) {
-            c->stream = static_cast<hipStream_t>(hip_stream);
-        } else {
-            ngr::hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate", __FILE__,
-                           __LINE__);
-            c->own_stream = true;
-        }
+        c->stream = static_cast<hipStream_t>(hip_stream);   // NULL: the default stream
+        c->own_stream = false;
         ngr::hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), ngr::Context::kPinnedWords * sizeof(uint64_t),
                                      hipHostMallocDefault),
                        "hipHostMalloc", __FILE__, __LINE__);

@@ -116,8 +116,7 @@ __global__ void read_positions(const uint32_t* __restrict__ v, const uint64_t* _
 constexpr uint32_t kPrune = 0, kAccept = 1, kOpen = 2;
 constexpr int kBuf = 128;              // node / leaf buffer entries per wave
 constexpr int kWaveLds = 64 * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
-constexpr int kMaxWaves = 8;           // waves per workgroup
-constexpr size_t kLdsLimit = 65536;    // LDS per workgroup used by the walk
+constexpr int kMaxWaves = 16;          // waves per workgroup
 // Table layouts in LDS. PAIR: per interval (value, slope to the next sample),
 // with a (0, 0) entry that the clamped index reaches for r >= r_cut. VALUE:
 // the samples only (plus one pad), the slope taken from the next sample and
@@ -142,6 +141,7 @@ struct WalkArgs {
     const uint32_t* ghi;
     uint64_t ng;
     uint32_t g0, g1;
+    uint32_t* queue;           // next group of this launch (counts from 0)
     uint32_t D, a, ntab;
     const float2* table;       // PAIR layout, D x D x ntab
     const float* table_v;      // VALUE layout, D x D x (ntab + 1)
@@ -233,7 +233,7 @@ __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t n
 }
 
 template <int GRID, int TAB, bool EPS0>
-__global__ __launch_bounds__(kMaxWaves * 64, 2) void walk_kernel(WalkArgs A)
+__global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
     HIP_DYNAMIC_SHARED(unsigned char, smem);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -261,14 +261,18 @@ __global__ __launch_bounds__(kMaxWaves * 64, 2) void walk_kernel(WalkArgs A)
     const double scale = A.box * 0x1p-64;
     const uint64_t n = A.n;
 
-    // Groups are dealt round robin to the waves of the grid. The wave's index
-    // is the same in all of its lanes, so every loop exit below depends only
-    // on wave-uniform values and the lanes of a wave stay together.
-    const uint32_t wave_id = uniform(blockIdx.x * (uint32_t)nwaves + (uint32_t)wave);
-    const uint32_t wave_count = gridDim.x * (uint32_t)nwaves;
+    // Waves take groups from a queue. Every lane executes the atomic (lane 0
+    // adds one, the others add zero), so no lane-dependent branch surrounds
+    // it; lane 0 is the first active lane and its return value is the wave's
+    // ticket. The loop exit then depends only on that wave-uniform value and
+    // the lanes of a wave stay together (cross-lane operations inside the
+    // loop need all of them).
     unsigned long long tot_pp = 0, tot_pn = 0;
     bool any_overflow = false;
-    for (uint32_t g = A.g0 + wave_id; g < A.g1; g += wave_count) {
+    for (;;) {
+        const uint32_t ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
+        const uint32_t g = A.g0 + uniform(ticket);
+        if (g >= A.g1) break;
         const uint32_t s0 = A.gstart[g], ns = A.gcount[g];
         uint32_t lo[3], hi[3];
         bool wrap = false;
@@ -577,23 +581,26 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     out = WalkOut{};
     if (t.n == 0 || g.ng == 0) return;
     const uint32_t D = t.D;
-    // layout and workgroup shape: at most 64 KiB of LDS per workgroup
+    // layout and workgroup shape within the LDS of one workgroup: the
+    // (value, slope) tables when at least 8 waves still fit beside them
+    const size_t lds_max = ctx.lds_per_block;
     int mode = kPair;
     size_t tab_bytes = table_bytes(kPair, D, law.ntab);
-    if (tab_bytes + 4 * (size_t)kWaveLds > kLdsLimit) {
+    if (tab_bytes + 8 * (size_t)kWaveLds > lds_max) {
         mode = kValue;
         tab_bytes = table_bytes(kValue, D, law.ntab);
     }
-    if (tab_bytes + kWaveLds > kLdsLimit) fail(NGR_EINVAL, "force tables do not fit in LDS");
-    const int waves = (int)std::min<size_t>(kMaxWaves, (kLdsLimit - tab_bytes) / kWaveLds);
+    if (tab_bytes + kWaveLds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
+    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - tab_bytes) / kWaveLds);
     const size_t lds = tab_bytes + (size_t)waves * kWaveLds;
-    const size_t per_cu = ctx.lds_per_block >= 2 * lds ? ctx.lds_per_block / lds : 1;
+    const size_t per_cu = std::max<size_t>(1, lds_max / lds);
     const int blocks = ctx.num_cu * (int)std::min<size_t>(per_cu, 4);
     const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
     ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
     ctx.ensure(ctx.counters, 4096);
     unsigned long long* stats = static_cast<unsigned long long*>(ctx.counters.p);
     uint32_t* err = reinterpret_cast<uint32_t*>(stats + 4);
+    uint32_t* queues = err + 8;
     HIP_CHECK(hipMemsetAsync(ctx.counters.p, 0, 4096, ctx.stream));
 
     WalkArgs A{};
@@ -656,6 +663,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
         A.a = a;
         A.g0 = (uint32_t)g.first[a];
         A.g1 = (uint32_t)g.first[a + 1];
+        A.queue = queues + a;
         for (uint32_t b = 0; b < D; ++b) A.G[b] = law.G[a * D + b];
         ctx.stage("walk: launch");
         auto launch = [&](auto kernel) {

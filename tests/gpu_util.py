@@ -40,9 +40,11 @@ def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None):
 
 def force_gate(acc_gpu, acc_orc, slack, rel=1e-5):
     """Per-particle gate |a_gpu - a_orc| <= rel * rms|a_orc| + slack. Returns
-    (ok, worst ratio, rms|a|, max |da| / rms)."""
-    rms = float(np.sqrt(np.mean(np.sum(acc_orc ** 2, axis=0))))
+    (ok, worst ratio of error to allowance, rms|a|, max |da| / rms)."""
+    rms = float(np.sqrt(np.mean(np.sum(acc_orc ** 2, axis=0)))) if acc_orc.size else 0.0
     da = np.linalg.norm(acc_gpu - acc_orc, axis=0)
     allowed = rel * rms + slack
-    worst = float(np.max(da / allowed)) if da.size else 0.0
-    return worst <= 1.0, worst, rms, float(np.max(da) / rms) if da.size else 0.0
+    ok = bool(np.all(da <= allowed))
+    ratio = np.divide(da, allowed, out=np.where(da > 0, np.inf, 0.0), where=allowed > 0)
+    worst = float(np.max(ratio)) if da.size else 0.0
+    return ok, worst, rms, (float(np.max(da)) / rms if rms > 0 and da.size else 0.0)

@@ -1,0 +1,290 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Exact for everything integer: lattice coordinates, keys, the sort
+permutation, the tree (levels, prefixes, links, per-species ranges), the
+groups and every per-group interaction count. Forces per particle within
+|a_gpu - a_orc| <= 1e-5 rms|a| + slack, where slack is the oracle's sum of
+|term| over pairs within 1e-6 r_cut^2 of the cut-off (a pair there may fall
+either side in finite precision). Masses and centres of mass within the
+float64 bound of sums taken in different orders.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1502_07442_amd as ngr
+import synth
+from gpu_util import device_inputs, force_gate, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ngr.Context(0)
+    yield c
+    c.close()
+
+
+def full_parity(ctx, p, group_size=None, check_tree=True):
+    """Run p on the GPU and compare every stage with the oracle."""
+    print(f"case {p.name} n={p.n} D={p.D} grid={p.grid} B={p.leaf_size} Ng={group_size or p.group_size}",
+          flush=True)
+    gs = group_size or p.group_size
+    acc, st, gc, tree = gpu_solve(ctx, p, group_counts=True, keep_tree=True, group_size=gs)
+    try:
+        T = oracle.Tree.of(p, group_size=gs)
+        if check_tree:
+            ex = ngr.tree_export(ctx, tree)
+            nd = T.nodes()
+            assert np.array_equal(ex["perm"], nd["perm"])
+            assert np.array_equal(ex["keys"], nd["keys"])
+            assert np.array_equal(ex["lattice"], oracle.lattice_of(p)[:, nd["perm"]])
+            assert tree.n_nodes == T.n_nodes
+            for k in ("level", "prefix", "parent", "first_child", "n_child", "start", "count"):
+                assert np.array_equal(ex[k], nd[k]), k
+            M, com = ngr.monopoles_export(ctx, tree)
+            Mo, como = T.monopole_arrays()
+            # float64 sums of N terms in different orders (bottom-up on the GPU,
+            # particle by particle in the oracle) differ by at most ~N 2^-52
+            cnt = nd["count"].astype(np.float64)
+            assert np.all(np.abs(M - Mo) <= (cnt + 1.0) * 2.0 ** -52 * Mo)
+            tol = ((cnt + 1.0) * 2.0 ** -52 + 1e-15)[:, None, :] * p.box
+            has = np.broadcast_to((Mo > 0)[:, None, :], com.shape)
+            assert np.all(np.abs(com - como)[has] <= np.broadcast_to(tol, com.shape)[has])
+            g = ngr.groups_export(ctx, tree, gs)
+            go = T.group_arrays()
+            for k in go:
+                assert np.array_equal(g[k], go[k]), k
+        ao, so, co, gco = T.force(oracle.law_of(p), group_counts=True)
+        assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"])
+        assert np.array_equal(gc, gco)
+        ok, worst, rms, mx = force_gate(acc, ao, so)
+        print(f"  interactions={co['pp'] + co['pn']} worst/allowed={worst:.3g} max|da|/rms={mx:.3g}", flush=True)
+        assert ok, f"force gate: worst ratio {worst}"
+        return acc, st
+    finally:
+        ngr.tree_free(ctx, tree)
+
+
+@pytest.mark.parametrize("seed", range(1, 11))
+def test_uniform_4096_two_species(ctx, seed):
+    full_parity(ctx, synth.c1(seed))
+
+
+def test_clustered_three_species_yukawa(ctx):
+    full_parity(ctx, synth.c2(2, n=2 ** 15))
+
+
+def test_clustered_six_species_r2_grid(ctx):
+    # D * ntab = 12288: the tables take the value-only LDS layout
+    full_parity(ctx, synth.clustered_problem(2 ** 15, 6, 3))
+
+
+def test_clustered_six_species_pair_tables(ctx):
+    full_parity(ctx, synth.clustered_problem(2 ** 15, 6, 4, ntab=512, grid="r"))
+
+
+def test_single_species(ctx):
+    full_parity(ctx, synth.clustered_problem(20000, 1, 5, ntab=2048))
+
+
+@pytest.mark.parametrize("B", [1, 3, 64])
+def test_leaf_sizes(ctx, B):
+    p = synth.clustered_problem(6000, 2, 6, ntab=256, grid="r")
+    p.leaf_size = B
+    full_parity(ctx, p)
+
+
+@pytest.mark.parametrize("Ng", [16, 32])
+def test_group_sizes(ctx, Ng):
+    full_parity(ctx, synth.clustered_problem(9000, 3, 7, ntab=512), group_size=Ng)
+
+
+def test_zero_softening(ctx):
+    p = synth.uniform_problem(3001, 2, 8, ntab=512)
+    p.eps = 0.0
+    full_parity(ctx, p)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 65, 129])
+def test_tiny_and_ragged(ctx, n):
+    # few particles: groups span most of the box and need the per-pair wrap
+    p = synth.uniform_problem(n, 2 if n > 1 else 1, 9 + n, ntab=64)
+    p.r_s, p.r_cut, p.eps = 0.06, 0.3, 0.01
+    t = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, p.r_s), 64, p.r_cut, "r")
+    p.tables = np.broadcast_to(t, (p.D, p.D, 64)).copy()
+    full_parity(ctx, p)
+
+
+def test_wide_groups_large_cutoff(ctx):
+    p = synth.uniform_problem(300, 1, 21, ntab=128)
+    p.r_cut = 0.45
+    p.tables = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, 0.1), 128, p.r_cut, "r")[None, None].copy()
+    full_parity(ctx, p)
+
+
+def test_edges_and_coincident_particles(ctx):
+    rng = np.random.default_rng(31)
+    n = 2000
+    pos = synth.uniform_positions(n, 1.0, rng)
+    pos[:, :50] = np.nextafter(1.0, 0.0)          # just below the upper face
+    pos[:, 50:100] = 0.0                           # on the lower face
+    pos[:, 100:140] = pos[:, 140:180]              # coincident pairs
+    p = synth.uniform_problem(n, 2, 31, ntab=256)
+    p.pos = pos
+    full_parity(ctx, p)
+
+
+def test_masses_unequal_and_zero(ctx):
+    p = synth.clustered_problem(8000, 3, 12, ntab=256)
+    rng = np.random.default_rng(12)
+    p.mass = rng.random(p.n) * 2.0 / p.n
+    p.mass[::17] = 0.0
+    full_parity(ctx, p)
+
+
+def test_asymmetric_G_and_laws(ctx):
+    p = synth.clustered_problem(8000, 3, 13, ntab=512)
+    rng = np.random.default_rng(13)
+    p.G = rng.uniform(-1, 2, (3, 3))
+    p.tables = p.tables * rng.uniform(0.5, 1.5, (3, 3, 1))
+    full_parity(ctx, p)
+
+
+def test_box_not_unit(ctx):
+    p = synth.clustered_problem(8000, 2, 14, ntab=512, box=37.5)
+    full_parity(ctx, p)
+
+
+def test_default_tables_from_split_scale(ctx):
+    """tables == NULL: the library tabulates the Newtonian short-range factor
+    from r_s; compared with the oracle using the same law tabulated here."""
+    import torch
+    p = synth.clustered_problem(6000, 2, 15, ntab=1024, grid="r")
+    t = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, p.r_s), 1024, p.r_cut, "r")
+    p.tables = np.broadcast_to(t, (2, 2, 1024)).copy()
+    p.G = np.ones((2, 2))
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **device_inputs(p))
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    ngr.tree_force(ctx, tree, G=p.G, tables=None, ntab=1024, grid="r", r_s=p.r_s, r_cut=p.r_cut, eps=p.eps,
+                   theta=p.theta, acc=acc)
+    ngr.tree_free(ctx, tree)
+    ao, so, _, _ = oracle.Tree.of(p).force(oracle.law_of(p))
+    ok, worst, _, _ = force_gate(acc.cpu().numpy(), ao, so)
+    assert ok, worst
+
+
+def test_repeat_is_bitwise_identical(ctx):
+    p = synth.clustered_problem(20000, 3, 16, ntab=512)
+    a1, _, _, _ = gpu_solve(ctx, p)
+    a2, _, _, _ = gpu_solve(ctx, p)
+    assert np.array_equal(a1, a2)
+
+
+def test_empty_input(ctx):
+    import torch
+    z = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    tree = ngr.tree_build(ctx, D=2, box=1.0, species=z, mass=torch.zeros(0, dtype=torch.float64, device="cuda"),
+                          pos=torch.zeros((3, 0), dtype=torch.float64, device="cuda"))
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    st = ngr.tree_force(ctx, tree, G=np.ones((2, 2)), tables=np.ones((2, 2, 8)), grid="r", r_cut=0.1, eps=0.01,
+                        theta=0.5, acc=acc)
+    assert st["interactions_pp"] == 0 and st["interactions_pn"] == 0 and st["n_groups"] == 0
+    ngr.tree_free(ctx, tree)
+
+
+def _status(fn):
+    try:
+        fn()
+    except ngr.NgravsError as e:
+        return e.status
+    return ngr.OK
+
+
+def test_errors_are_reported(ctx):
+    import torch
+    p = synth.uniform_problem(500, 2, 17, ntab=64)
+    t = device_inputs(p)
+    bad_species = t["species"].clone()
+    bad_species[3] = 2
+    assert _status(lambda: ngr.tree_build(ctx, D=2, box=1.0, species=bad_species, mass=t["mass"], pos=t["pos"])) == ngr.EINVAL
+    bad_mass = t["mass"].clone()
+    bad_mass[7] = -1.0
+    assert _status(lambda: ngr.tree_build(ctx, D=2, box=1.0, species=t["species"], mass=bad_mass, pos=t["pos"])) == ngr.EINVAL
+    bad_pos = t["pos"].clone()
+    bad_pos[1, 9] = float("nan")
+    assert _status(lambda: ngr.tree_build(ctx, D=2, box=1.0, species=t["species"], mass=t["mass"], pos=bad_pos)) == ngr.EINVAL
+    assert _status(lambda: ngr.tree_build(ctx, D=7, box=1.0, species=t["species"], mass=t["mass"], pos=t["pos"])) == ngr.EINVAL
+    assert _status(lambda: ngr.tree_build(ctx, D=2, box=0.0, species=t["species"], mass=t["mass"], pos=t["pos"])) == ngr.EINVAL
+    assert _status(lambda: ngr.tree_build(ctx, D=2, box=1.0, species=t["species"], mass=t["mass"], pos=t["pos"],
+                                          leaf_size=65)) == ngr.EINVAL
+    tree = ngr.tree_build(ctx, D=2, box=1.0, species=t["species"], mass=t["mass"], pos=t["pos"])
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    kw = dict(G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta, acc=acc)
+    assert _status(lambda: ngr.tree_force(ctx, tree, **kw)) == ngr.ESTATE
+    ngr.compute_monopoles(ctx, tree)
+    for change in (dict(r_cut=0.5), dict(r_cut=-1.0), dict(eps=-0.1), dict(theta=0.0), dict(group_size=48),
+                   dict(grid=7), dict(G=np.full((2, 2), np.nan)), dict(tables=np.full((2, 2, 64), np.inf)),
+                   dict(tables=np.ones((2, 2, 1))), dict(tables=np.ones((2, 2, 7000)))):
+        assert _status(lambda: ngr.tree_force(ctx, tree, **{**kw, **change})) == ngr.EINVAL, change
+    assert _status(lambda: ngr.tree_force(ctx, tree, **kw)) == ngr.OK
+    ngr.tree_free(ctx, tree)
+
+
+def test_sampled_parity_at_2_21(ctx):
+    """The three-species clustered box at full size: exact counts and the
+    force gate on a seeded sample of groups (the oracle computes only those)."""
+    sampled_parity(ctx, synth.c2(2), n_groups=400)
+
+
+@pytest.mark.slow
+def test_sampled_parity_at_2_24_six_species(ctx):
+    """The 2^24, six-species workload of the benchmark, in its launch
+    configuration, on a seeded sample of groups."""
+    sampled_parity(ctx, synth.c3(3), n_groups=300)
+
+
+def sampled_parity(ctx, p, n_groups):
+    print(f"case {p.name} n={p.n} D={p.D}", flush=True)
+    acc, st, gc, tree = gpu_solve(ctx, p, group_counts=True, keep_tree=True)
+    try:
+        ex = ngr.tree_export(ctx, tree)
+        print("  gpu done", flush=True)
+        T = oracle.Tree.of(p)
+        print("  oracle tree done", flush=True)
+        nd = T.nodes()
+        assert np.array_equal(ex["perm"], nd["perm"]) and np.array_equal(ex["keys"], nd["keys"])
+        assert tree.n_nodes == T.n_nodes
+        for k in ("level", "prefix", "first_child", "n_child", "start", "count"):
+            assert np.array_equal(ex[k], nd[k]), k
+        go = T.group_arrays()
+        g = ngr.groups_export(ctx, tree, p.group_size)
+        for k in go:
+            assert np.array_equal(g[k], go[k]), k
+        rng = np.random.default_rng(1234)
+        sel = np.sort(rng.choice(T.n_groups, min(n_groups, T.n_groups), replace=False)).astype(np.uint32)
+        # always include the largest-count groups (the densest regions)
+        dense = np.argsort(-(gc[:, 2] + gc[:, 3]))[:20].astype(np.uint32)
+        sel = np.unique(np.concatenate([sel, dense]))
+        ao, so, co, gco = T.force(oracle.law_of(p), groups=sel, group_counts=True)
+        assert np.array_equal(gc[sel], gco)
+        assert st["interactions_pp"] == int(gc[:, 3].sum()) and st["interactions_pn"] == int(gc[:, 2].sum())
+        sinks = np.concatenate([np.arange(go["start"][k], go["start"][k] + go["count"][k]) for k in sel])
+        idx = nd["perm"][sinks]
+        # the rms over every particle needs every force: take it from the GPU
+        # result (it enters only the tolerance scale)
+        rms = float(np.sqrt(np.mean(np.sum(acc ** 2, axis=0))))
+        da = np.linalg.norm(acc[:, idx] - ao[:, idx], axis=0)
+        worst = float(np.max(da / (1e-5 * rms + so[idx])))
+        print(f"  sampled sinks={len(idx)} worst/allowed={worst:.3g}", flush=True)
+        assert worst <= 1.0
+    finally:
+        ngr.tree_free(ctx, tree)
