@@ -17,7 +17,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_PER_INTERACTION = 26          # algorithmic count per pair term (see the design notes)
+# Algorithmic flops of one pair term (FMA = 2, transcendental = 1): offsets 3, r^2 5, +eps^2 1,
+# rsqrt 1, cube 2, table index 1, floor/fraction 2, lerp 2, mu*f*rho^3 2, three accumulations 6.
+FLOPS_PER_INTERACTION = 26
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
 
 
@@ -63,8 +65,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the many-GPU design is "
-              f"described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
+              f"measured for one MI355X", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -74,7 +76,7 @@ def main():
     import synth
 
     log(f"generating the clustered workload n={args.n}")
-    p = synth.c3(3, n=args.n)
+    p = synth.clustered_d6(3, n=args.n)
     dev = torch.device("cuda", 0)
     pos = torch.from_numpy(p.pos).to(dev)
     species = torch.from_numpy(p.species).to(dev)

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libngravs.so")
 SOURCES = ["api.hip", "build.hip", "scan.hip", "sort.hip", "walk.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
-    # packed FP32 instructions off on this target (see the design notes)
+    # no packed FP32 instructions: some of their forms have given wrong results on these machines
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

@@ -28,7 +28,7 @@ __all__ = [
     "Problem", "GRID_R", "GRID_R2", "largest_remainder", "exact_species",
     "uniform_positions", "uniform_lattice", "clustered_positions",
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
-    "sample_table", "scaled_params", "random_laws", "c1", "c2", "c3",
+    "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
     "clustered_problem", "uniform_problem", "batch_box",
 ]
 
@@ -204,7 +204,7 @@ def random_laws(D: int, ntab: int, r_s: float, r_cut: float, grid: str,
 
 
 # ----------------------------------------------------------------- configs --
-def c1(seed: int = 1) -> Problem:
+def uniform_4096(seed: int = 1) -> Problem:
     """4096 uniform particles, two equal species, Newtonian short-range laws."""
     n, D, box = 4096, 2, 1.0
     rng = np.random.default_rng(seed)
@@ -221,7 +221,7 @@ def c1(seed: int = 1) -> Problem:
                    lattice=lat, seed=seed)
 
 
-def c2(seed: int = 2, n: int = 2 ** 21) -> Problem:
+def clustered_yukawa_d3(seed: int = 2, n: int = 2 ** 21) -> Problem:
     """Clustered box, three species (50/30/20), Yukawa-modified laws and a
     repulsive self-interaction of the third species."""
     D, box = 3, 1.0
@@ -263,7 +263,7 @@ def clustered_problem(n: int, D: int, seed: int, *, f_cl: float = 0.7,
                    leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed)
 
 
-def c3(seed: int = 3, n: int = 2 ** 24) -> Problem:
+def clustered_d6(seed: int = 3, n: int = 2 ** 24) -> Problem:
     """Clustered box at scale: six species, random G and random mixed laws."""
     p = clustered_problem(n, 6, seed, grid=GRID_R2, ntab=2048)
     p.name = f"clustered-{n}-D6-seed{seed}"

@@ -74,11 +74,11 @@ def full_parity(ctx, p, group_size=None, check_tree=True):
 
 @pytest.mark.parametrize("seed", range(1, 11))
 def test_uniform_4096_two_species(ctx, seed):
-    full_parity(ctx, synth.c1(seed))
+    full_parity(ctx, synth.uniform_4096(seed))
 
 
 def test_clustered_three_species_yukawa(ctx):
-    full_parity(ctx, synth.c2(2, n=2 ** 15))
+    full_parity(ctx, synth.clustered_yukawa_d3(2, n=2 ** 15))
 
 
 def test_clustered_six_species_r2_grid(ctx):
@@ -242,14 +242,14 @@ def test_errors_are_reported(ctx):
 def test_sampled_parity_at_2_21(ctx):
     """The three-species clustered box at full size: exact counts and the
     force gate on a seeded sample of groups (the oracle computes only those)."""
-    sampled_parity(ctx, synth.c2(2), n_groups=400)
+    sampled_parity(ctx, synth.clustered_yukawa_d3(2), n_groups=400)
 
 
 @pytest.mark.slow
 def test_sampled_parity_at_2_24_six_species(ctx):
     """The 2^24, six-species workload of the benchmark, in its launch
     configuration, on a seeded sample of groups."""
-    sampled_parity(ctx, synth.c3(3), n_groups=300)
+    sampled_parity(ctx, synth.clustered_d6(3), n_groups=300)
 
 
 def sampled_parity(ctx, p, n_groups):

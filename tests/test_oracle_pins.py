@@ -465,13 +465,13 @@ def test_cubic_lattice_has_no_net_force(oracle_lib):
     assert np.max(np.abs(ad)) <= 1e-12 * (1.0 / n) / s ** 2
 
 
-@pytest.mark.parametrize("maker", ["c2small", "d6small", "uniform"])
+@pytest.mark.parametrize("maker", ["yukawa_d3", "mixed_d6", "uniform"])
 def test_tree_accuracy_within_paper_tolerance(oracle_lib, maker):
     """Tree versus direct sum at theta = 0.5: the 99th percentile of
     |a_tree - a_dir| / |a_dir| stays within the paper's tree tolerance."""
     alpha = paper_constant("tree_error_tolerance_alpha")
-    p = {"c2small": lambda: synth.c2(2, n=2 ** 15),
-         "d6small": lambda: synth.clustered_problem(2 ** 15, 6, 3),
+    p = {"yukawa_d3": lambda: synth.clustered_yukawa_d3(2, n=2 ** 15),
+         "mixed_d6": lambda: synth.clustered_problem(2 ** 15, 6, 3),
          "uniform": lambda: synth.uniform_problem(2 ** 14, 2, 4)}[maker]()
     T = oracle_lib.Tree.of(p)
     acc, _, cnt, _ = T.force(oracle_lib.law_of(p))

@@ -36,5 +36,5 @@ def test_tables_and_params():
     assert abs(r_s - 1.25 / 1024) < 1e-15 and abs(eps - 1 / 10240) < 1e-15 and r_cut == 4.5 * r_s
     t = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, r_s), 2048, r_cut, synth.GRID_R2)
     assert t[0] == 1.0 and 0.0175 < t[-1] < 0.0176
-    p = synth.c1(1)
+    p = synth.uniform_4096(1)
     assert p.n == 4096 and p.D == 2 and p.tables.shape == (2, 2, 1024) and p.lattice.dtype == np.uint64
