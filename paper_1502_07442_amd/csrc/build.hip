@@ -28,13 +28,18 @@ __global__ void check_inputs(uint64_t n, uint32_t D, const uint8_t* __restrict__
     __syncthreads();
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bad = 0;
+    uint32_t s = NGR_MAX_SPECIES;
     if (i < n) {
-        uint32_t s = species[i];
+        s = species[i];
         double m = mass[i];
         if (s >= D) bad |= kBadSpecies;
-        else atomicAdd(&local[s], 1u);
         if (!(m >= 0.0) || !isfinite(m)) bad |= kBadMass;
         if (pos && !(isfinite(pos[i]) && isfinite(pos[n + i]) && isfinite(pos[2 * n + i]))) bad |= kBadPos;
+    }
+    // species counts: one LDS add per wave and species
+    for (uint32_t b = 0; b < D; ++b) {
+        const unsigned long long m = __ballot(s == b);
+        if ((threadIdx.x & 63u) == 0 && m) atomicAdd(&local[b], (unsigned)__popcll(m));
     }
     if (bad) atomicOr(flags, bad);
     __syncthreads();
@@ -168,13 +173,18 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
     uint64_t pl = t / 8;
     uint64_t p = level_begin + pl;
     uint32_t o = (uint32_t)(t % 8);
+    bool leaf = false;
     if (o == 0) {
         uint32_t nc = 0;
         for (int k = 0; k < 8; ++k) nc += flags[pl * 8 + k];
         n_child[p] = (uint8_t)nc;
         first_child[p] = nc ? (int32_t)(next_begin + offs[pl * 8]) : -1;
-        if (!nc) atomicAdd(leaves, 1ull);
+        leaf = nc == 0;
     }
+    // new leaves: the wave's first one adds the wave's count
+    const unsigned long long lm = __ballot(leaf);
+    const uint32_t ln = __lane_id();
+    if (leaf && __popcll(lm & ((1ull << ln) - 1ull)) == 0) atomicAdd(leaves, (unsigned long long)__popcll(lm));
     if (!flags[t]) return;
     uint64_t c = next_begin + offs[t];
     level[c] = (uint8_t)(lvl + 1);

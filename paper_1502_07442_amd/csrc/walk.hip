@@ -28,6 +28,14 @@
 
 #include "ngr_internal.hpp"
 
+// Records evaluated per iteration of the pair loop (independent chains for
+// the scheduler to interleave).
+#ifndef NGR_EVAL_UNROLL
+#define NGR_EVAL_UNROLL 2
+#endif
+#define NGR_STR2(x) #x
+#define NGR_PRAGMA_UNROLL(n) _Pragma(NGR_STR2(unroll n))
+
 namespace ngr {
 namespace {
 
@@ -112,11 +120,75 @@ __global__ void read_positions(const uint32_t* __restrict__ v, const uint64_t* _
     if (t < k) out[t] = pos[t] < n ? v[pos[t]] : total_if_end;
 }
 
+// ------------------------------------------------------- group order ----
+// The walk hands groups out heaviest first, estimated from the particle
+// density around each group: particles per cell of a level-L grid whose cell
+// side is at least r_cut, summed over the 5 x 5 x 5 cells around the group's
+// first particle. Cells of level L carry the total count of their node;
+// particles of leaves above level L are counted one by one.
+constexpr int kOrderRadius = 2;
+
+__global__ void density_grid(uint64_t nodes, uint32_t D, uint32_t L, const uint4* __restrict__ cell,
+                             const uint8_t* __restrict__ n_child, const uint32_t* __restrict__ start,
+                             const uint32_t* __restrict__ count, const uint64_t* __restrict__ X, uint64_t n,
+                             uint32_t* __restrict__ H)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nodes) return;
+    const uint4 c = cell[i];
+    const uint32_t sh = (uint32_t)kLevels - L;
+    if (c.w == L) {
+        uint32_t tot = 0;
+        for (uint32_t b = 0; b < D; ++b) tot += count[i * D + b];
+        H[((uint64_t)(c.x >> sh) << (2 * L)) | ((uint64_t)(c.y >> sh) << L) | (c.z >> sh)] = tot;
+    } else if (c.w < L && n_child[i] == 0) {
+        for (uint32_t b = 0; b < D; ++b) {
+            const uint64_t s = start[i * D + b], e = s + count[i * D + b];
+            for (uint64_t j = s; j < e; ++j) {
+                const uint64_t x = X[j] >> (64 - L), y = X[n + j] >> (64 - L), z = X[2 * n + j] >> (64 - L);
+                atomicAdd(&H[(x << (2 * L)) | (y << L) | z], 1u);
+            }
+        }
+    }
+}
+
+// Sort key of every group: species, then the density bucket descending
+// (half-octave steps of the neighbourhood count); value: the group index.
+__global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t L, const uint32_t* __restrict__ gstart,
+                                 const uint64_t* __restrict__ keys, const uint64_t* __restrict__ X,
+                                 const uint32_t* __restrict__ H, uint64_t* __restrict__ okey,
+                                 uint32_t* __restrict__ oval)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const uint64_t j = gstart[g];
+    uint32_t v = 1;
+    if (L > 0) {
+        const int32_t S = 1 << L, m = S - 1;
+        const int32_t x = (int32_t)(X[j] >> (64 - L)), y = (int32_t)(X[n + j] >> (64 - L)),
+                      z = (int32_t)(X[2 * n + j] >> (64 - L));
+        for (int32_t dx = -kOrderRadius; dx <= kOrderRadius; ++dx)
+            for (int32_t dy = -kOrderRadius; dy <= kOrderRadius; ++dy)
+                for (int32_t dz = -kOrderRadius; dz <= kOrderRadius; ++dz) {
+                    const uint64_t q = ((uint64_t)((x + dx) & m) << (2 * L)) | ((uint64_t)((y + dy) & m) << L) |
+                                       (uint64_t)((z + dz) & m);
+                    v += H[q];
+                }
+    }
+    const uint32_t msb = 31u - (uint32_t)__builtin_clz(v);
+    const uint32_t half = msb ? (v >> (msb - 1)) & 1u : 0u;
+    const uint32_t bucket = 2u * msb + half;            // < 64
+    okey[g] = ((keys[j] >> 60) << 8) | (255u - bucket);
+    oval[g] = (uint32_t)g;
+}
+
 // --------------------------------------------------------------- walk ----
 constexpr uint32_t kPrune = 0, kAccept = 1, kOpen = 2;
 constexpr int kBuf = 128;              // node / leaf buffer entries per wave
-constexpr int kWaveLds = 64 * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
+constexpr int kRec = 68;               // record slots per wave: 64 and up to 3 pads
+constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
 constexpr int kMaxWaves = 16;          // waves per workgroup
+constexpr int kCtrlBytes = 256;        // LDS control area ahead of the tables
 // Table layouts in LDS. PAIR: per interval (value, slope to the next sample),
 // with a (0, 0) entry that the clamped index reaches for r >= r_cut. VALUE:
 // the samples only (plus one pad), the slope taken from the next sample and
@@ -140,12 +212,13 @@ struct WalkArgs {
     const uint32_t* glo;
     const uint32_t* ghi;
     uint64_t ng;
-    uint32_t g0, g1;
-    uint32_t* queue;           // next group of this launch (counts from 0)
-    uint32_t D, a, ntab;
+    const uint32_t* order;     // group indices: species by species, heaviest first
+    uint32_t first[NGR_MAX_SPECIES + 1];   // groups of species a: order[first[a] .. first[a + 1])
+    uint32_t* queues;          // per species: groups of that species handed out so far
+    uint32_t D, ntab;
     const float2* table;       // PAIR layout, D x D x ntab
     const float* table_v;      // VALUE layout, D x D x (ntab + 1)
-    double G[NGR_MAX_SPECIES];
+    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
     double box, inv_box, eps2, R2, theta2;
     uint32_t wrap_limit;
     float tscale, toff, tmax;
@@ -176,25 +249,26 @@ __device__ inline uint32_t wave_incl(uint32_t v, int lane)
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Pair terms of this lane's sink with nrec LDS records of one source species.
-template <int GRID, int TAB, bool EPS0, bool WRAP>
-__device__ inline void eval_records(const WalkArgs& A, const double4* __restrict__ rec, uint32_t nrec,
+// Pair terms of this lane's sink with LDS records of one source species:
+// records rec[0], rec[K], rec[2K], ... (iters of them; the caller offsets rec
+// by the lane's replica).
+template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K>
+__device__ inline void eval_records(const WalkArgs& A, const double4* __restrict__ rec, uint32_t iters,
                                     const void* __restrict__ tbv, double ox, double oy, double oz, double& ax,
                                     double& ay, double& az)
 {
     const double eps2 = A.eps2;
     const float tscale = A.tscale, toff = A.toff, tmax = A.tmax;
-#pragma unroll 2
-    for (uint32_t r = 0; r < nrec; ++r) {
-        const double4 s = rec[r];
+    NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
+    for (uint32_t it = 0; it < iters; ++it) {
+        const double4 s = rec[it * K];
         double dx = s.x - ox, dy = s.y - oy, dz = s.z - oz;
         if (WRAP) {
             dx -= A.box * rint(dx * A.inv_box);
             dy -= A.box * rint(dy * A.inv_box);
             dz -= A.box * rint(dz * A.inv_box);
         }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double re2 = r2 + eps2;
+        const double re2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));   // r^2 + eps^2
         const float sf = (float)re2;
         const float z = __builtin_amdgcn_rsqf(sf);
         const double zd = (double)z;
@@ -202,11 +276,11 @@ __device__ inline void eval_records(const WalkArgs& A, const double4* __restrict
         const double e = fma(-re2, z2, 1.0);          // 1 - re2 z^2 = -2 (relative error of z)
         const double z3 = z2 * zd;
         float t;
-        if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);
-        else t = __builtin_sqrtf((float)r2) * tscale;
+        if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);                 // r^2 / h, from r^2 + eps^2
+        else t = __builtin_sqrtf((float)(re2 - eps2)) * tscale;             // r / h
         t = __builtin_amdgcn_fmed3f(t, 0.0f, tmax);
         const int k = (int)t;
-        const float w = t - (float)k;
+        const float w = __builtin_amdgcn_fractf(t);
         float f;
         if (TAB == kPair) {
             const float2 T = static_cast<const float2*>(tbv)[k];
@@ -218,7 +292,7 @@ __device__ inline void eval_records(const WalkArgs& A, const double4* __restrict
         }
         const double p = (double)f * s.w * z3;
         double coef = fma(p, 1.5 * e, p);              // (r^2+eps^2)^(-3/2) to ~1e-13
-        if (EPS0) coef = r2 > 0.0 ? coef : 0.0;
+        if (EPS0) coef = re2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
         az = fma(coef, dz, az);
@@ -239,20 +313,13 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const uint32_t D = A.D, ntab = A.ntab;
     const uint32_t tstride = TAB == kPair ? ntab : ntab + 1;   // entries per table
-    if (TAB == kPair) {
-        float2* tab = reinterpret_cast<float2*>(smem);
-        const float2* src = A.table + (uint64_t)A.a * D * ntab;
-        for (uint32_t k = threadIdx.x; k < D * ntab; k += blockDim.x) tab[k] = src[k];
-    } else {
-        float* tab = reinterpret_cast<float*>(smem);
-        const float* src = A.table_v + (uint64_t)A.a * D * (ntab + 1);
-        for (uint32_t k = threadIdx.x; k < D * (ntab + 1); k += blockDim.x) tab[k] = src[k];
-    }
-    __syncthreads();
+    // LDS: a control word, the sink species' D tables, then per-wave buffers
+    int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+    unsigned char* tsm = smem + kCtrlBytes;
     const uint32_t tab_bytes = table_bytes(TAB, D, ntab);
-    unsigned char* wb = smem + tab_bytes + wave * kWaveLds;
+    unsigned char* wb = tsm + tab_bytes + wave * kWaveLds;
     double4* rec = reinterpret_cast<double4*>(wb);
-    uint32_t* pnb = reinterpret_cast<uint32_t*>(wb + 64 * 32);
+    uint32_t* pnb = reinterpret_cast<uint32_t*>(wb + kRec * 32);
     uint32_t* ppb = pnb + kBuf;
     uint32_t* scanb = ppb + kBuf;        // 68 entries
     uint32_t* pst = scanb + 68;          // 64 entries
@@ -261,18 +328,51 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     const double scale = A.box * 0x1p-64;
     const uint64_t n = A.n;
 
-    // Waves take groups from a queue. Every lane executes the atomic (lane 0
-    // adds one, the others add zero), so no lane-dependent branch surrounds
-    // it; lane 0 is the first active lane and its return value is the wave's
-    // ticket. The loop exit then depends only on that wave-uniform value and
-    // the lanes of a wave stay together (cross-lane operations inside the
-    // loop need all of them).
+    // One launch serves every sink species. A workgroup holds the tables of
+    // one species at a time: it starts on a species of its own (the
+    // workgroups are spread over the species that have groups), its waves
+    // take that species' groups until none is left, and then, together, it
+    // moves to the species with the most groups still to hand out.
+    uint32_t a = 0;
+    {
+        uint32_t nonempty = 0;
+        for (uint32_t b = 0; b < D; ++b) nonempty += A.first[b + 1] > A.first[b] ? 1u : 0u;
+        const uint32_t k = blockIdx.x % max(nonempty, 1u);
+        uint32_t seen = 0;
+        for (uint32_t b = 0; b < D; ++b) {
+            const bool ne = A.first[b + 1] > A.first[b];
+            if (ne && seen == k) a = b;
+            seen += ne ? 1u : 0u;
+        }
+    }
+
     unsigned long long tot_pp = 0, tot_pn = 0;
     bool any_overflow = false;
     for (;;) {
-        const uint32_t ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
-        const uint32_t g = A.g0 + uniform(ticket);
-        if (g >= A.g1) break;
+        if (TAB == kPair) {
+            float2* tab = reinterpret_cast<float2*>(tsm);
+            const float2* src = A.table + (uint64_t)a * D * ntab;
+            for (uint32_t k = threadIdx.x; k < D * ntab; k += blockDim.x) tab[k] = src[k];
+        } else {
+            float* tab = reinterpret_cast<float*>(tsm);
+            const float* src = A.table_v + (uint64_t)a * D * (ntab + 1);
+            for (uint32_t k = threadIdx.x; k < D * (ntab + 1); k += blockDim.x) tab[k] = src[k];
+        }
+        __syncthreads();
+        const uint32_t g_begin = A.first[a], g_count = A.first[a + 1] - A.first[a];
+        uint32_t* const queue = A.queues + a;
+        const double* const Ga = A.G + a * D;
+
+    // Waves take groups from the species' queue. Every lane executes the
+    // atomic (lane 0 adds one, the others add zero), so no lane-dependent
+    // branch surrounds it; lane 0 is the first active lane and its return
+    // value is the wave's ticket. The loop exit then depends only on that
+    // wave-uniform value and the lanes of a wave stay together (cross-lane
+    // operations inside the loop need all of them).
+    for (;;) {
+        const uint32_t ticket = uniform(atomicAdd(queue, lane == 0 ? 1u : 0u));
+        if (ticket >= g_count) break;
+        const uint32_t g = A.order[g_begin + ticket];
         const uint32_t s0 = A.gstart[g], ns = A.gcount[g];
         uint32_t lo[3], hi[3];
         bool wrap = false;
@@ -287,9 +387,19 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                        C2 = (uint64_t)(lo[2] + hi[2]) << 43;
         const double cf0 = (double)(lo[0] + hi[0]) * 0x1p-21, cf1 = (double)(lo[1] + hi[1]) * 0x1p-21,
                      cf2 = (double)(lo[2] + hi[2]) * 0x1p-21;
+        // A group of at most 32 (16) sinks runs K = 2 (4) copies of itself,
+        // one per 32 (16) lanes; copy q takes records q, q + K, q + 2K, ...
+        // and the copies' sums are added at the end. Far away massless pads
+        // after the last record give the copies equal trip counts. Groups
+        // that need the periodic wrap run one copy.
+        const uint32_t lk = wrap ? 0u : ns <= 16u ? 2u : ns <= 32u ? 1u : 0u;
+        const uint32_t K = 1u << lk;
+        const uint32_t sink = (uint32_t)lane & ((64u >> lk) - 1u), replica = (uint32_t)lane >> (6u - lk);
+        const double4* const rrec = rec + replica;
+        const double4 pad = make_double4(1e30, 1e30, 1e30, 0.0);
         double ox = 0.0, oy = 0.0, oz = 0.0;
-        if ((uint32_t)lane < ns) {
-            uint64_t i = s0 + lane;
+        if (sink < ns) {
+            uint64_t i = s0 + sink;
             ox = (double)(int64_t)(A.X[i] - C0) * scale;
             oy = (double)(int64_t)(A.X[n + i] - C1) * scale;
             oz = (double)(int64_t)(A.X[2 * n + i] - C2) * scale;
@@ -298,9 +408,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
 
         auto eval = [&](uint32_t b, uint32_t nrec) {
-            const unsigned char* tb = smem + (TAB == kPair ? 8u : 4u) * b * tstride;
-            if (wrap) eval_records<GRID, TAB, EPS0, true>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else eval_records<GRID, TAB, EPS0, false>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            const unsigned char* tb = tsm + (TAB == kPair ? 8u : 4u) * b * tstride;
+            const uint32_t iters = (nrec + K - 1u) >> lk;
+            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(A, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            else eval_records<GRID, TAB, EPS0, false, 4>(A, rrec, iters, tb, ox, oy, oz, ax, ay, az);
         };
 
         // Accepted nodes: one record per non-empty species monopole.
@@ -316,8 +429,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     d0 -= rint(d0);
                     d1 -= rint(d1);
                     d2 -= rint(d2);
-                    rec[__popcll(m & lt)] = make_double4(d0 * A.box, d1 * A.box, d2 * A.box, A.G[b] * r.w);
+                    rec[__popcll(m & lt)] = make_double4(d0 * A.box, d1 * A.box, d2 * A.box, Ga[b] * r.w);
                 }
+                if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
                 wave_sync();
                 if (nrec) eval(b, nrec);
                 pn_src += nrec;
@@ -355,8 +469,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                         rec[lane] = make_double4((double)(int64_t)(A.X[j] - C0) * scale,
                                                  (double)(int64_t)(A.X[n + j] - C1) * scale,
                                                  (double)(int64_t)(A.X[2 * n + j] - C2) * scale,
-                                                 A.G[b] * A.mass[j]);
+                                                 Ga[b] * A.mass[j]);
                     }
+                    if (K > 1u && (uint32_t)lane < 3u) rec[min(64u, T - base) + lane] = pad;
                     wave_sync();
                     eval(b, min(64u, T - base));
                     wave_sync();
@@ -448,6 +563,17 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             if (npn) flush_nodes(npn);
             if (npp) flush_leaves(npp);
         }
+        // fold the copies' sums into lanes 0 .. 64/K - 1 (fixed order)
+        if (K == 4u) {
+            ax += __shfl_xor(ax, 16, 64);
+            ay += __shfl_xor(ay, 16, 64);
+            az += __shfl_xor(az, 16, 64);
+        }
+        if (K >= 2u) {
+            ax += __shfl_xor(ax, 32, 64);
+            ay += __shfl_xor(ay, 32, 64);
+            az += __shfl_xor(az, 32, 64);
+        }
         if ((uint32_t)lane < ns) {
             const uint32_t p = A.perm[s0 + lane];
             A.acc[p] = ax;
@@ -461,6 +587,24 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             const unsigned long long v[4] = {n_acc, n_leaf, pn, pp};
             A.gcounts[4ull * g + lane] = v[lane];
         }
+    }
+        __syncthreads();                   // every wave is done with this species' tables
+        if (wave == 0) {
+            uint32_t best = D, best_left = 0;
+            for (uint32_t b = 0; b < D; ++b) {
+                const uint32_t cnt = A.first[b + 1] - A.first[b];
+                const uint32_t q = uniform(atomicAdd(A.queues + b, 0u));
+                const uint32_t left = cnt - min(q, cnt);
+                if (left > best_left) {
+                    best_left = left;
+                    best = b;
+                }
+            }
+            ctrl[0] = (int32_t)best;       // every lane stores the same value
+        }
+        __syncthreads();
+        a = uniform((uint32_t)ctrl[0]);
+        if (a >= D) break;
     }
     if (lane == 0) {
         atomicAdd(&A.stats[0], tot_pp);
@@ -575,6 +719,36 @@ void upload_law(Context& ctx, const ngr_force_params& fp, uint32_t D, Law& law)
     ctx.to_device(law.table_v, hv.data(), nv * sizeof(float));
 }
 
+// Group indices species by species, each species' groups in descending
+// order of the density estimate (ties in tree order). Returns device memory
+// of g.ng entries, to be released by the caller.
+static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, double r_cut)
+{
+    const uint64_t ng = g.ng;
+    // the finest level whose cells are at least r_cut wide, at most 8
+    uint32_t L = 0;
+    while (L < 8 && std::ldexp(t.box, -(int)(L + 1)) >= r_cut) ++L;
+    uint64_t* okey = static_cast<uint64_t*>(ctx.alloc(2 * ng * sizeof(uint64_t)));
+    uint32_t* oval = static_cast<uint32_t*>(ctx.alloc(2 * ng * sizeof(uint32_t)));
+    uint32_t* H = nullptr;
+    if (L > 0) {
+        const uint64_t cells = 1ull << (3 * L);
+        H = static_cast<uint32_t*>(ctx.alloc(cells * sizeof(uint32_t)));
+        HIP_CHECK(hipMemsetAsync(H, 0, cells * sizeof(uint32_t), ctx.stream));
+        const uint64_t nodes = t.level_start[std::min<uint32_t>(L, t.depth) + 1];
+        hipLaunchKernelGGL(density_grid, dim3(blocks_for(nodes, 256)), dim3(256), 0, ctx.stream, nodes, t.D, L,
+                           t.cell, t.n_child, t.start, t.count, t.X, t.n, H);
+        LAUNCH_CHECK("density_grid");
+    }
+    hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.n, L, g.start,
+                       t.keys, t.X, H, okey, oval);
+    LAUNCH_CHECK("group_order_keys");
+    radix_sort_pairs(ctx, okey, oval, okey + ng, oval + ng, ng, 16);
+    if (H) ctx.release(H);
+    ctx.release(okey);
+    return oval;
+}
+
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, double* acc,
                 uint64_t* group_counts_dev, WalkOut& out)
 {
@@ -585,10 +759,10 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     // (value, slope) tables when at least 8 waves still fit beside them
     const size_t lds_max = ctx.lds_per_block;
     int mode = kPair;
-    size_t tab_bytes = table_bytes(kPair, D, law.ntab);
+    size_t tab_bytes = kCtrlBytes + table_bytes(kPair, D, law.ntab);
     if (tab_bytes + 8 * (size_t)kWaveLds > lds_max) {
         mode = kValue;
-        tab_bytes = table_bytes(kValue, D, law.ntab);
+        tab_bytes = kCtrlBytes + table_bytes(kValue, D, law.ntab);
     }
     if (tab_bytes + kWaveLds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
     const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - tab_bytes) / kWaveLds);
@@ -602,6 +776,8 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     uint32_t* err = reinterpret_cast<uint32_t*>(stats + 4);
     uint32_t* queues = err + 8;
     HIP_CHECK(hipMemsetAsync(ctx.counters.p, 0, 4096, ctx.stream));
+    ctx.stage("walk: order");
+    uint32_t* order = order_groups(ctx, t, g, law.r_cut);
 
     WalkArgs A{};
     A.cell = t.cell;
@@ -620,10 +796,14 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     A.glo = g.lo;
     A.ghi = g.hi;
     A.ng = g.ng;
+    A.order = order;
+    for (uint32_t a = 0; a <= D; ++a) A.first[a] = (uint32_t)g.first[a];
+    A.queues = queues;
     A.D = D;
     A.ntab = law.ntab;
     A.table = law.table;
     A.table_v = law.table_v;
+    for (uint32_t k = 0; k < D * D; ++k) A.G[k] = law.G[k];
     A.box = t.box;
     A.inv_box = 1.0 / t.box;
     A.eps2 = law.eps * law.eps;
@@ -658,34 +838,27 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     HIP_CHECK(hipEventCreate(&e1));
     HIP_CHECK(hipEventRecord(e0, ctx.stream));
     const bool eps0 = law.eps == 0.0;
-    for (uint32_t a = 0; a < D; ++a) {
-        if (g.first[a + 1] <= g.first[a]) continue;
-        A.a = a;
-        A.g0 = (uint32_t)g.first[a];
-        A.g1 = (uint32_t)g.first[a + 1];
-        A.queue = queues + a;
-        for (uint32_t b = 0; b < D; ++b) A.G[b] = law.G[a * D + b];
-        ctx.stage("walk: launch");
-        auto launch = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, dim3(blocks), dim3(waves * 64), lds, ctx.stream, A);
-            LAUNCH_CHECK("walk_kernel");
-        };
-        const int sel = (law.grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
-        switch (sel) {
-        case 0: launch(walk_kernel<NGR_GRID_R, kPair, false>); break;
-        case 1: launch(walk_kernel<NGR_GRID_R, kPair, true>); break;
-        case 2: launch(walk_kernel<NGR_GRID_R, kValue, false>); break;
-        case 3: launch(walk_kernel<NGR_GRID_R, kValue, true>); break;
-        case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false>); break;
-        case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true>); break;
-        case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false>); break;
-        default: launch(walk_kernel<NGR_GRID_R2, kValue, true>); break;
-        }
+    ctx.stage("walk: launch");
+    auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(waves * 64), lds, ctx.stream, A);
+        LAUNCH_CHECK("walk_kernel");
+    };
+    const int sel = (law.grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
+    switch (sel) {
+    case 0: launch(walk_kernel<NGR_GRID_R, kPair, false>); break;
+    case 1: launch(walk_kernel<NGR_GRID_R, kPair, true>); break;
+    case 2: launch(walk_kernel<NGR_GRID_R, kValue, false>); break;
+    case 3: launch(walk_kernel<NGR_GRID_R, kValue, true>); break;
+    case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false>); break;
+    case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true>); break;
+    case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false>); break;
+    default: launch(walk_kernel<NGR_GRID_R2, kValue, true>); break;
     }
     HIP_CHECK(hipEventRecord(e1, ctx.stream));
     uint64_t words[40];
     ctx.read_words(words, ctx.counters.p, 40);
     ctx.stage("walk: done");
+    ctx.release(order);
     float ms = 0.0f;
     HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
     HIP_CHECK(hipEventDestroy(e0));

@@ -48,6 +48,7 @@ def full_parity(ctx, p, group_size=None, check_tree=True):
             assert tree.n_nodes == T.n_nodes
             for k in ("level", "prefix", "parent", "first_child", "n_child", "start", "count"):
                 assert np.array_equal(ex[k], nd[k]), k
+            assert (st["n_nodes"], st["n_leaves"]) == (T.n_nodes, int(np.count_nonzero(nd["n_child"] == 0)))
             M, com = ngr.monopoles_export(ctx, tree)
             Mo, como = T.monopole_arrays()
             # float64 sums of N terms in different orders (bottom-up on the GPU,
