@@ -23,27 +23,31 @@ __global__ void check_inputs(uint64_t n, uint32_t D, const uint8_t* __restrict__
                              const double* __restrict__ mass, const double* __restrict__ pos,
                              uint32_t* __restrict__ flags, unsigned long long* __restrict__ counts)
 {
+    // grid-stride over a bounded grid: one global atomic per workgroup and
+    // species (same-address atomics from the whole chip are slow)
     __shared__ unsigned int local[NGR_MAX_SPECIES];
+    __shared__ unsigned int local_bad;
     if (threadIdx.x < NGR_MAX_SPECIES) local[threadIdx.x] = 0;
+    if (threadIdx.x == 0) local_bad = 0;
     __syncthreads();
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bad = 0;
-    uint32_t s = NGR_MAX_SPECIES;
-    if (i < n) {
-        s = species[i];
-        double m = mass[i];
+    uint32_t mine[NGR_MAX_SPECIES] = {0, 0, 0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t s = species[i];
+        const double m = mass[i];
         if (s >= D) bad |= kBadSpecies;
+#pragma unroll
+        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) mine[b] += s == b ? 1u : 0u;
         if (!(m >= 0.0) || !isfinite(m)) bad |= kBadMass;
         if (pos && !(isfinite(pos[i]) && isfinite(pos[n + i]) && isfinite(pos[2 * n + i]))) bad |= kBadPos;
     }
-    // species counts: one LDS add per wave and species
-    for (uint32_t b = 0; b < D; ++b) {
-        const unsigned long long m = __ballot(s == b);
-        if ((threadIdx.x & 63u) == 0 && m) atomicAdd(&local[b], (unsigned)__popcll(m));
-    }
-    if (bad) atomicOr(flags, bad);
+    for (uint32_t b = 0; b < D; ++b)
+        if (mine[b]) atomicAdd(&local[b], mine[b]);
+    if (bad) atomicOr(&local_bad, bad);
     __syncthreads();
     if (threadIdx.x < D && local[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)local[threadIdx.x]);
+    if (threadIdx.x == 0 && local_bad) atomicOr(flags, local_bad);
 }
 
 // Positions to 64-bit lattice coordinates, X = floor(u * 2^64) with
@@ -165,26 +169,19 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
                               uint32_t D, const uint32_t* __restrict__ flags, const uint32_t* __restrict__ offs,
                               const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ ccount,
                               uint8_t* level, uint64_t* prefix, int32_t* parent, int32_t* first_child,
-                              uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count,
-                              unsigned long long* leaves)
+                              uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_level * 8) return;
     uint64_t pl = t / 8;
     uint64_t p = level_begin + pl;
     uint32_t o = (uint32_t)(t % 8);
-    bool leaf = false;
     if (o == 0) {
         uint32_t nc = 0;
         for (int k = 0; k < 8; ++k) nc += flags[pl * 8 + k];
         n_child[p] = (uint8_t)nc;
         first_child[p] = nc ? (int32_t)(next_begin + offs[pl * 8]) : -1;
-        leaf = nc == 0;
     }
-    // new leaves: the wave's first one adds the wave's count
-    const unsigned long long lm = __ballot(leaf);
-    const uint32_t ln = __lane_id();
-    if (leaf && __popcll(lm & ((1ull << ln) - 1ull)) == 0) atomicAdd(leaves, (unsigned long long)__popcll(lm));
     if (!flags[t]) return;
     uint64_t c = next_begin + offs[t];
     level[c] = (uint8_t)(lvl + 1);
@@ -200,6 +197,21 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
         start[c * D + b] = cstart[t * D + b];
         count[c * D + b] = ccount[t * D + b];
     }
+}
+
+// Number of leaves (nodes without children), over a bounded grid with one
+// global atomic per workgroup.
+__global__ void count_leaves(uint64_t nn, const uint8_t* __restrict__ n_child, unsigned long long* __restrict__ out)
+{
+    __shared__ unsigned long long part;
+    if (threadIdx.x == 0) part = 0;
+    __syncthreads();
+    unsigned long long c = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += stride) c += n_child[i] == 0;
+    if (c) atomicAdd(&part, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && part) atomicAdd(out, part);
 }
 
 // Monopoles of one level (section 2.2), one thread per (node, species b).
@@ -293,7 +305,8 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(flags + 2);
     HIP_CHECK(hipMemsetAsync(flags, 0, (1 + NGR_MAX_SPECIES) * sizeof(uint64_t), ctx.stream));
     if (n) {
-        hipLaunchKernelGGL(check_inputs, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, D, p.species, p.mass, p.pos, flags, counts);
+        hipLaunchKernelGGL(check_inputs, dim3((unsigned)std::min<uint64_t>(blocks_for(n, 256), 4u * ctx.num_cu)), dim3(256), 0,
+                           ctx.stream, n, D, p.species, p.mass, p.pos, flags, counts);
         LAUNCH_CHECK("check_inputs");
     }
     uint64_t host[1 + NGR_MAX_SPECIES];
@@ -372,7 +385,7 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
         uint64_t nb = t.level_start[lvl + 1];
         grow_nodes(ctx, t, nb + next);
         hipLaunchKernelGGL(emit_children, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, nb, lvl, D, fl, offs, cst, ccn, t.level, t.prefix, t.parent, t.first_child, t.n_child,
-            t.cell, t.start, t.count, leaves);
+            t.cell, t.start, t.count);
         LAUNCH_CHECK("emit_children");
         ctx.release(fl);
         ctx.release(cst);
@@ -380,6 +393,9 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
         t.level_start.push_back(nb + next);
     }
     t.depth = depth;
+    hipLaunchKernelGGL(count_leaves, dim3((unsigned)std::min<uint64_t>(blocks_for(t.nn, 256), 4u * ctx.num_cu)), dim3(256),
+                       0, ctx.stream, t.nn, t.n_child, leaves);
+    LAUNCH_CHECK("count_leaves");
     ctx.stage("build: done");
     uint64_t nleaves = 0;
     ctx.read_words(&nleaves, leaves, 1);

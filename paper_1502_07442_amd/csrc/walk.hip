@@ -87,29 +87,39 @@ __global__ void scatter_group_starts(uint64_t n, const uint32_t* __restrict__ fl
 }
 
 // Count and integer bounding box (20-bit key lattice, hi exclusive) of each
-// group; a group ends where the next one starts.
+// group; a group ends where the next one starts. One wave per group (at most
+// 64 particles), one particle per lane.
 __global__ void finish_groups(uint64_t ng, uint64_t n, uint32_t Ng, const uint32_t* __restrict__ gstart,
                               uint32_t* __restrict__ gcount, uint32_t* __restrict__ glo, uint32_t* __restrict__ ghi,
                               const uint64_t* __restrict__ X, uint32_t* __restrict__ error_flag)
 {
-    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;   // the same for the whole wave
+    const uint32_t lane = threadIdx.x & 63u;
     if (g >= ng) return;
-    uint64_t s = gstart[g], e = (g + 1 < ng) ? gstart[g + 1] : n;
-    if (e <= s || e - s > Ng || e > n) {   // groups hold 1..Ng consecutive particles
-        atomicOr(error_flag, 1u);
-        gcount[g] = 0;
+    const uint64_t s = gstart[g], e = (g + 1 < ng) ? gstart[g + 1] : n;
+    if (e <= s || e - s > Ng || e - s > 64 || e > n) {   // groups hold 1..Ng consecutive particles
+        if (lane == 0) {
+            atomicOr(error_flag, 1u);
+            gcount[g] = 0;
+        }
         return;
     }
-    gcount[g] = (uint32_t)(e - s);
+    if (lane == 0) gcount[g] = (uint32_t)(e - s);
     for (int a = 0; a < 3; ++a) {
         uint32_t lo = 0xffffffffu, hi = 0;
-        for (uint64_t j = s; j < e; ++j) {
-            uint32_t k = (uint32_t)(X[a * n + j] >> 44);
-            lo = min(lo, k);
-            hi = max(hi, k + 1);
+        if (s + lane < e) {
+            const uint32_t k = (uint32_t)(X[a * n + s + lane] >> 44);
+            lo = k;
+            hi = k + 1;
         }
-        glo[a * ng + g] = lo;
-        ghi[a * ng + g] = hi;
+        for (int d = 32; d > 0; d >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+        }
+        if (lane == 0) {
+            glo[a * ng + g] = lo;
+            ghi[a * ng + g] = hi;
+        }
     }
 }
 
@@ -606,10 +616,24 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         a = uniform((uint32_t)ctrl[0]);
         if (a >= D) break;
     }
+    // workgroup totals first: one global atomic per workgroup and counter
+    // (every wave has left the species loop through the same barriers)
+    unsigned long long* part = reinterpret_cast<unsigned long long*>(wb);
     if (lane == 0) {
-        atomicAdd(&A.stats[0], tot_pp);
-        atomicAdd(&A.stats[1], tot_pn);
+        part[0] = tot_pp;
+        part[1] = tot_pn;
         if (any_overflow) atomicOr(A.error_flag, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long pp = 0, pn = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            const unsigned long long* q = reinterpret_cast<const unsigned long long*>(tsm + tab_bytes + w * kWaveLds);
+            pp += q[0];
+            pn += q[1];
+        }
+        atomicAdd(&A.stats[0], pp);
+        atomicAdd(&A.stats[1], pn);
     }
 }
 
@@ -664,7 +688,7 @@ void make_groups(Context& ctx, const Tree& t, uint32_t group_size, Groups& g)
     hipLaunchKernelGGL(scatter_group_starts, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, flags, gidx,
                        g.start);
     LAUNCH_CHECK("scatter_group_starts");
-    hipLaunchKernelGGL(finish_groups, dim3(blocks_for(ngh, 256)), dim3(256), 0, ctx.stream, (uint64_t)ngh, n,
+    hipLaunchKernelGGL(finish_groups, dim3(blocks_for((uint64_t)ngh * 64, 256)), dim3(256), 0, ctx.stream, (uint64_t)ngh, n,
                        group_size, g.start, g.count, g.lo, g.hi, t.X, errd);
     LAUNCH_CHECK("finish_groups");
     uint64_t words[8];
