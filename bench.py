@@ -27,6 +27,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def walk_traffic():
+    """HBM bytes of one walk launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None when the walk sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "walk_clustered_2p24_D6_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        k, _, v = line.strip().partition(": ")
+        if k in ("walk_traffic_bytes", "source_sha256"):
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("walk.hip", "ngr_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1502_07442_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or "walk_traffic_bytes" not in fields:
+        return None
+    return float(fields["walk_traffic_bytes"])
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -130,7 +152,7 @@ def main():
         "walk_ms": ms_walk,
         "walk_interactions_per_s": inter / (ms_walk * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": walk_traffic()},
     }
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores")

@@ -228,7 +228,7 @@ struct WalkArgs {
     uint32_t D, ntab;
     const float2* table;       // PAIR layout, D x D x ntab
     const float* table_v;      // VALUE layout, D x D x (ntab + 1)
-    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
+    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // 1.5 G_ab (row a = sink species)
     double box, inv_box, eps2, R2, theta2;
     uint32_t wrap_limit;
     float tscale, toff, tmax;
@@ -283,7 +283,10 @@ __device__ inline void eval_records(const WalkArgs& A, const double4* __restrict
         const float z = __builtin_amdgcn_rsqf(sf);
         const double zd = (double)z;
         const double z2 = zd * zd;
-        const double e = fma(-re2, z2, 1.0);          // 1 - re2 z^2 = -2 (relative error of z)
+        // with e = 1 - re2 z^2 (minus twice the relative error of z),
+        // (r^2+eps^2)^(-3/2) = z^3 (1 + 1.5 e) to ~1e-13; the records carry
+        // 1.5 G m, so the factor used is 5/3 - re2 z^2 = (1 + 1.5 e) / 1.5
+        const double e = fma(-re2, z2, 5.0 / 3.0);
         const double z3 = z2 * zd;
         float t;
         if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);                 // r^2 / h, from r^2 + eps^2
@@ -301,7 +304,7 @@ __device__ inline void eval_records(const WalkArgs& A, const double4* __restrict
             f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
         }
         const double p = (double)f * s.w * z3;
-        double coef = fma(p, 1.5 * e, p);              // (r^2+eps^2)^(-3/2) to ~1e-13
+        double coef = p * e;
         if (EPS0) coef = re2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
@@ -827,7 +830,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     A.ntab = law.ntab;
     A.table = law.table;
     A.table_v = law.table_v;
-    for (uint32_t k = 0; k < D * D; ++k) A.G[k] = law.G[k];
+    for (uint32_t k = 0; k < D * D; ++k) A.G[k] = 1.5 * law.G[k];   // see eval_records
     A.box = t.box;
     A.inv_box = 1.0 / t.box;
     A.eps2 = law.eps * law.eps;
