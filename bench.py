@@ -49,6 +49,57 @@ def walk_traffic():
     return float(fields["walk_traffic_bytes"])
 
 
+def batched(ngr, synth, nbox=256, reps=3):
+    """The many-box workload: nbox independent boxes in one
+    ngr_batch_build_force call (group size chosen by the library), against
+    the same boxes looped box by box through the single-box calls on the same
+    stream. Inputs are resident before timing; each call includes the build."""
+    import numpy as np
+    import torch
+    probs = [synth.batch_box(k) for k in range(nbox)]
+    dev = torch.device("cuda", 0)
+    inputs = []
+    for q in probs:
+        inputs.append(dict(species=torch.from_numpy(np.ascontiguousarray(q.species, np.uint8)).to(dev),
+                           mass=torch.from_numpy(q.mass).to(dev), pos=torch.from_numpy(q.pos).to(dev)))
+    accs = [torch.empty((3, q.n), dtype=torch.float64, device=dev) for q in probs]
+    boxes = [ngr.BatchBox(D=q.D, box=q.box, acc=a, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps,
+                          theta=q.theta, r_s=q.r_s, leaf_size=q.leaf_size, group_size=0, **t)
+             for q, t, a in zip(probs, inputs, accs)]
+    ctx = ngr.Context(0)
+    st = ngr.batch_build_force(ctx, boxes)          # warm-up
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ngr.batch_build_force(ctx, boxes)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_batch = float(np.median(times))
+    inter = st["interactions_pp"] + st["interactions_pn"]
+
+    def loop():
+        for q, t, a in zip(probs, inputs, accs):
+            tree = ngr.tree_build(ctx, D=q.D, box=q.box, leaf_size=q.leaf_size, **t)
+            ngr.compute_monopoles(ctx, tree)
+            ngr.tree_force(ctx, tree, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps, theta=q.theta,
+                           r_s=q.r_s, group_size=0, acc=a)
+            ngr.tree_free(ctx, tree)
+    loop()                                          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": f"{nbox} clustered boxes: n log-uniform in [2^12, 2^18], D in 1..4, clustered fraction "
+                        f"in [0, 0.8], laws of their own", "n_boxes": nbox, "n_particles": st["n_particles"],
+            "interactions": inter, "ms_per_batch": t_batch * 1e3, "boxes_per_s": nbox / t_batch,
+            "interactions_per_s": inter / t_batch, "walk_ms": st["ms_walk"], "build_ms": st["ms_build"],
+            "loop_ms": t_loop * 1e3, "loop_boxes_per_s": nbox / t_loop, "speedup_vs_loop": t_loop / t_batch,
+            "group_size": "library choice (32)"}
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -85,6 +136,7 @@ def main():
     ap.add_argument("--n", type=int, default=2 ** 24, help="particles (the benchmark workload is 2^24)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
@@ -154,6 +206,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": walk_traffic()},
     }
+    if not args.no_batched:
+        log("many-box workload: one batched call against the single-box loop")
+        out["batched"] = batched(ngr, synth)
+        log(f"batched: {out['batched']['ms_per_batch']:.1f} ms per batch, loop {out['batched']['loop_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(p, inter, args.cpu_seconds)

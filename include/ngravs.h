@@ -127,7 +127,7 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   r_cut    cut-off radius, 0 < r_cut < box / 2
  *   eps      Plummer softening, >= 0
  *   theta    opening angle, > 0
- *   group_size  sinks per walk, 16, 32 or 64 (0 means 64)
+ *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice, 32)
  */
 typedef struct {
     const double* G;
@@ -220,6 +220,55 @@ ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree,
 ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree,
                                  const ngr_force_params* fp, double* acc,
                                  ngr_force_stats* st, uint64_t* group_counts);
+
+/* ---- many boxes in one call ---- */
+
+/* One independent box of a batch. Pointers and sizes as in the single-box
+ * calls: particles (device arrays), tree parameters, force parameters (host
+ * arrays) and acc (device, 3 x n float64, written in the box's input order).
+ * force.group_size == 0 lets the library choose the box's group size. */
+typedef struct {
+    ngr_particles particles;
+    ngr_tree_params tree;
+    ngr_force_params force;
+    double* acc;
+} ngr_box;
+
+/* Filled by ngr_batch_build_force (host). Times are hipEvent milliseconds on
+ * the context's stream; ms_groups includes the ordering of the walk queue. */
+typedef struct {
+    uint64_t n_particles;
+    uint64_t n_nodes;
+    uint64_t n_groups;
+    uint64_t interactions_pp;
+    uint64_t interactions_pn;
+    double ms_build;
+    double ms_monopoles;
+    double ms_groups;
+    double ms_walk;
+} ngr_batch_stats;
+
+/*
+ * Tree build, monopoles and short-range force of nbox independent periodic
+ * boxes (sections 2, 2.2 and 2.4.1 applied to each box), done together: one
+ * check-and-key pass, one sort by (box, species, key), one level-by-level
+ * octree over all boxes, one monopole pass and one walk launch whose
+ * workgroups move between (box, sink species) segments. Boxes may differ in
+ * n, D, box side, leaf size, G, tables, r_cut, eps, theta and group size;
+ * they must share the table grid.
+ * Each box's acc and per-box counts are those of ngr_tree_build +
+ * ngr_compute_monopoles + ngr_tree_force on that box alone with the same
+ * parameters and resolved group size, bit for bit.
+ *   nbox     1..65535; all boxes together hold fewer than 2^32 - 1 particles
+ *   st       host, may be NULL
+ *   per_box  host array of nbox entries, may be NULL: each box's interaction
+ *            counts, nodes, leaves, depth, groups and resolved group size
+ *            (its times are 0)
+ * Errors: as the single-box calls (the message names the box), NGR_EINVAL for
+ * nbox out of range or mixed grids. No tree outlives the call.
+ */
+ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes,
+                                 ngr_batch_stats* st, ngr_force_stats* per_box);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,8 @@ GRIDS = {"r": GRID_R, "r2": GRID_R2, GRID_R: GRID_R, GRID_R2: GRID_R2}
 MAX_SPECIES = 6
 EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_tree_build",
             "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_free",
-            "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export"]
+            "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
+            "ngr_batch_build_force"]
 
 
 class NgravsError(RuntimeError):
@@ -55,6 +56,19 @@ class ForceStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Box(C.Structure):
+    _fields_ = [("particles", Particles), ("tree", TreeParams), ("force", ForceParams), ("acc", C.c_void_p)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("n_particles", C.c_uint64), ("n_nodes", C.c_uint64), ("n_groups", C.c_uint64),
+                ("interactions_pp", C.c_uint64), ("interactions_pn", C.c_uint64), ("ms_build", C.c_double),
+                ("ms_monopoles", C.c_double), ("ms_groups", C.c_double), ("ms_walk", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -79,6 +93,7 @@ def lib():
             "ngr_tree_export": (i32, [P] * 12),
             "ngr_monopoles_export": (i32, [P] * 4),
             "ngr_groups_export": (i32, [P, P, u32, P, P, P, P, P, P]),
+            "ngr_batch_build_force": (i32, [P, u32, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -232,3 +247,35 @@ def groups_export(ctx: Context, tree: Tree, group_size: int = 64) -> dict:
                                        *[_np(out[k]) for k in ("species", "start", "count", "lo", "hi")]),
                "groups export")
     return out
+
+
+class BatchBox:
+    """One box of a batch: device tensors species (uint8, n), mass (float64,
+    n), pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n), and
+    acc (float64, 3 x n, written); host arrays G (D x D) and tables
+    (D x D x ntab, or None); scalars as in tree_build / tree_force.
+    group_size 0 lets the library choose."""
+
+    def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
+                 leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None):
+        self.n = int(species.shape[0])
+        self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
+        self.tree = TreeParams(leaf_size)
+        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab)
+        self.acc = _dev(acc)
+        self._keep = (species, mass, pos, lattice, acc)
+
+
+def batch_build_force(ctx: Context, boxes, per_box: bool = False):
+    """ngr_batch_build_force over a list of BatchBox. Returns the batch
+    statistics as a dict, and with per_box=True also a list of per-box
+    statistics dicts."""
+    arr = (Box * len(boxes))()
+    for k, b in enumerate(boxes):
+        arr[k] = Box(b.particles, b.tree, b.force, b.acc)
+    st = BatchStats()
+    pb = (ForceStats * len(boxes))() if per_box else None
+    ctx._check(lib().ngr_batch_build_force(ctx.handle, len(boxes), arr, C.byref(st), pb), "batch build and force")
+    if per_box:
+        return st.as_dict(), [pb[k].as_dict() for k in range(len(boxes))]
+    return st.as_dict()

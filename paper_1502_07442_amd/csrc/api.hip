@@ -149,45 +149,65 @@ ngr_status guarded(ngr_context* ctx, F&& f)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-void free_tree_memory(ngr::Context& c, ngr::Tree& t)
-{
-    c.release(t.X);
-    c.release(t.mass);
-    c.release(t.perm);
-    c.release(t.keys);
-    c.release(t.level);
-    c.release(t.prefix);
-    c.release(t.parent);
-    c.release(t.first_child);
-    c.release(t.n_child);
-    c.release(t.cell);
-    c.release(t.start);
-    c.release(t.count);
-    c.release(t.mono);
-}
+void free_tree_memory(ngr::Context& c, ngr::Tree& t) { ngr::free_tree(c, t); }
 
-void check_force_params(const ngr::Tree& t, const ngr_force_params* fp, uint32_t* group_size)
+// Checks of one box's force parameters (D species, box side); returns the
+// group size (0 resolved by the caller's rule).
+uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, const std::string& where)
 {
     using ngr::fail;
-    if (!fp) fail(NGR_EINVAL, "force params are NULL");
-    if (!fp->G) fail(NGR_EINVAL, "G is NULL");
-    const uint32_t D = t.D;
-    if (fp->ntab < 2) fail(NGR_EINVAL, "ntab must be >= 2");
-    if ((uint64_t)D * fp->ntab > NGR_MAX_TABLE) fail(NGR_EINVAL, "D * ntab exceeds NGR_MAX_TABLE");
-    if (fp->grid != NGR_GRID_R && fp->grid != NGR_GRID_R2) fail(NGR_EINVAL, "grid must be NGR_GRID_R or NGR_GRID_R2");
-    if (!finite_pos(fp->r_cut)) fail(NGR_EINVAL, "r_cut must be finite and > 0");
-    if (!(fp->r_cut < 0.5 * t.box)) fail(NGR_EINVAL, "r_cut must be < box / 2");
-    if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, "eps must be finite and >= 0");
-    if (!finite_pos(fp->theta)) fail(NGR_EINVAL, "theta must be finite and > 0");
-    if (!fp->tables && !finite_pos(fp->r_s)) fail(NGR_EINVAL, "r_s must be finite and > 0 when tables is NULL");
-    uint32_t gs = fp->group_size ? fp->group_size : 64;
-    if (gs != 16 && gs != 32 && gs != 64) fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
+    if (!fp) fail(NGR_EINVAL, where + "force params are NULL");
+    if (!fp->G) fail(NGR_EINVAL, where + "G is NULL");
+    if (fp->ntab < 2) fail(NGR_EINVAL, where + "ntab must be >= 2");
+    if ((uint64_t)D * fp->ntab > NGR_MAX_TABLE) fail(NGR_EINVAL, where + "D * ntab exceeds NGR_MAX_TABLE");
+    if (fp->grid != NGR_GRID_R && fp->grid != NGR_GRID_R2) fail(NGR_EINVAL, where + "grid must be NGR_GRID_R or NGR_GRID_R2");
+    if (!finite_pos(fp->r_cut)) fail(NGR_EINVAL, where + "r_cut must be finite and > 0");
+    if (!(fp->r_cut < 0.5 * box)) fail(NGR_EINVAL, where + "r_cut must be < box / 2");
+    if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, where + "eps must be finite and >= 0");
+    if (!finite_pos(fp->theta)) fail(NGR_EINVAL, where + "theta must be finite and > 0");
+    if (!fp->tables && !finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
+    const uint32_t gs = fp->group_size;
+    if (gs != 0 && gs != 16 && gs != 32 && gs != 64) fail(NGR_EINVAL, where + "group_size must be 16, 32 or 64 (or 0)");
     for (uint32_t k = 0; k < D * D; ++k)
-        if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, "G has a non-finite entry");
+        if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, where + "G has a non-finite entry");
     if (fp->tables)
         for (uint64_t k = 0; k < (uint64_t)D * D * fp->ntab; ++k)
-            if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, "a table entry is not finite");
-    *group_size = gs;
+            if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, where + "a table entry is not finite");
+    return gs;
+}
+
+// Group size of a box when the caller leaves it to the library (0). With
+// groups of at most 32 (16) sinks evaluating 2 (4) records per lane slot,
+// 32 gave the shortest walk on the many-box workload (256 clustered boxes of
+// 2^12..2^18 particles, D 1..4: walk 41 ms at 32 against 45 ms at 16 and 64).
+uint32_t chosen_group_size(uint64_t n, uint32_t D)
+{
+    (void)n;
+    (void)D;
+    return 32;
+}
+
+void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const std::string& where, ngr::BoxIn& b)
+{
+    using ngr::fail;
+    if (!p) fail(NGR_EINVAL, where + "particles are NULL");
+    if (p->D < 1 || p->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, where + "D must be in 1..6");
+    if (!finite_pos(p->box)) fail(NGR_EINVAL, where + "box must be finite and > 0");
+    if (p->n >= (1ull << 32) - 1) fail(NGR_EINVAL, where + "n must be < 2^32 - 1");
+    const uint32_t B = tp && tp->leaf_size ? tp->leaf_size : 16;
+    if (B > 64) fail(NGR_EINVAL, where + "leaf_size must be in 1..64");
+    if (p->n) {
+        if (!p->species || !p->mass) fail(NGR_EINVAL, where + "species or mass is NULL");
+        if ((p->pos == nullptr) == (p->lattice == nullptr)) fail(NGR_EINVAL, where + "exactly one of pos and lattice must be set");
+    }
+    b.n = p->n;
+    b.D = p->D;
+    b.box = p->box;
+    b.leaf_size = B;
+    b.pos = p->pos;
+    b.lattice = p->lattice;
+    b.species = p->species;
+    b.mass = p->mass;
 }
 
 ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
@@ -197,12 +217,12 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         using ngr::fail;
         if (!tree) fail(NGR_EINVAL, "tree is NULL");
         if (!tree->has_monopoles) fail(NGR_ESTATE, "ngr_compute_monopoles must precede ngr_tree_force");
-        uint32_t gs = 64;
-        check_force_params(*tree, fp, &gs);
+        uint32_t gs = check_force_params(tree->D, tree->box, fp, "");
+        if (!gs) gs = chosen_group_size(tree->n, tree->D);
         if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
         ngr::Context& c = *ctx;
         ngr::Groups g;
-        ngr::Law law;
+        std::vector<ngr::Law> laws(1);
         ngr::WalkOut wo;
         uint64_t* gc = nullptr;
         hipEvent_t e0, e1;
@@ -210,16 +230,15 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         ngr::hip_check(hipEventCreate(&e1), "hipEventCreate", __FILE__, __LINE__);
         try {
             ngr::hip_check(hipEventRecord(e0, c.stream), "hipEventRecord", __FILE__, __LINE__);
-            ngr::make_groups(c, *tree, gs, g);
+            ngr::make_groups(c, *tree, std::vector<uint32_t>{gs}, g);
             ngr::hip_check(hipEventRecord(e1, c.stream), "hipEventRecord", __FILE__, __LINE__);
-            ngr::upload_law(c, *fp, tree->D, law);
+            ngr::make_law(*fp, tree->D, laws[0]);
             if (group_counts_host && g.ng) gc = static_cast<uint64_t*>(c.alloc(g.ng * 4 * sizeof(uint64_t)));
-            ngr::walk_force(c, *tree, g, law, acc, gc, wo);
+            ngr::walk_force(c, *tree, g, laws, std::vector<double*>{acc}, gc, wo);
             if (gc) c.to_host(group_counts_host, gc, g.ng * 4 * sizeof(uint64_t));
             c.sync();
         } catch (...) {
             c.release(gc);
-            c.release(law.table);
             g.free(c);
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
@@ -238,11 +257,10 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             st->n_groups = g.ng;
             st->group_size = gs;
             st->depth = tree->depth;
-            st->ms_groups = ms_groups;
+            st->ms_groups = ms_groups + wo.ms_order;
             st->ms_walk = wo.ms_walk;
         }
         c.release(gc);
-        c.release(law.table);
         g.free(c);
     });
 }
@@ -297,18 +315,11 @@ NGR_API ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p, cons
     return guarded(ctx, [&] {
         using ngr::fail;
         if (!p || !out) fail(NGR_EINVAL, "particles or out is NULL");
-        if (p->D < 1 || p->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, "D must be in 1..6");
-        if (!finite_pos(p->box)) fail(NGR_EINVAL, "box must be finite and > 0");
-        if (p->n >= (1ull << 32) - 1) fail(NGR_EINVAL, "n must be < 2^32 - 1");
-        uint32_t B = tp && tp->leaf_size ? tp->leaf_size : 16;
-        if (B > 64) fail(NGR_EINVAL, "leaf_size must be in 1..64");
-        if (p->n) {
-            if (!p->species || !p->mass) fail(NGR_EINVAL, "species or mass is NULL");
-            if ((p->pos == nullptr) == (p->lattice == nullptr)) fail(NGR_EINVAL, "exactly one of pos and lattice must be set");
-        }
+        std::vector<ngr::BoxIn> boxes(1);
+        check_particles(p, tp, "", boxes[0]);
         ngr_tree* t = new ngr_tree();
         try {
-            ngr::build_tree(*ctx, *p, B, *t);
+            ngr::build_forest(*ctx, boxes, *t);
             ctx->sync();
         } catch (...) {
             try {
@@ -430,11 +441,11 @@ NGR_API ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree, uin
 {
     return guarded(ctx, [&] {
         if (!tree || !n_groups) ngr::fail(NGR_EINVAL, "tree or n_groups is NULL");
-        uint32_t gs = group_size ? group_size : 64;
+        uint32_t gs = group_size ? group_size : chosen_group_size(tree->n, tree->D);
         if (gs != 16 && gs != 32 && gs != 64) ngr::fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
         ngr::Groups g;
         try {
-            ngr::make_groups(*ctx, *tree, gs, g);
+            ngr::make_groups(*ctx, *tree, std::vector<uint32_t>{gs}, g);
             *n_groups = g.ng;
             if (species) {
                 for (uint32_t a = 0; a < tree->D; ++a)
@@ -451,5 +462,92 @@ NGR_API ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree, uin
         }
         g.free(*ctx);
         ctx->sync();
+    });
+}
+
+NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes, ngr_batch_stats* st,
+                                         ngr_force_stats* per_box)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!boxes) fail(NGR_EINVAL, "boxes is NULL");
+        if (nbox == 0 || nbox > 65535) fail(NGR_EINVAL, "nbox must be in 1..65535");
+        std::vector<ngr::BoxIn> in(nbox);
+        std::vector<uint32_t> gs(nbox);
+        std::vector<ngr::Law> laws(nbox);
+        std::vector<double*> acc(nbox);
+        for (uint32_t k = 0; k < nbox; ++k) {
+            const std::string where = "box " + std::to_string(k) + ": ";
+            check_particles(&boxes[k].particles, &boxes[k].tree, where, in[k]);
+            gs[k] = check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
+            if (!gs[k]) gs[k] = chosen_group_size(in[k].n, in[k].D);
+            if (!boxes[k].acc && in[k].n) fail(NGR_EINVAL, where + "acc is NULL");
+            if (boxes[k].force.grid != boxes[0].force.grid) fail(NGR_EINVAL, where + "the boxes must share the table grid");
+            acc[k] = boxes[k].acc;
+        }
+        for (uint32_t k = 0; k < nbox; ++k) ngr::make_law(boxes[k].force, in[k].D, laws[k]);
+        ngr::Context& c = *ctx;
+        ngr::Tree t;
+        ngr::Groups g;
+        ngr::WalkOut wo;
+        std::vector<uint64_t> bnodes, bleaves;
+        std::vector<uint32_t> bdepth;
+        hipEvent_t ev[4];
+        for (auto& e : ev) ngr::hip_check(hipEventCreate(&e), "hipEventCreate", __FILE__, __LINE__);
+        auto destroy = [&] {
+            for (auto& e : ev) (void)hipEventDestroy(e);
+        };
+        try {
+            ngr::hip_check(hipEventRecord(ev[0], c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::build_forest(c, in, t);
+            ngr::hip_check(hipEventRecord(ev[1], c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::compute_monopoles(c, t);
+            ngr::hip_check(hipEventRecord(ev[2], c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::make_groups(c, t, gs, g);
+            ngr::hip_check(hipEventRecord(ev[3], c.stream), "hipEventRecord", __FILE__, __LINE__);
+            ngr::walk_force(c, t, g, laws, acc, nullptr, wo);
+            if (per_box) ngr::box_node_counts(c, t, bnodes, bleaves, bdepth);
+            c.sync();
+        } catch (...) {
+            try {
+                ngr::free_tree(c, t);
+                g.free(c);
+            } catch (...) {
+            }
+            destroy();
+            throw;
+        }
+        float ms[3] = {0, 0, 0};
+        for (int i = 0; i < 3; ++i)
+            ngr::hip_check(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]), "hipEventElapsedTime", __FILE__, __LINE__);
+        destroy();
+        if (st) {
+            std::memset(st, 0, sizeof *st);
+            st->n_particles = t.n;
+            st->n_nodes = t.nn;
+            st->n_groups = g.ng;
+            st->interactions_pp = wo.pp;
+            st->interactions_pn = wo.pn;
+            st->ms_build = ms[0];
+            st->ms_monopoles = ms[1];
+            st->ms_groups = ms[2] + wo.ms_order;
+            st->ms_walk = wo.ms_walk;
+        }
+        if (per_box) {
+            const uint32_t D = t.D;
+            for (uint32_t k = 0; k < nbox; ++k) {
+                ngr_force_stats& b = per_box[k];
+                std::memset(&b, 0, sizeof b);
+                b.interactions_pp = wo.box_pp[k];
+                b.interactions_pn = wo.box_pn[k];
+                b.n_nodes = bnodes[k];
+                b.n_leaves = bleaves[k];
+                b.n_groups = g.first.empty() ? 0 : g.first[(size_t)(k + 1) * D] - g.first[(size_t)k * D];
+                b.group_size = gs[k];
+                b.depth = bdepth[k];
+            }
+        }
+        ngr::free_tree(c, t);
+        g.free(c);
     });
 }

@@ -17,50 +17,16 @@ namespace {
 
 enum : uint32_t { kBadSpecies = 1, kBadMass = 2, kBadPos = 4 };
 
-// One thread per particle: flags bad species ids, masses and positions, and
-// counts each species (the counts give the species segments of the sort).
-__global__ void check_inputs(uint64_t n, uint32_t D, const uint8_t* __restrict__ species,
-                             const double* __restrict__ mass, const double* __restrict__ pos,
-                             uint32_t* __restrict__ flags, unsigned long long* __restrict__ counts)
-{
-    // grid-stride over a bounded grid: one global atomic per workgroup and
-    // species (same-address atomics from the whole chip are slow)
-    __shared__ unsigned int local[NGR_MAX_SPECIES];
-    __shared__ unsigned int local_bad;
-    if (threadIdx.x < NGR_MAX_SPECIES) local[threadIdx.x] = 0;
-    if (threadIdx.x == 0) local_bad = 0;
-    __syncthreads();
-    uint32_t bad = 0;
-    uint32_t mine[NGR_MAX_SPECIES] = {0, 0, 0, 0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t s = species[i];
-        const double m = mass[i];
-        if (s >= D) bad |= kBadSpecies;
-#pragma unroll
-        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) mine[b] += s == b ? 1u : 0u;
-        if (!(m >= 0.0) || !isfinite(m)) bad |= kBadMass;
-        if (pos && !(isfinite(pos[i]) && isfinite(pos[n + i]) && isfinite(pos[2 * n + i]))) bad |= kBadPos;
-    }
-    for (uint32_t b = 0; b < D; ++b)
-        if (mine[b]) atomicAdd(&local[b], mine[b]);
-    if (bad) atomicOr(&local_bad, bad);
-    __syncthreads();
-    if (threadIdx.x < D && local[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)local[threadIdx.x]);
-    if (threadIdx.x == 0 && local_bad) atomicOr(flags, local_bad);
-}
-
-// Positions to 64-bit lattice coordinates, X = floor(u * 2^64) with
-// u = x / box taken modulo 1 (the box is periodic).
-__global__ void to_lattice(uint64_t n3, const double* __restrict__ x, double box, uint64_t* __restrict__ X)
-{
-    uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n3) return;
-    double u = x[k] / box;
-    u = u - floor(u);
-    if (u >= 1.0) u = 0.0;
-    X[k] = (uint64_t)(u * 18446744073709551616.0);
-}
+// One box of a build as the device sees it.
+struct BoxInDev {
+    const double* pos;
+    const uint64_t* lattice;
+    const uint8_t* species;
+    const double* mass;
+    uint64_t n, off;          // particles and first index in the concatenated arrays
+    double box;
+    uint32_t D, leaf;
+};
 
 // Spread the low 20 bits of v so that bit i lands on bit 3i.
 __device__ inline uint64_t spread3(uint64_t v)
@@ -74,16 +40,82 @@ __device__ inline uint64_t spread3(uint64_t v)
     return v;
 }
 
-// Key = species << 60 | Morton interleave of the top 20 bits of each axis,
-// x the most significant bit of each 3-bit digit; value = input index.
-__global__ void make_keys(uint64_t n, const uint64_t* __restrict__ X, const uint8_t* __restrict__ species,
-                          uint64_t* __restrict__ keys, uint32_t* __restrict__ idx)
+// One thread per particle of box blockIdx.y (grid-stride over a bounded
+// grid): checks the species id, mass and position; converts the position to
+// the 64-bit lattice, X = floor(u * 2^64) with u = x / box taken modulo 1 (the
+// box is periodic); forms the key species << 60 | Morton interleave of the top
+// 20 bits of each axis (x the most significant bit of each 3-bit digit); and
+// counts each species of the box (the counts give its species segments).
+// Per-box flags and counts take one global atomic per workgroup.
+__global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64_t* __restrict__ Xin,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, double* __restrict__ mass_cat,
+                       uint16_t* __restrict__ boxid, uint32_t* __restrict__ flags,
+                       unsigned long long* __restrict__ counts)
 {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t m = (spread3(X[i] >> 44) << 2) | (spread3(X[n + i] >> 44) << 1) | spread3(X[2 * n + i] >> 44);
-    keys[i] = ((uint64_t)species[i] << kKeyBits) | m;
-    idx[i] = (uint32_t)i;
+    __shared__ unsigned int local[NGR_MAX_SPECIES];
+    __shared__ unsigned int local_bad;
+    const uint32_t k = blockIdx.y;
+    const BoxInDev B = boxes[k];
+    if (threadIdx.x < NGR_MAX_SPECIES) local[threadIdx.x] = 0;
+    if (threadIdx.x == 0) local_bad = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    uint32_t mine[NGR_MAX_SPECIES] = {0, 0, 0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.n; i += stride) {
+        const uint32_t s = B.species[i];
+        const double m = B.mass[i];
+        if (s >= B.D) bad |= kBadSpecies;
+#pragma unroll
+        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) mine[b] += s == b ? 1u : 0u;
+        if (!(m >= 0.0) || !isfinite(m)) bad |= kBadMass;
+        uint64_t X[3];
+        if (B.pos) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double x = B.pos[a * B.n + i];
+                if (!isfinite(x)) bad |= kBadPos;
+                double u = x / B.box;
+                u = u - floor(u);
+                if (!(u < 1.0)) u = 0.0;
+                X[a] = (uint64_t)(u * 18446744073709551616.0);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) X[a] = B.lattice[a * B.n + i];
+        }
+        const uint64_t g = B.off + i;
+        Xin[g] = X[0];
+        Xin[ntot + g] = X[1];
+        Xin[2 * ntot + g] = X[2];
+        const uint64_t mo = (spread3(X[0] >> 44) << 2) | (spread3(X[1] >> 44) << 1) | spread3(X[2] >> 44);
+        keys[g] = ((uint64_t)(s & 0xfu) << kKeyBits) | mo;
+        idx[g] = (uint32_t)g;
+        mass_cat[g] = m;
+        if (boxid) boxid[g] = (uint16_t)k;
+    }
+    for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b)
+        if (mine[b]) atomicAdd(&local[b], mine[b]);
+    if (bad) atomicOr(&local_bad, bad);
+    __syncthreads();
+    if (threadIdx.x < NGR_MAX_SPECIES && local[threadIdx.x])
+        atomicAdd(&counts[(uint64_t)k * NGR_MAX_SPECIES + threadIdx.x], (unsigned long long)local[threadIdx.x]);
+    if (threadIdx.x == 0 && local_bad) atomicOr(&flags[k], local_bad);
+}
+
+// Sort key of the box pass: the box of each element, in the current order.
+__global__ void box_keys(uint64_t n, const uint32_t* __restrict__ idx, const uint16_t* __restrict__ boxid,
+                         uint64_t* __restrict__ kb)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) kb[i] = boxid[idx[i]];
+}
+
+__global__ void gather_keys(uint64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ kin,
+                            uint64_t* __restrict__ kout)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) kout[i] = kin[perm[i]];
 }
 
 // The single reordering of the particle data into sorted order.
@@ -100,20 +132,24 @@ __global__ void gather_particles(uint64_t n, const uint32_t* __restrict__ perm, 
     mout[i] = min[p];
 }
 
-__global__ void init_root(uint32_t D, const uint64_t* __restrict__ seg_dev, uint8_t* level, uint64_t* prefix,
-                          int32_t* parent, int32_t* first_child, uint8_t* n_child, uint4* cell,
-                          uint32_t* start, uint32_t* count)
+// The roots: node k is box k's root, holding its species segments.
+__global__ void init_roots(uint32_t nbox, uint32_t D, const uint64_t* __restrict__ bseg, uint8_t* level,
+                           uint64_t* prefix, int32_t* parent, int32_t* first_child, uint8_t* n_child, uint4* cell,
+                           uint32_t* start, uint32_t* count, uint32_t* node_box)
 {
-    if (threadIdx.x != 0) return;
-    level[0] = 0;
-    prefix[0] = 0;
-    parent[0] = -1;
-    first_child[0] = -1;
-    n_child[0] = 0;
-    cell[0] = make_uint4(0, 0, 0, 0);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nbox) return;
+    level[k] = 0;
+    prefix[k] = 0;
+    parent[k] = -1;
+    first_child[k] = -1;
+    n_child[k] = 0;
+    cell[k] = make_uint4(0, 0, 0, 0);
+    node_box[k] = k;
+    const uint64_t* sg = bseg + (uint64_t)k * (NGR_MAX_SPECIES + 1);
     for (uint32_t b = 0; b < D; ++b) {
-        start[b] = (uint32_t)seg_dev[b];
-        count[b] = (uint32_t)(seg_dev[b + 1] - seg_dev[b]);
+        start[(uint64_t)k * D + b] = (uint32_t)sg[b];
+        count[(uint64_t)k * D + b] = (uint32_t)(sg[b + 1] - sg[b]);
     }
 }
 
@@ -131,7 +167,8 @@ __device__ inline uint64_t lower_bound(const uint64_t* __restrict__ keys, uint64
 // species are found by binary search inside the node's species range (the
 // range is sorted by key). Nodes holding more than B particles below level 20
 // split; a non-empty octant becomes a child.
-__global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl, uint32_t D, uint32_t B,
+__global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl, uint32_t D,
+                            const uint32_t* __restrict__ leaf_size, const uint32_t* __restrict__ node_box,
                             const uint64_t* __restrict__ keys, const uint64_t* __restrict__ prefix,
                             const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
                             uint32_t* __restrict__ cstart, uint32_t* __restrict__ ccount,
@@ -141,6 +178,7 @@ __global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl
     if (t >= n_level * 8) return;
     uint64_t p = level_begin + t / 8;
     uint32_t o = (uint32_t)(t % 8);
+    const uint32_t B = leaf_size[node_box[p]];
     uint64_t total = 0;
     for (uint32_t b = 0; b < D; ++b) total += count[p * D + b];
     if (total <= B || lvl >= (uint32_t)kLevels) {
@@ -169,7 +207,8 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
                               uint32_t D, const uint32_t* __restrict__ flags, const uint32_t* __restrict__ offs,
                               const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ ccount,
                               uint8_t* level, uint64_t* prefix, int32_t* parent, int32_t* first_child,
-                              uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count)
+                              uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count,
+                              uint32_t* node_box)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_level * 8) return;
@@ -187,6 +226,7 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
     level[c] = (uint8_t)(lvl + 1);
     prefix[c] = prefix[p] * 8 + o;
     parent[c] = (int32_t)p;
+    node_box[c] = node_box[p];
     first_child[c] = -1;
     n_child[c] = 0;
     uint4 pc = cell[p];
@@ -212,6 +252,19 @@ __global__ void count_leaves(uint64_t nn, const uint8_t* __restrict__ n_child, u
     if (c) atomicAdd(&part, c);
     __syncthreads();
     if (threadIdx.x == 0 && part) atomicAdd(out, part);
+}
+
+// Nodes, leaves and deepest level of every box (for per-box statistics).
+__global__ void node_counts(uint64_t nn, const uint32_t* __restrict__ node_box, const uint8_t* __restrict__ n_child,
+                            const uint8_t* __restrict__ level, unsigned long long* __restrict__ nodes,
+                            unsigned long long* __restrict__ leaves, uint32_t* __restrict__ depth)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const uint32_t k = node_box[i];
+    atomicAdd(&nodes[k], 1ull);
+    if (n_child[i] == 0) atomicAdd(&leaves[k], 1ull);
+    atomicMax(&depth[k], (uint32_t)level[i]);
 }
 
 // Monopoles of one level (section 2.2), one thread per (node, species b).
@@ -285,83 +338,173 @@ void grow_nodes(Context& ctx, Tree& t, uint64_t need)
     grow(ctx, t.cell, used, cap);
     grow(ctx, t.start, used * t.D, cap * t.D);
     grow(ctx, t.count, used * t.D, cap * t.D);
+    grow(ctx, t.node_box, used, cap);
     t.cap = cap;
 }
 
 }  // namespace
 
-void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& t)
+void free_tree(Context& ctx, Tree& t)
 {
-    const uint64_t n = p.n;
-    const uint32_t D = p.D;
+    for (void* q : {(void*)t.X, (void*)t.mass, (void*)t.perm, (void*)t.keys, (void*)t.level, (void*)t.prefix,
+                    (void*)t.parent, (void*)t.first_child, (void*)t.n_child, (void*)t.cell, (void*)t.start,
+                    (void*)t.count, (void*)t.node_box, (void*)t.mono, (void*)t.boff_dev})
+        ctx.release(q);
+    t.X = nullptr;
+    t.mass = nullptr;
+    t.perm = nullptr;
+    t.keys = nullptr;
+    t.level = nullptr;
+    t.prefix = nullptr;
+    t.parent = nullptr;
+    t.first_child = nullptr;
+    t.n_child = nullptr;
+    t.cell = nullptr;
+    t.start = nullptr;
+    t.count = nullptr;
+    t.node_box = nullptr;
+    t.mono = nullptr;
+    t.boff_dev = nullptr;
+}
+
+void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
+{
+    const uint32_t nbox = (uint32_t)boxes.size();
+    if (nbox == 0 || nbox > 65535) fail(NGR_EINVAL, "the number of boxes must be in 1..65535");
+    uint32_t D = 0;
+    uint64_t n = 0;
+    t.nbox = nbox;
+    t.boff.assign(nbox + 1, 0);
+    t.bD.resize(nbox);
+    t.bbox.resize(nbox);
+    t.bleaf.resize(nbox);
+    std::vector<BoxInDev> bin(nbox);
+    for (uint32_t k = 0; k < nbox; ++k) {
+        const BoxIn& b = boxes[k];
+        D = std::max(D, b.D);
+        t.boff[k] = n;
+        t.bD[k] = b.D;
+        t.bbox[k] = b.box;
+        t.bleaf[k] = b.leaf_size;
+        bin[k] = BoxInDev{b.pos, b.lattice, b.species, b.mass, b.n, n, b.box, b.D, b.leaf_size};
+        n += b.n;
+    }
+    t.boff[nbox] = n;
+    if (n >= (1ull << 32) - 1) fail(NGR_EINVAL, "the boxes hold 2^32 - 1 or more particles");
     t.n = n;
     t.D = D;
-    t.box = p.box;
-    t.leaf_size = leaf_size;
+    t.box = t.bbox[0];
+    t.leaf_size = t.bleaf[0];
 
-    // ---- input checks and species counts (the one synchronisation before the build)
-    ctx.stage("build: input checks");
-    uint32_t* flags = static_cast<uint32_t*>(ctx.alloc((1 + NGR_MAX_SPECIES) * sizeof(uint64_t)));
-    unsigned long long* counts = reinterpret_cast<unsigned long long*>(flags + 2);
-    HIP_CHECK(hipMemsetAsync(flags, 0, (1 + NGR_MAX_SPECIES) * sizeof(uint64_t), ctx.stream));
+    // ---- input checks, lattice, keys and species counts (one synchronisation)
+    ctx.stage("build: input checks and keys");
+    const uint64_t n1 = std::max<uint64_t>(n, 1);
+    t.X = static_cast<uint64_t*>(ctx.alloc(3 * n1 * sizeof(uint64_t)));
+    t.mass = static_cast<double*>(ctx.alloc(n1 * sizeof(double)));
+    t.perm = static_cast<uint32_t*>(ctx.alloc(n1 * sizeof(uint32_t)));
+    t.keys = static_cast<uint64_t*>(ctx.alloc(n1 * sizeof(uint64_t)));
+    t.boff_dev = static_cast<uint64_t*>(ctx.alloc((nbox + 1) * sizeof(uint64_t)));
+    ctx.to_device(t.boff_dev, t.boff.data(), (nbox + 1) * sizeof(uint64_t));
+    std::vector<uint64_t> counts((size_t)nbox * NGR_MAX_SPECIES, 0);
+    std::vector<uint32_t> flags(nbox, 0);
+    uint64_t* Xin = nullptr;
+    double* mass_cat = nullptr;
+    uint16_t* boxid = nullptr;
     if (n) {
-        hipLaunchKernelGGL(check_inputs, dim3((unsigned)std::min<uint64_t>(blocks_for(n, 256), 4u * ctx.num_cu)), dim3(256), 0,
-                           ctx.stream, n, D, p.species, p.mass, p.pos, flags, counts);
-        LAUNCH_CHECK("check_inputs");
+        Xin = static_cast<uint64_t*>(ctx.alloc(3 * n * sizeof(uint64_t)));
+        mass_cat = static_cast<double*>(ctx.alloc(n * sizeof(double)));
+        if (nbox > 1) boxid = static_cast<uint16_t*>(ctx.alloc(n * sizeof(uint16_t)));
+        BoxInDev* bin_dev = static_cast<BoxInDev*>(ctx.alloc(nbox * sizeof(BoxInDev)));
+        uint32_t* flags_dev = static_cast<uint32_t*>(ctx.alloc(nbox * sizeof(uint32_t)));
+        unsigned long long* counts_dev =
+            static_cast<unsigned long long*>(ctx.alloc((size_t)nbox * NGR_MAX_SPECIES * sizeof(uint64_t)));
+        ctx.to_device(bin_dev, bin.data(), nbox * sizeof(BoxInDev));
+        HIP_CHECK(hipMemsetAsync(flags_dev, 0, nbox * sizeof(uint32_t), ctx.stream));
+        HIP_CHECK(hipMemsetAsync(counts_dev, 0, (size_t)nbox * NGR_MAX_SPECIES * sizeof(uint64_t), ctx.stream));
+        uint64_t nmax = 0;
+        for (const BoxIn& b : boxes) nmax = std::max(nmax, b.n);
+        // about four workgroups per CU over all boxes, at least one per box
+        const uint64_t per_box = std::max<uint64_t>(1, (4ull * ctx.num_cu + nbox - 1) / nbox);
+        const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(nmax, 256), per_box));
+        hipLaunchKernelGGL(ingest, dim3(gx, nbox), dim3(256), 0, ctx.stream, bin_dev, n, Xin, t.keys, t.perm, mass_cat,
+                           boxid, flags_dev, counts_dev);
+        LAUNCH_CHECK("ingest");
+        ctx.to_host(flags.data(), flags_dev, nbox * sizeof(uint32_t));
+        ctx.to_host(counts.data(), counts_dev, (size_t)nbox * NGR_MAX_SPECIES * sizeof(uint64_t));
+        ctx.release(bin_dev);
+        ctx.release(flags_dev);
+        ctx.release(counts_dev);
     }
-    uint64_t host[1 + NGR_MAX_SPECIES];
-    ctx.read_words(host, flags, 1 + NGR_MAX_SPECIES);
-    ctx.release(flags);
-    uint32_t bad = (uint32_t)(host[0] & 0xffffffffu);
-    if (bad & kBadSpecies) fail(NGR_EINVAL, "a species id is >= D");
-    if (bad & kBadMass) fail(NGR_EINVAL, "a mass is negative or not finite");
-    if (bad & kBadPos) fail(NGR_EINVAL, "a position is not finite");
-    t.seg[0] = 0;
-    for (uint32_t b = 0; b < D; ++b) t.seg[b + 1] = t.seg[b] + host[1 + b];
-    for (uint32_t b = D; b < NGR_MAX_SPECIES; ++b) t.seg[b + 1] = t.seg[D];
+    for (uint32_t k = 0; k < nbox; ++k) {
+        if (!flags[k]) continue;
+        const std::string where = nbox > 1 ? "box " + std::to_string(k) + ": " : "";
+        ctx.release(Xin);
+        ctx.release(mass_cat);
+        ctx.release(boxid);
+        if (flags[k] & kBadSpecies) fail(NGR_EINVAL, where + "a species id is >= D");
+        if (flags[k] & kBadMass) fail(NGR_EINVAL, where + "a mass is negative or not finite");
+        fail(NGR_EINVAL, where + "a position is not finite");
+    }
+    t.bseg.assign((size_t)nbox * (NGR_MAX_SPECIES + 1), 0);
+    for (uint32_t k = 0; k < nbox; ++k) {
+        uint64_t* sg = &t.bseg[(size_t)k * (NGR_MAX_SPECIES + 1)];
+        sg[0] = t.boff[k];
+        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b)
+            sg[b + 1] = sg[b] + (b < t.bD[k] ? counts[(size_t)k * NGR_MAX_SPECIES + b] : 0);
+    }
+    for (uint32_t b = 0; b <= NGR_MAX_SPECIES; ++b) t.seg[b] = t.bseg[b] - t.boff[0];
 
-    // ---- lattice, keys, sort, gather
-    ctx.stage("build: keys and sort");
-    t.X = static_cast<uint64_t*>(ctx.alloc(3 * std::max<uint64_t>(n, 1) * sizeof(uint64_t)));
-    t.mass = static_cast<double*>(ctx.alloc(std::max<uint64_t>(n, 1) * sizeof(double)));
-    t.perm = static_cast<uint32_t*>(ctx.alloc(std::max<uint64_t>(n, 1) * sizeof(uint32_t)));
-    t.keys = static_cast<uint64_t*>(ctx.alloc(std::max<uint64_t>(n, 1) * sizeof(uint64_t)));
+    // ---- sort by (box, species, key) and the one reordering
+    ctx.stage("build: sort");
     if (n) {
-        uint64_t* Xin = static_cast<uint64_t*>(ctx.alloc(3 * n * sizeof(uint64_t)));
-        if (p.pos) {
-            hipLaunchKernelGGL(to_lattice, dim3(blocks_for(3 * n, 256)), dim3(256), 0, ctx.stream, 3 * n, p.pos, p.box, Xin);
-            LAUNCH_CHECK("to_lattice");
-        } else {
-            HIP_CHECK(hipMemcpyAsync(Xin, p.lattice, 3 * n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx.stream));
-        }
         uint64_t* ktmp = static_cast<uint64_t*>(ctx.alloc(n * sizeof(uint64_t)));
         uint32_t* vtmp = static_cast<uint32_t*>(ctx.alloc(n * sizeof(uint32_t)));
-        hipLaunchKernelGGL(make_keys, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, Xin, p.species, t.keys, t.perm);
-        LAUNCH_CHECK("make_keys");
+        uint64_t* keys0 = nullptr;
+        if (nbox > 1) {
+            keys0 = static_cast<uint64_t*>(ctx.alloc(n * sizeof(uint64_t)));
+            HIP_CHECK(hipMemcpyAsync(keys0, t.keys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx.stream));
+        }
         radix_sort_pairs(ctx, t.keys, t.perm, ktmp, vtmp, n, 64);
-        hipLaunchKernelGGL(gather_particles, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, Xin, p.mass, t.X, t.mass);
+        if (nbox > 1) {
+            // stable by box last: within a box the key order (ties in input order) stays
+            uint64_t* kb = static_cast<uint64_t*>(ctx.alloc(n * sizeof(uint64_t)));
+            hipLaunchKernelGGL(box_keys, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, boxid, kb);
+            LAUNCH_CHECK("box_keys");
+            const int bits = nbox <= 256 ? 8 : 16;
+            radix_sort_pairs(ctx, kb, t.perm, ktmp, vtmp, n, bits);
+            hipLaunchKernelGGL(gather_keys, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, keys0, t.keys);
+            LAUNCH_CHECK("gather_keys");
+            ctx.release(kb);
+            ctx.release(keys0);
+        }
+        hipLaunchKernelGGL(gather_particles, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, Xin, mass_cat,
+                           t.X, t.mass);
         LAUNCH_CHECK("gather_particles");
         ctx.release(ktmp);
         ctx.release(vtmp);
         ctx.release(Xin);
+        ctx.release(mass_cat);
+        ctx.release(boxid);
     }
 
-    // ---- breadth-first octree
+    // ---- breadth-first octree over all boxes, level by level
     ctx.stage("build: octree");
     t.nn = 0;
     t.cap = 0;
-    grow_nodes(ctx, t, std::max<uint64_t>(1024, n / 2 + 1));
+    grow_nodes(ctx, t, std::max<uint64_t>(1024 + nbox, n / 2 + nbox + 1));
+    uint32_t* leaf_dev = static_cast<uint32_t*>(ctx.alloc(nbox * sizeof(uint32_t)));
+    ctx.to_device(leaf_dev, t.bleaf.data(), nbox * sizeof(uint32_t));
     {
-        uint64_t* seg_dev = static_cast<uint64_t*>(ctx.alloc((NGR_MAX_SPECIES + 1) * sizeof(uint64_t)));
-        ctx.write_words(seg_dev, t.seg, NGR_MAX_SPECIES + 1);
-        hipLaunchKernelGGL(init_root, dim3(1), dim3(64), 0, ctx.stream, D, seg_dev, t.level, t.prefix, t.parent, t.first_child, t.n_child,
-                                          t.cell, t.start, t.count);
-        LAUNCH_CHECK("init_root");
-        ctx.release(seg_dev);
+        uint64_t* bseg_dev = static_cast<uint64_t*>(ctx.alloc(t.bseg.size() * sizeof(uint64_t)));
+        ctx.to_device(bseg_dev, t.bseg.data(), t.bseg.size() * sizeof(uint64_t));
+        hipLaunchKernelGGL(init_roots, dim3(blocks_for(nbox, 64)), dim3(64), 0, ctx.stream, nbox, D, bseg_dev, t.level,
+                           t.prefix, t.parent, t.first_child, t.n_child, t.cell, t.start, t.count, t.node_box);
+        LAUNCH_CHECK("init_roots");
+        ctx.release(bseg_dev);
     }
-    t.nn = 1;
+    t.nn = nbox;
     t.level_start.assign(1, 0);
-    t.level_start.push_back(1);
+    t.level_start.push_back(nbox);
     unsigned long long* leaves = static_cast<unsigned long long*>(ctx.alloc(2 * sizeof(unsigned long long)));
     uint32_t* total_dev = reinterpret_cast<uint32_t*>(leaves + 1);
     HIP_CHECK(hipMemsetAsync(leaves, 0, 2 * sizeof(unsigned long long), ctx.stream));
@@ -375,8 +518,8 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
         uint32_t* offs = fl + slots;
         uint32_t* cst = static_cast<uint32_t*>(ctx.alloc(slots * D * sizeof(uint32_t) * 2));
         uint32_t* ccn = cst + slots * D;
-        hipLaunchKernelGGL(split_level, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, lvl, D, leaf_size, t.keys, t.prefix,
-                                                                    t.start, t.count, cst, ccn, fl);
+        hipLaunchKernelGGL(split_level, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, lvl, D, leaf_dev,
+                           t.node_box, t.keys, t.prefix, t.start, t.count, cst, ccn, fl);
         LAUNCH_CHECK("split_level");
         scan_exclusive(ctx, fl, offs, slots, total_dev);
         uint64_t next_word = 0;
@@ -384,8 +527,9 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
         const uint32_t next = (uint32_t)(next_word & 0xffffffffu);
         uint64_t nb = t.level_start[lvl + 1];
         grow_nodes(ctx, t, nb + next);
-        hipLaunchKernelGGL(emit_children, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, nb, lvl, D, fl, offs, cst, ccn, t.level, t.prefix, t.parent, t.first_child, t.n_child,
-            t.cell, t.start, t.count);
+        hipLaunchKernelGGL(emit_children, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, nb, lvl, D, fl,
+                           offs, cst, ccn, t.level, t.prefix, t.parent, t.first_child, t.n_child, t.cell, t.start,
+                           t.count, t.node_box);
         LAUNCH_CHECK("emit_children");
         ctx.release(fl);
         ctx.release(cst);
@@ -400,7 +544,31 @@ void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& 
     uint64_t nleaves = 0;
     ctx.read_words(&nleaves, leaves, 1);
     ctx.release(leaves);
+    ctx.release(leaf_dev);
     t.n_leaves = nleaves;
+}
+
+void box_node_counts(Context& ctx, const Tree& t, std::vector<uint64_t>& nodes, std::vector<uint64_t>& leaves,
+                     std::vector<uint32_t>& depth)
+{
+    const uint32_t nbox = t.nbox;
+    nodes.assign(nbox, 0);
+    leaves.assign(nbox, 0);
+    depth.assign(nbox, 0);
+    unsigned char* buf = static_cast<unsigned char*>(ctx.alloc(nbox * (2 * sizeof(uint64_t) + sizeof(uint32_t))));
+    unsigned long long* nd = reinterpret_cast<unsigned long long*>(buf);
+    unsigned long long* lf = nd + nbox;
+    uint32_t* dp = reinterpret_cast<uint32_t*>(lf + nbox);
+    HIP_CHECK(hipMemsetAsync(buf, 0, nbox * (2 * sizeof(uint64_t) + sizeof(uint32_t)), ctx.stream));
+    if (t.nn) {
+        hipLaunchKernelGGL(node_counts, dim3(blocks_for(t.nn, 256)), dim3(256), 0, ctx.stream, t.nn, t.node_box, t.n_child,
+                           t.level, nd, lf, dp);
+        LAUNCH_CHECK("node_counts");
+    }
+    ctx.to_host(nodes.data(), nd, nbox * sizeof(uint64_t));
+    ctx.to_host(leaves.data(), lf, nbox * sizeof(uint64_t));
+    ctx.to_host(depth.data(), dp, nbox * sizeof(uint32_t));
+    ctx.release(buf);
 }
 
 void compute_monopoles(Context& ctx, Tree& t)

@@ -71,17 +71,43 @@ struct Context {
     void to_device(void* dev, const void* host, size_t bytes);
 };
 
-struct Tree {
+// One box to build: caller-owned device arrays of one periodic box.
+struct BoxIn {
     uint64_t n = 0;
-    uint32_t D = 0;
+    uint32_t D = 1;
+    double box = 1.0;
+    uint32_t leaf_size = 16;
+    const double* pos = nullptr;         // 3 x n, or NULL
+    const uint64_t* lattice = nullptr;   // 3 x n, or NULL
+    const uint8_t* species = nullptr;
+    const double* mass = nullptr;
+};
+
+// The tree of one or more independent boxes built together. Particles of all
+// boxes are kept in one sorted array, box after box; nodes are breadth first
+// over all boxes (level by level, box after box within a level); the roots
+// are nodes 0 .. nbox-1. Per-node arrays of species use the largest D of the
+// boxes as stride (species a box does not have are empty).
+struct Tree {
+    uint64_t n = 0;                // particles of all boxes
+    uint32_t D = 0;                // species stride: the largest D of the boxes
+    uint32_t nbox = 0;
+    // per box (host)
+    std::vector<uint64_t> boff;    // nbox + 1: first sorted particle (= first input index) of each box
+    std::vector<uint32_t> bD;      // species of each box
+    std::vector<double> bbox;      // box side
+    std::vector<uint32_t> bleaf;   // leaf size
+    std::vector<uint64_t> bseg;    // nbox x (NGR_MAX_SPECIES + 1): species segments, sorted positions
+    uint64_t* boff_dev = nullptr;  // device copy of boff
+    // one-box conveniences (box 0)
     double box = 0.0;
     uint32_t leaf_size = 16;
-    // particles in sorted order (species, then Morton key)
+    uint64_t seg[NGR_MAX_SPECIES + 1] = {0};
+    // particles in sorted order (box, species, Morton key)
     uint64_t* X = nullptr;         // 3 x n lattice coordinates
     double* mass = nullptr;        // n
-    uint32_t* perm = nullptr;      // n, sorted position -> input index
-    uint64_t* keys = nullptr;      // n sorted keys
-    uint64_t seg[NGR_MAX_SPECIES + 1] = {0};   // species segments (host copy)
+    uint32_t* perm = nullptr;      // n, sorted position -> input index (over all boxes)
+    uint64_t* keys = nullptr;      // n sorted keys (species << 60 | Morton), per box
     // nodes, breadth first; capacity cap
     uint64_t nn = 0, cap = 0;
     uint32_t depth = 0;
@@ -94,11 +120,13 @@ struct Tree {
     uint4* cell = nullptr;         // corner (20-bit key units) x, y, z and level
     uint32_t* start = nullptr;     // nn x D, [node * D + b]
     uint32_t* count = nullptr;     // nn x D
+    uint32_t* node_box = nullptr;  // nn, the box of each node
     uint64_t n_leaves = 0;
     // monopoles: D x nn records {com_x, com_y, com_z (box fraction), M}
     double4* mono = nullptr;
     bool has_monopoles = false;
 };
+void free_tree(Context& ctx, Tree& t);
 
 // ---- device scan (scan.hip) ----
 // Exclusive prefix sum of n uint32 values; out may alias in. If total is
@@ -112,36 +140,49 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
                       uint32_t* vals_tmp, uint64_t n, int bits);
 
 // ---- build steps (build.hip) ----
-void build_tree(Context& ctx, const ngr_particles& p, uint32_t leaf_size, Tree& t);
+// Check, key, sort and build the tree of every box in one pass. Boxes with an
+// invalid species id, mass or position fail with NGR_EINVAL naming the box.
+void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t);
 void compute_monopoles(Context& ctx, Tree& t);
+// Nodes, leaves and deepest level of each box of a tree (host vectors).
+void box_node_counts(Context& ctx, const Tree& t, std::vector<uint64_t>& nodes, std::vector<uint64_t>& leaves,
+                     std::vector<uint32_t>& depth);
 
 // ---- groups and walk (walk.hip) ----
+// Groups of sinks, ordered like the particles (box, species, key). A segment
+// is one (box, species) pair: segment s = box * D + species (D = tree stride);
+// its groups are first[s] .. first[s + 1).
 struct Groups {
     uint64_t ng = 0;
-    uint32_t size = 64;
+    uint32_t nseg = 0;
     uint32_t* start = nullptr;     // ng
     uint32_t* count = nullptr;     // ng
     uint32_t* lo = nullptr;        // 3 x ng
     uint32_t* hi = nullptr;        // 3 x ng
-    uint64_t first[NGR_MAX_SPECIES + 1] = {0};   // first group of each species (host)
+    uint32_t* box = nullptr;       // ng, box of each group
+    std::vector<uint64_t> first;   // host, nseg + 1
     void free(Context& ctx);
 };
-void make_groups(Context& ctx, const Tree& t, uint32_t group_size, Groups& g);
+// group_size: per box, 16, 32 or 64
+void make_groups(Context& ctx, const Tree& t, const std::vector<uint32_t>& group_size, Groups& g);
 
+// Force law and walk parameters of one box.
 struct Law {
     uint32_t D = 0, ntab = 0, grid = 0;
     double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
     double r_cut = 0, eps = 0, theta = 0;
-    float2* table = nullptr;       // device, D x D x ntab (value, slope to next), last = (0, 0)
-    float* table_v = nullptr;      // device, D x D x (ntab + 1) samples plus a zero pad (same block)
+    std::vector<float2> pair;      // host, D x D x ntab (value, slope to next), last = (0, 0)
+    std::vector<float> value;      // host, D x D x (ntab + 1) samples plus a zero pad
 };
-void upload_law(Context& ctx, const ngr_force_params& fp, uint32_t D, Law& law);
+void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
 
 struct WalkOut {
     uint64_t pp = 0, pn = 0;
-    double ms_walk = 0.0;
+    std::vector<uint64_t> box_pp, box_pn;   // per box
+    double ms_walk = 0.0, ms_order = 0.0;
 };
-void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, double* acc,
-                uint64_t* group_counts_dev, WalkOut& out);
+// laws and acc: one per box of the tree; acc[k] is box k's 3 x n_k output.
+void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
+                const std::vector<double*>& acc, uint64_t* group_counts_dev, WalkOut& out);
 
 }  // namespace ngr

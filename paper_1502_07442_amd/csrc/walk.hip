@@ -25,6 +25,8 @@
 // refined by one float64 correction step.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "ngr_internal.hpp"
 
@@ -41,13 +43,16 @@ namespace {
 
 // ------------------------------------------------------------- groups ----
 // One thread per (node, species a). For a node holding more than Ng particles
-// of species a: a leaf is cut into chunks of Ng; an internal node groups runs
-// of consecutive children whose species-a counts add up to at most Ng
-// (children with more than Ng are handled by their own thread). The root
-// forms one group when it holds at most Ng. Every group start is flagged.
-__global__ void mark_group_starts(uint64_t nn, uint32_t D, uint32_t Ng, const uint32_t* __restrict__ start,
-                                  const uint32_t* __restrict__ count, const int32_t* __restrict__ first_child,
-                                  const uint8_t* __restrict__ n_child, uint32_t* __restrict__ flags)
+// of species a (Ng of the node's box): a leaf is cut into chunks of Ng; an
+// internal node groups runs of consecutive children whose species-a counts
+// add up to at most Ng (children with more than Ng are handled by their own
+// thread). A root forms one group when it holds at most Ng. Every group start
+// is flagged.
+__global__ void mark_group_starts(uint64_t nn, uint32_t D, const uint32_t* __restrict__ Ng_box,
+                                  const uint32_t* __restrict__ node_box, const uint32_t* __restrict__ start,
+                                  const uint32_t* __restrict__ count, const int32_t* __restrict__ parent,
+                                  const int32_t* __restrict__ first_child, const uint8_t* __restrict__ n_child,
+                                  uint32_t* __restrict__ flags)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nn * D) return;
@@ -55,8 +60,9 @@ __global__ void mark_group_starts(uint64_t nn, uint32_t D, uint32_t Ng, const ui
     uint32_t a = (uint32_t)(t % D);
     uint32_t na = count[i * D + a];
     if (na == 0) return;
+    const uint32_t Ng = Ng_box[node_box[i]];
     if (na <= Ng) {
-        if (i == 0) flags[start[a]] = 1;
+        if (parent[i] < 0) flags[start[i * D + a]] = 1;
         return;
     }
     if (n_child[i] == 0) {
@@ -86,65 +92,84 @@ __global__ void scatter_group_starts(uint64_t n, const uint32_t* __restrict__ fl
     if (i < n && flags[i]) gstart[gidx[i]] = (uint32_t)i;
 }
 
-// Count and integer bounding box (20-bit key lattice, hi exclusive) of each
-// group; a group ends where the next one starts. One wave per group (at most
-// 64 particles), one particle per lane.
-__global__ void finish_groups(uint64_t ng, uint64_t n, uint32_t Ng, const uint32_t* __restrict__ gstart,
-                              uint32_t* __restrict__ gcount, uint32_t* __restrict__ glo, uint32_t* __restrict__ ghi,
+// Count, integer bounding box (20-bit key lattice, hi exclusive) and box of
+// each group; a group ends where the next one starts. One wave per group (at
+// most 64 particles), one particle per lane.
+__global__ void finish_groups(uint64_t ng, uint64_t n, uint32_t nbox, const uint64_t* __restrict__ boff,
+                              const uint32_t* __restrict__ gstart, uint32_t* __restrict__ gcount,
+                              uint32_t* __restrict__ glo, uint32_t* __restrict__ ghi, uint32_t* __restrict__ gbox,
                               const uint64_t* __restrict__ X, uint32_t* __restrict__ error_flag)
 {
     const uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;   // the same for the whole wave
     const uint32_t lane = threadIdx.x & 63u;
     if (g >= ng) return;
     const uint64_t s = gstart[g], e = (g + 1 < ng) ? gstart[g + 1] : n;
-    if (e <= s || e - s > Ng || e - s > 64 || e > n) {   // groups hold 1..Ng consecutive particles
+    // box: the last k with boff[k] <= s
+    uint32_t lo = 0, hi = nbox;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (boff[mid] <= s) lo = mid;
+        else hi = mid;
+    }
+    if (e <= s || e - s > 64 || e > n || e > boff[lo + 1]) {   // groups hold 1..64 particles of one box
         if (lane == 0) {
             atomicOr(error_flag, 1u);
             gcount[g] = 0;
         }
         return;
     }
-    if (lane == 0) gcount[g] = (uint32_t)(e - s);
+    if (lane == 0) {
+        gcount[g] = (uint32_t)(e - s);
+        gbox[g] = lo;
+    }
     for (int a = 0; a < 3; ++a) {
-        uint32_t lo = 0xffffffffu, hi = 0;
+        uint32_t l = 0xffffffffu, h = 0;
         if (s + lane < e) {
             const uint32_t k = (uint32_t)(X[a * n + s + lane] >> 44);
-            lo = k;
-            hi = k + 1;
+            l = k;
+            h = k + 1;
         }
         for (int d = 32; d > 0; d >>= 1) {
-            lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
-            hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+            l = min(l, (uint32_t)__shfl_xor((int)l, d, 64));
+            h = max(h, (uint32_t)__shfl_xor((int)h, d, 64));
         }
         if (lane == 0) {
-            glo[a * ng + g] = lo;
-            ghi[a * ng + g] = hi;
+            glo[a * ng + g] = l;
+            ghi[a * ng + g] = h;
         }
     }
 }
 
-__global__ void read_positions(const uint32_t* __restrict__ v, const uint64_t* __restrict__ pos, uint32_t k,
-                               uint64_t n, uint32_t total_if_end, uint32_t* __restrict__ out)
+// First group of each segment: the group index at the segment's first sorted
+// position (a position of n, past the end, gives ng).
+__global__ void segment_firsts(uint32_t k, const uint64_t* __restrict__ pos, const uint32_t* __restrict__ gidx,
+                               uint64_t n, uint32_t ng, uint32_t* __restrict__ out)
 {
-    uint32_t t = threadIdx.x;
-    if (t < k) out[t] = pos[t] < n ? v[pos[t]] : total_if_end;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < k) out[t] = pos[t] < n ? gidx[pos[t]] : ng;
 }
 
 // ------------------------------------------------------- group order ----
-// The walk hands groups out heaviest first, estimated from the particle
-// density around each group: particles per cell of a level-L grid whose cell
-// side is at least r_cut, summed over the 5 x 5 x 5 cells around the group's
-// first particle. Cells of level L carry the total count of their node;
-// particles of leaves above level L are counted one by one.
+// The walk hands out each segment's groups heaviest first, estimated from the
+// particle density around each group: particles per cell of a level-L grid
+// of the group's box (cells at least r_cut wide), summed over the 5 x 5 x 5
+// cells around the group's first particle. Cells of level L carry the total
+// count of their node; particles of leaves above level L are counted one by
+// one.
 constexpr int kOrderRadius = 2;
 
-__global__ void density_grid(uint64_t nodes, uint32_t D, uint32_t L, const uint4* __restrict__ cell,
-                             const uint8_t* __restrict__ n_child, const uint32_t* __restrict__ start,
-                             const uint32_t* __restrict__ count, const uint64_t* __restrict__ X, uint64_t n,
-                             uint32_t* __restrict__ H)
+__global__ void density_grid(uint64_t nodes, uint32_t D, const uint32_t* __restrict__ Lbox,
+                             const uint64_t* __restrict__ Hoff, const uint32_t* __restrict__ node_box,
+                             const uint4* __restrict__ cell, const uint8_t* __restrict__ n_child,
+                             const uint32_t* __restrict__ start, const uint32_t* __restrict__ count,
+                             const uint64_t* __restrict__ X, uint64_t n, uint32_t* __restrict__ Hall)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nodes) return;
+    const uint32_t box = node_box[i];
+    const uint32_t L = Lbox[box];
+    if (L == 0) return;
+    uint32_t* H = Hall + Hoff[box];
     const uint4 c = cell[i];
     const uint32_t sh = (uint32_t)kLevels - L;
     if (c.w == L) {
@@ -162,19 +187,23 @@ __global__ void density_grid(uint64_t nodes, uint32_t D, uint32_t L, const uint4
     }
 }
 
-// Sort key of every group: species, then the density bucket descending
+// Sort key of every group: its segment, then the density bucket descending
 // (half-octave steps of the neighbourhood count); value: the group index.
-__global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t L, const uint32_t* __restrict__ gstart,
-                                 const uint64_t* __restrict__ keys, const uint64_t* __restrict__ X,
-                                 const uint32_t* __restrict__ H, uint64_t* __restrict__ okey,
-                                 uint32_t* __restrict__ oval)
+__global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t D, const uint32_t* __restrict__ gstart,
+                                 const uint32_t* __restrict__ gbox, const uint32_t* __restrict__ Lbox,
+                                 const uint64_t* __restrict__ Hoff, const uint64_t* __restrict__ keys,
+                                 const uint64_t* __restrict__ X, const uint32_t* __restrict__ Hall,
+                                 uint64_t* __restrict__ okey, uint32_t* __restrict__ oval)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
     const uint64_t j = gstart[g];
+    const uint32_t box = gbox[g];
+    const uint32_t L = Lbox[box];
     uint32_t v = 1;
     if (L > 0) {
-        const int32_t S = 1 << L, m = S - 1;
+        const uint32_t* H = Hall + Hoff[box];
+        const int32_t m = (1 << L) - 1;
         const int32_t x = (int32_t)(X[j] >> (64 - L)), y = (int32_t)(X[n + j] >> (64 - L)),
                       z = (int32_t)(X[2 * n + j] >> (64 - L));
         for (int32_t dx = -kOrderRadius; dx <= kOrderRadius; ++dx)
@@ -188,7 +217,8 @@ __global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t L, const uint
     const uint32_t msb = 31u - (uint32_t)__builtin_clz(v);
     const uint32_t half = msb ? (v >> (msb - 1)) & 1u : 0u;
     const uint32_t bucket = 2u * msb + half;            // < 64
-    okey[g] = ((keys[j] >> 60) << 8) | (255u - bucket);
+    const uint64_t seg = (uint64_t)box * D + (keys[j] >> kKeyBits);
+    okey[g] = (seg << 8) | (255u - bucket);
     oval[g] = (uint32_t)g;
 }
 
@@ -198,12 +228,29 @@ constexpr int kBuf = 128;              // node / leaf buffer entries per wave
 constexpr int kRec = 68;               // record slots per wave: 64 and up to 3 pads
 constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
 constexpr int kMaxWaves = 16;          // waves per workgroup
-constexpr int kCtrlBytes = 256;        // LDS control area ahead of the tables
+constexpr int kCtrlBytes = 512;        // LDS control area ahead of the tables
 // Table layouts in LDS. PAIR: per interval (value, slope to the next sample),
 // with a (0, 0) entry that the clamped index reaches for r >= r_cut. VALUE:
 // the samples only (plus one pad), the slope taken from the next sample and
 // r >= r_cut zeroed by a compare; half the LDS for twice the tables.
 enum TableMode { kPair = 0, kValue = 1 };
+
+// Force-law and walk parameters of one box.
+struct BoxParams {
+    double box, inv_box, eps2, R2, theta2;
+    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // 1.5 G_ab, row a = sink species, D x D
+    double* acc;               // 3 x n output, input order
+    uint64_t in_off, n;        // first input index (over all boxes) and particles of the box
+    uint64_t tab, tabv;        // first entry of the box's tables in the PAIR (float2) and VALUE (float) arrays
+    float tscale, toff, tmax;
+    uint32_t wrap_limit, D, ntab;
+};
+
+// Per-lane-invariant values of the pair term, taken from the box.
+struct PairParams {
+    double box, inv_box, eps2;
+    float tscale, toff, tmax;
+};
 
 struct WalkArgs {
     const uint4* cell;
@@ -222,23 +269,25 @@ struct WalkArgs {
     const uint32_t* glo;
     const uint32_t* ghi;
     uint64_t ng;
-    const uint32_t* order;     // group indices: species by species, heaviest first
-    uint32_t first[NGR_MAX_SPECIES + 1];   // groups of species a: order[first[a] .. first[a + 1])
-    uint32_t* queues;          // per species: groups of that species handed out so far
-    uint32_t D, ntab;
-    const float2* table;       // PAIR layout, D x D x ntab
-    const float* table_v;      // VALUE layout, D x D x (ntab + 1)
-    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // 1.5 G_ab (row a = sink species)
-    double box, inv_box, eps2, R2, theta2;
-    uint32_t wrap_limit;
-    float tscale, toff, tmax;
-    double* acc;
-    unsigned long long* stats;
+    uint32_t D;                // species stride of the tree; segment s = box * D + species
+    uint32_t nseg;
+    const uint32_t* order;     // group indices: segment by segment, heaviest first
+    const uint32_t* seg_first; // nseg + 1: groups of segment s are order[seg_first[s] .. seg_first[s + 1])
+    uint32_t* queues;          // nseg: groups of each segment handed out so far
+    const uint32_t* sched;     // non-empty segments, most groups first
+    uint32_t nsched;
+    uint32_t* cursor;          // next entry of sched to start
+    const BoxParams* boxes;
+    const float2* table;       // PAIR layout of every box
+    const float* table_v;      // VALUE layout of every box
+    unsigned long long* seg_counts;   // nseg x 2: pp and pn interactions of each segment
     unsigned long long* gcounts;
     uint32_t* stacks;
     uint32_t stack_cap;
     uint32_t* error_flag;
     uint32_t max_steps;        // traversal batches per group never exceed the node count
+    uint32_t tab_bytes;        // LDS bytes of the largest segment's tables
+    BoxParams box0;            // the box of a one-box call (read from the arguments)
 };
 
 __device__ inline void wave_sync()
@@ -263,7 +312,7 @@ __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfir
 // records rec[0], rec[K], rec[2K], ... (iters of them; the caller offsets rec
 // by the lane's replica).
 template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K>
-__device__ inline void eval_records(const WalkArgs& A, const double4* __restrict__ rec, uint32_t iters,
+__device__ inline void eval_records(const PairParams& A, const double4* __restrict__ rec, uint32_t iters,
                                     const void* __restrict__ tbv, double ox, double oy, double oz, double& ax,
                                     double& ay, double& az)
 {
@@ -319,18 +368,18 @@ __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t n
     return (raw + 255u) & ~255u;
 }
 
-template <int GRID, int TAB, bool EPS0>
+template <int GRID, int TAB, bool EPS0, bool ONE>
 __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
     HIP_DYNAMIC_SHARED(unsigned char, smem);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const uint32_t D = A.D, ntab = A.ntab;
-    const uint32_t tstride = TAB == kPair ? ntab : ntab + 1;   // entries per table
-    // LDS: a control word, the sink species' D tables, then per-wave buffers
+    const uint32_t D = A.D;                // species stride of the node arrays
+    // LDS: control area (next segment; per-wave counts), the tables of one
+    // segment, then per-wave buffers
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+    unsigned long long* part = reinterpret_cast<unsigned long long*>(smem + 256);   // 2 per wave
     unsigned char* tsm = smem + kCtrlBytes;
-    const uint32_t tab_bytes = table_bytes(TAB, D, ntab);
-    unsigned char* wb = tsm + tab_bytes + wave * kWaveLds;
+    unsigned char* wb = tsm + A.tab_bytes + wave * kWaveLds;
     double4* rec = reinterpret_cast<double4*>(wb);
     uint32_t* pnb = reinterpret_cast<uint32_t*>(wb + kRec * 32);
     uint32_t* ppb = pnb + kBuf;
@@ -338,45 +387,42 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     uint32_t* pst = scanb + 68;          // 64 entries
     uint32_t* stack = A.stacks + ((uint64_t)blockIdx.x * nwaves + wave) * A.stack_cap;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const double scale = A.box * 0x1p-64;
     const uint64_t n = A.n;
 
-    // One launch serves every sink species. A workgroup holds the tables of
-    // one species at a time: it starts on a species of its own (the
-    // workgroups are spread over the species that have groups), its waves
-    // take that species' groups until none is left, and then, together, it
-    // moves to the species with the most groups still to hand out.
-    uint32_t a = 0;
-    {
-        uint32_t nonempty = 0;
-        for (uint32_t b = 0; b < D; ++b) nonempty += A.first[b + 1] > A.first[b] ? 1u : 0u;
-        const uint32_t k = blockIdx.x % max(nonempty, 1u);
-        uint32_t seen = 0;
-        for (uint32_t b = 0; b < D; ++b) {
-            const bool ne = A.first[b + 1] > A.first[b];
-            if (ne && seen == k) a = b;
-            seen += ne ? 1u : 0u;
-        }
-    }
-
-    unsigned long long tot_pp = 0, tot_pn = 0;
+    // One launch serves every segment (box, sink species). A workgroup holds
+    // the tables of one segment at a time. Workgroups start on the segments
+    // with the most groups (spread over them when there are fewer segments
+    // than workgroups); when its segment's queue is empty, the whole
+    // workgroup takes the next segment not yet started and, once every
+    // segment has started, joins the one with the most groups left.
+    uint32_t seg = A.sched[blockIdx.x % A.nsched];
     bool any_overflow = false;
     for (;;) {
+        const uint32_t bxi = seg / D, a = seg % D;
+        const BoxParams& P = ONE ? A.box0 : A.boxes[bxi];
+        const uint32_t Dk = P.D, ntab = P.ntab;
+        const uint32_t tstride = TAB == kPair ? ntab : ntab + 1;   // entries per table
         if (TAB == kPair) {
             float2* tab = reinterpret_cast<float2*>(tsm);
-            const float2* src = A.table + (uint64_t)a * D * ntab;
-            for (uint32_t k = threadIdx.x; k < D * ntab; k += blockDim.x) tab[k] = src[k];
+            const float2* src = A.table + P.tab + (uint64_t)a * Dk * ntab;
+            for (uint32_t k = threadIdx.x; k < Dk * ntab; k += blockDim.x) tab[k] = src[k];
         } else {
             float* tab = reinterpret_cast<float*>(tsm);
-            const float* src = A.table_v + (uint64_t)a * D * (ntab + 1);
-            for (uint32_t k = threadIdx.x; k < D * (ntab + 1); k += blockDim.x) tab[k] = src[k];
+            const float* src = A.table_v + P.tabv + (uint64_t)a * Dk * (ntab + 1);
+            for (uint32_t k = threadIdx.x; k < Dk * (ntab + 1); k += blockDim.x) tab[k] = src[k];
         }
         __syncthreads();
-        const uint32_t g_begin = A.first[a], g_count = A.first[a + 1] - A.first[a];
-        uint32_t* const queue = A.queues + a;
-        const double* const Ga = A.G + a * D;
+        const PairParams pp{P.box, P.inv_box, P.eps2, P.tscale, P.toff, P.tmax};
+        const double R2 = P.R2, theta2 = P.theta2, bx = P.box, scale = P.box * 0x1p-64;
+        const uint32_t wrap_limit = P.wrap_limit;
+        double* const acc = P.acc;
+        const uint64_t in_off = P.in_off, nbx = P.n;
+        const double* const Ga = P.G + a * Dk;
+        const uint32_t g_begin = A.seg_first[seg], g_count = A.seg_first[seg + 1] - g_begin;
+        uint32_t* const queue = A.queues + seg;
+        unsigned long long tot_pp = 0, tot_pn = 0;
 
-    // Waves take groups from the species' queue. Every lane executes the
+    // Waves take groups from the segment's queue. Every lane executes the
     // atomic (lane 0 adds one, the others add zero), so no lane-dependent
     // branch surrounds it; lane 0 is the first active lane and its return
     // value is the wave's ticket. The loop exit then depends only on that
@@ -393,7 +439,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         for (int k = 0; k < 3; ++k) {
             lo[k] = A.glo[k * A.ng + g];
             hi[k] = A.ghi[k * A.ng + g];
-            wrap |= (hi[k] - lo[k]) > A.wrap_limit;
+            wrap |= (hi[k] - lo[k]) > wrap_limit;
         }
         // group centre: lattice units and box fraction
         const uint64_t C0 = (uint64_t)(lo[0] + hi[0]) << 43, C1 = (uint64_t)(lo[1] + hi[1]) << 43,
@@ -423,15 +469,15 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         auto eval = [&](uint32_t b, uint32_t nrec) {
             const unsigned char* tb = tsm + (TAB == kPair ? 8u : 4u) * b * tstride;
             const uint32_t iters = (nrec + K - 1u) >> lk;
-            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(A, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(A, rrec, iters, tb, ox, oy, oz, ax, ay, az);
-            else eval_records<GRID, TAB, EPS0, false, 4>(A, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            else eval_records<GRID, TAB, EPS0, false, 4>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
         };
 
         // Accepted nodes: one record per non-empty species monopole.
         auto flush_nodes = [&](uint32_t k) {
-            for (uint32_t b = 0; b < D; ++b) {
+            for (uint32_t b = 0; b < Dk; ++b) {
                 double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
                 if ((uint32_t)lane < k) r = A.mono[(uint64_t)b * A.nn + pnb[lane]];
                 const bool v = (uint32_t)lane < k && r.w > 0.0;
@@ -442,7 +488,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     d0 -= rint(d0);
                     d1 -= rint(d1);
                     d2 -= rint(d2);
-                    rec[__popcll(m & lt)] = make_double4(d0 * A.box, d1 * A.box, d2 * A.box, Ga[b] * r.w);
+                    rec[__popcll(m & lt)] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w);
                 }
                 if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
                 wave_sync();
@@ -454,7 +500,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 
         // Opened leaves: every particle, one source species at a time.
         auto flush_leaves = [&](uint32_t k) {
-            for (uint32_t b = 0; b < D; ++b) {
+            for (uint32_t b = 0; b < Dk; ++b) {
                 uint32_t c = 0, st = 0;
                 if ((uint32_t)lane < k) {
                     uint32_t leaf = ppb[lane];
@@ -495,7 +541,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 
         // breadth-first traversal in batches of 64 nodes
         uint32_t sp = 1, npn = 0, npp = 0;
-        stack[0] = 0;                      // the root; every lane stores the same value
+        stack[0] = bxi;                    // the box's root; every lane stores the same value
         wave_sync();
         bool overflow = false;
         uint32_t steps = 0;
@@ -526,8 +572,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     D2 += (double)gp * (double)gp;
                     D2m += (double)gm * (double)gm;
                 }
-                if (D2 >= A.R2) dec = kPrune;
-                else if ((double)(4ll * S * S) < A.theta2 * D2 && D2m < A.R2) dec = kAccept;
+                if (D2 >= R2) dec = kPrune;
+                else if ((double)(4ll * S * S) < theta2 * D2 && D2m < R2) dec = kAccept;
                 else {
                     dec = kOpen;
                     nc = A.n_child[node];
@@ -588,10 +634,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             az += __shfl_xor(az, 32, 64);
         }
         if ((uint32_t)lane < ns) {
-            const uint32_t p = A.perm[s0 + lane];
-            A.acc[p] = ax;
-            A.acc[n + p] = ay;
-            A.acc[2 * n + p] = az;
+            const uint64_t p = A.perm[s0 + lane] - in_off;
+            acc[p] = ax;
+            acc[nbx + p] = ay;
+            acc[2 * nbx + p] = az;
         }
         const unsigned long long pn = pn_src * ns, pp = pp_src * ns - ns;
         tot_pp += pp;
@@ -601,43 +647,54 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             A.gcounts[4ull * g + lane] = v[lane];
         }
     }
-        __syncthreads();                   // every wave is done with this species' tables
+        __syncthreads();                   // every wave is done with this segment's tables
+        if (lane == 0) {
+            part[2 * wave] = tot_pp;
+            part[2 * wave + 1] = tot_pn;
+        }
         if (wave == 0) {
-            uint32_t best = D, best_left = 0;
-            for (uint32_t b = 0; b < D; ++b) {
-                const uint32_t cnt = A.first[b + 1] - A.first[b];
-                const uint32_t q = uniform(atomicAdd(A.queues + b, 0u));
-                const uint32_t left = cnt - min(q, cnt);
-                if (left > best_left) {
-                    best_left = left;
-                    best = b;
+            // next segment: the next one not started, else the one with the most groups left
+            const uint32_t t = uniform(atomicAdd(A.cursor, lane == 0 ? 1u : 0u));
+            uint32_t next = A.nseg;
+            if (t < A.nsched) {
+                next = A.sched[t];
+            } else {
+                uint32_t best = 0, best_s = A.nseg;
+                for (uint32_t q = (uint32_t)lane; q < A.nseg; q += 64u) {
+                    const uint32_t cnt = A.seg_first[q + 1] - A.seg_first[q];
+                    const uint32_t h = __hip_atomic_load(A.queues + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t left = cnt - min(h, cnt);
+                    if (left > best) {
+                        best = left;
+                        best_s = q;
+                    }
                 }
+                for (int d = 32; d > 0; d >>= 1) {
+                    const uint32_t ob = (uint32_t)__shfl_xor((int)best, d, 64);
+                    const uint32_t os = (uint32_t)__shfl_xor((int)best_s, d, 64);
+                    if (ob > best || (ob == best && os < best_s)) {
+                        best = ob;
+                        best_s = os;
+                    }
+                }
+                next = best ? best_s : A.nseg;
             }
-            ctrl[0] = (int32_t)best;       // every lane stores the same value
+            ctrl[0] = (int32_t)next;       // every lane stores the same value
         }
         __syncthreads();
-        a = uniform((uint32_t)ctrl[0]);
-        if (a >= D) break;
-    }
-    // workgroup totals first: one global atomic per workgroup and counter
-    // (every wave has left the species loop through the same barriers)
-    unsigned long long* part = reinterpret_cast<unsigned long long*>(wb);
-    if (lane == 0) {
-        part[0] = tot_pp;
-        part[1] = tot_pn;
-        if (any_overflow) atomicOr(A.error_flag, 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long pp = 0, pn = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            const unsigned long long* q = reinterpret_cast<const unsigned long long*>(tsm + tab_bytes + w * kWaveLds);
-            pp += q[0];
-            pn += q[1];
+        if (threadIdx.x == 0) {            // the segment's counts: one global atomic per workgroup
+            unsigned long long spp = 0, spn = 0;
+            for (int w = 0; w < nwaves; ++w) {
+                spp += part[2 * w];
+                spn += part[2 * w + 1];
+            }
+            if (spp) atomicAdd(&A.seg_counts[2ull * seg], spp);
+            if (spn) atomicAdd(&A.seg_counts[2ull * seg + 1], spn);
         }
-        atomicAdd(&A.stats[0], pp);
-        atomicAdd(&A.stats[1], pn);
+        seg = uniform((uint32_t)ctrl[0]);
+        if (seg >= A.nseg) break;
     }
+    if (lane == 0 && any_overflow) atomicOr(A.error_flag, 1u);
 }
 
 inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
@@ -650,64 +707,76 @@ void Groups::free(Context& ctx)
     ctx.release(count);
     ctx.release(lo);
     ctx.release(hi);
-    start = count = lo = hi = nullptr;
+    ctx.release(box);
+    start = count = lo = hi = box = nullptr;
     ng = 0;
+    nseg = 0;
+    first.clear();
 }
 
-void make_groups(Context& ctx, const Tree& t, uint32_t group_size, Groups& g)
+void make_groups(Context& ctx, const Tree& t, const std::vector<uint32_t>& group_size, Groups& g)
 {
-    g.size = group_size;
     const uint64_t n = t.n;
+    const uint32_t D = t.D, nbox = t.nbox;
     g.ng = 0;
-    for (int a = 0; a <= NGR_MAX_SPECIES; ++a) g.first[a] = 0;
+    g.nseg = nbox * D;
+    g.first.assign(g.nseg + 1, 0);
     if (n == 0) return;
     ctx.stage("groups: mark");
     uint32_t* flags = static_cast<uint32_t*>(ctx.alloc(n * sizeof(uint32_t) * 2 + 64));
     uint32_t* gidx = flags + n;
     uint32_t* total = gidx + n;
+    uint32_t* Ng_dev = static_cast<uint32_t*>(ctx.alloc(nbox * sizeof(uint32_t)));
+    ctx.to_device(Ng_dev, group_size.data(), nbox * sizeof(uint32_t));
     HIP_CHECK(hipMemsetAsync(flags, 0, n * sizeof(uint32_t), ctx.stream));
-    hipLaunchKernelGGL(mark_group_starts, dim3(blocks_for(t.nn * t.D, 256)), dim3(256), 0, ctx.stream, t.nn, t.D,
-                       group_size, t.start, t.count, t.first_child, t.n_child, flags);
+    hipLaunchKernelGGL(mark_group_starts, dim3(blocks_for(t.nn * D, 256)), dim3(256), 0, ctx.stream, t.nn, D, Ng_dev,
+                       t.node_box, t.start, t.count, t.parent, t.first_child, t.n_child, flags);
     LAUNCH_CHECK("mark_group_starts");
     scan_exclusive(ctx, flags, gidx, n, total);
     uint64_t w = 0;
     ctx.read_words(&w, total, 1);
     const uint32_t ngh = (uint32_t)(w & 0xffffffffu);
     if (ngh == 0 || ngh > n) fail(NGR_EDEVICE, "group formation produced an impossible group count");
-    // first group of each species: the group index at the species segment start
-    uint64_t* segd = static_cast<uint64_t*>(ctx.alloc(16 * sizeof(uint64_t)));
-    uint32_t* outd = reinterpret_cast<uint32_t*>(segd + 8);
-    uint32_t* errd = outd + 8;
-    ctx.write_words(segd, t.seg, NGR_MAX_SPECIES + 1);
+    // first group of each segment: the group index at the segment's first particle
+    std::vector<uint64_t> pos(g.nseg + 1);
+    for (uint32_t k = 0; k < nbox; ++k)
+        for (uint32_t a = 0; a < D; ++a) pos[(size_t)k * D + a] = t.bseg[(size_t)k * (NGR_MAX_SPECIES + 1) + a];
+    pos[g.nseg] = n;
+    uint64_t* pos_dev = static_cast<uint64_t*>(ctx.alloc(pos.size() * sizeof(uint64_t)));
+    uint32_t* first_dev = static_cast<uint32_t*>(ctx.alloc(pos.size() * sizeof(uint32_t) + 64));
+    uint32_t* errd = first_dev + pos.size();
+    ctx.to_device(pos_dev, pos.data(), pos.size() * sizeof(uint64_t));
     HIP_CHECK(hipMemsetAsync(errd, 0, sizeof(uint32_t), ctx.stream));
-    hipLaunchKernelGGL(read_positions, dim3(1), dim3(64), 0, ctx.stream, gidx, segd, t.D + 1, n, ngh, outd);
-    LAUNCH_CHECK("read_positions");
+    hipLaunchKernelGGL(segment_firsts, dim3(blocks_for(pos.size(), 256)), dim3(256), 0, ctx.stream, (uint32_t)pos.size(),
+                       pos_dev, gidx, n, ngh, first_dev);
+    LAUNCH_CHECK("segment_firsts");
     g.ng = ngh;
     g.start = static_cast<uint32_t*>(ctx.alloc((uint64_t)ngh * sizeof(uint32_t)));
     g.count = static_cast<uint32_t*>(ctx.alloc((uint64_t)ngh * sizeof(uint32_t)));
     g.lo = static_cast<uint32_t*>(ctx.alloc(3ull * ngh * sizeof(uint32_t)));
     g.hi = static_cast<uint32_t*>(ctx.alloc(3ull * ngh * sizeof(uint32_t)));
+    g.box = static_cast<uint32_t*>(ctx.alloc((uint64_t)ngh * sizeof(uint32_t)));
     ctx.stage("groups: boxes");
     hipLaunchKernelGGL(scatter_group_starts, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, flags, gidx,
                        g.start);
     LAUNCH_CHECK("scatter_group_starts");
-    hipLaunchKernelGGL(finish_groups, dim3(blocks_for((uint64_t)ngh * 64, 256)), dim3(256), 0, ctx.stream, (uint64_t)ngh, n,
-                       group_size, g.start, g.count, g.lo, g.hi, t.X, errd);
+    hipLaunchKernelGGL(finish_groups, dim3(blocks_for((uint64_t)ngh * 64, 256)), dim3(256), 0, ctx.stream, (uint64_t)ngh,
+                       n, nbox, t.boff_dev, g.start, g.count, g.lo, g.hi, g.box, t.X, errd);
     LAUNCH_CHECK("finish_groups");
-    uint64_t words[8];
-    ctx.read_words(words, outd, 8);
-    const uint32_t* firsts = reinterpret_cast<const uint32_t*>(words);
-    if (firsts[8]) fail(NGR_EDEVICE, "group formation produced an inconsistent group");
-    for (uint32_t a = 0; a <= t.D; ++a) g.first[a] = firsts[a];
-    for (uint32_t a = t.D + 1; a <= NGR_MAX_SPECIES; ++a) g.first[a] = ngh;
+    std::vector<uint32_t> fh(pos.size() + 1);
+    ctx.to_host(fh.data(), first_dev, (pos.size() + 1) * sizeof(uint32_t));
+    if (fh[pos.size()]) fail(NGR_EDEVICE, "group formation produced an inconsistent group");
+    for (size_t k = 0; k < pos.size(); ++k) g.first[k] = fh[k];
     ctx.release(flags);
-    ctx.release(segd);
+    ctx.release(Ng_dev);
+    ctx.release(pos_dev);
+    ctx.release(first_dev);
 }
 
 // Tables of every pair (a, b), in both LDS layouts (see TableMode): PAIR as
 // (value, slope to the next sample) for the ntab - 1 intervals plus a (0, 0)
 // entry; VALUE as the ntab samples plus a zero pad.
-void upload_law(Context& ctx, const ngr_force_params& fp, uint32_t D, Law& law)
+void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
 {
     law.D = D;
     law.ntab = fp.ntab;
@@ -728,83 +797,191 @@ void upload_law(Context& ctx, const ngr_force_params& fp, uint32_t D, Law& law)
             def[k] = std::erfc(x) + r / (fp.r_s * std::sqrt(M_PI)) * std::exp(-x * x);
         }
     }
-    const size_t np = (size_t)D * D * ntab, nv = (size_t)D * D * (ntab + 1);
-    std::vector<float2> hp(np);
-    std::vector<float> hv(nv);
+    law.pair.resize((size_t)D * D * ntab);
+    law.value.resize((size_t)D * D * (ntab + 1));
     for (uint32_t ab = 0; ab < D * D; ++ab) {
         const double* src = T ? T + (size_t)ab * ntab : def.data();
-        float2* dp = hp.data() + (size_t)ab * ntab;
-        float* dv = hv.data() + (size_t)ab * (ntab + 1);
+        float2* dp = law.pair.data() + (size_t)ab * ntab;
+        float* dv = law.value.data() + (size_t)ab * (ntab + 1);
         for (uint32_t k = 0; k + 1 < ntab; ++k) dp[k] = make_float2((float)src[k], (float)(src[k + 1] - src[k]));
         dp[ntab - 1] = make_float2(0.0f, 0.0f);
         for (uint32_t k = 0; k < ntab; ++k) dv[k] = (float)src[k];
         dv[ntab] = 0.0f;
     }
-    law.table = static_cast<float2*>(ctx.alloc(np * sizeof(float2) + nv * sizeof(float)));
-    law.table_v = reinterpret_cast<float*>(law.table + np);
-    ctx.to_device(law.table, hp.data(), np * sizeof(float2));
-    ctx.to_device(law.table_v, hv.data(), nv * sizeof(float));
 }
 
-// Group indices species by species, each species' groups in descending
+// Group indices segment by segment, each segment's groups in descending
 // order of the density estimate (ties in tree order). Returns device memory
 // of g.ng entries, to be released by the caller.
-static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, double r_cut)
+static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws)
 {
     const uint64_t ng = g.ng;
-    // the finest level whose cells are at least r_cut wide, at most 8
-    uint32_t L = 0;
-    while (L < 8 && std::ldexp(t.box, -(int)(L + 1)) >= r_cut) ++L;
+    const uint32_t nbox = t.nbox;
+    // per box: the finest level whose cells are at least r_cut wide, at most
+    // 8, and no more cells in all than 2^26
+    std::vector<uint32_t> L(nbox);
+    std::vector<uint64_t> Hoff(nbox + 1, 0);
+    uint32_t cap = 8;
+    for (;;) {
+        uint64_t cells = 0;
+        for (uint32_t k = 0; k < nbox; ++k) {
+            uint32_t l = 0;
+            while (l < cap && std::ldexp(t.bbox[k], -(int)(l + 1)) >= laws[k].r_cut) ++l;
+            L[k] = (t.boff[k + 1] > t.boff[k]) ? l : 0;
+            Hoff[k] = cells;
+            cells += L[k] ? (1ull << (3 * L[k])) : 0;
+        }
+        Hoff[nbox] = cells;
+        if (cells <= (1ull << 26) || cap == 0) break;
+        --cap;
+    }
     uint64_t* okey = static_cast<uint64_t*>(ctx.alloc(2 * ng * sizeof(uint64_t)));
     uint32_t* oval = static_cast<uint32_t*>(ctx.alloc(2 * ng * sizeof(uint32_t)));
+    uint32_t* Ld = static_cast<uint32_t*>(ctx.alloc(nbox * sizeof(uint32_t)));
+    uint64_t* Hoffd = static_cast<uint64_t*>(ctx.alloc((nbox + 1) * sizeof(uint64_t)));
+    ctx.to_device(Ld, L.data(), nbox * sizeof(uint32_t));
+    ctx.to_device(Hoffd, Hoff.data(), (nbox + 1) * sizeof(uint64_t));
     uint32_t* H = nullptr;
-    if (L > 0) {
-        const uint64_t cells = 1ull << (3 * L);
-        H = static_cast<uint32_t*>(ctx.alloc(cells * sizeof(uint32_t)));
-        HIP_CHECK(hipMemsetAsync(H, 0, cells * sizeof(uint32_t), ctx.stream));
-        const uint64_t nodes = t.level_start[std::min<uint32_t>(L, t.depth) + 1];
-        hipLaunchKernelGGL(density_grid, dim3(blocks_for(nodes, 256)), dim3(256), 0, ctx.stream, nodes, t.D, L,
-                           t.cell, t.n_child, t.start, t.count, t.X, t.n, H);
+    if (Hoff[nbox]) {
+        H = static_cast<uint32_t*>(ctx.alloc(Hoff[nbox] * sizeof(uint32_t)));
+        HIP_CHECK(hipMemsetAsync(H, 0, Hoff[nbox] * sizeof(uint32_t), ctx.stream));
+        uint32_t Lmax = 0;
+        for (uint32_t k = 0; k < nbox; ++k) Lmax = std::max(Lmax, L[k]);
+        const uint64_t nodes = t.level_start[std::min<uint32_t>(Lmax, t.depth) + 1];
+        hipLaunchKernelGGL(density_grid, dim3(blocks_for(nodes, 256)), dim3(256), 0, ctx.stream, nodes, t.D, Ld, Hoffd,
+                           t.node_box, t.cell, t.n_child, t.start, t.count, t.X, t.n, H);
         LAUNCH_CHECK("density_grid");
     }
-    hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.n, L, g.start,
-                       t.keys, t.X, H, okey, oval);
+    hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.n, t.D, g.start,
+                       g.box, Ld, Hoffd, t.keys, t.X, H, okey, oval);
     LAUNCH_CHECK("group_order_keys");
-    radix_sort_pairs(ctx, okey, oval, okey + ng, oval + ng, ng, 16);
+    int bits = 8;
+    while ((1ull << (bits - 8)) < g.nseg) bits += 8;
+    radix_sort_pairs(ctx, okey, oval, okey + ng, oval + ng, ng, bits);
     if (H) ctx.release(H);
     ctx.release(okey);
+    ctx.release(Ld);
+    ctx.release(Hoffd);
     return oval;
 }
 
-void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, double* acc,
-                uint64_t* group_counts_dev, WalkOut& out)
+void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
+                const std::vector<double*>& accv, uint64_t* group_counts_dev, WalkOut& out)
 {
     out = WalkOut{};
+    const uint32_t nbox = t.nbox, D = t.D;
+    out.box_pp.assign(nbox, 0);
+    out.box_pn.assign(nbox, 0);
     if (t.n == 0 || g.ng == 0) return;
-    const uint32_t D = t.D;
+    const uint32_t grid = laws[0].grid;
+    bool eps0 = false;
+    uint32_t pair_max = 0, value_max = 0;
+    for (uint32_t k = 0; k < nbox; ++k) {
+        if (laws[k].grid != grid) fail(NGR_EINVAL, "the boxes of one call must share the table grid");
+        eps0 |= laws[k].eps == 0.0;
+        pair_max = std::max(pair_max, table_bytes(kPair, laws[k].D, laws[k].ntab));
+        value_max = std::max(value_max, table_bytes(kValue, laws[k].D, laws[k].ntab));
+    }
     // layout and workgroup shape within the LDS of one workgroup: the
     // (value, slope) tables when at least 8 waves still fit beside them
     const size_t lds_max = ctx.lds_per_block;
     int mode = kPair;
-    size_t tab_bytes = kCtrlBytes + table_bytes(kPair, D, law.ntab);
-    if (tab_bytes + 8 * (size_t)kWaveLds > lds_max) {
+    size_t tab_bytes = pair_max;
+    if (kCtrlBytes + tab_bytes + 8 * (size_t)kWaveLds > lds_max) {
         mode = kValue;
-        tab_bytes = kCtrlBytes + table_bytes(kValue, D, law.ntab);
+        tab_bytes = value_max;
     }
-    if (tab_bytes + kWaveLds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
-    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - tab_bytes) / kWaveLds);
-    const size_t lds = tab_bytes + (size_t)waves * kWaveLds;
+    if (kCtrlBytes + tab_bytes + kWaveLds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
+    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - kCtrlBytes - tab_bytes) / kWaveLds);
+    const size_t lds = kCtrlBytes + tab_bytes + (size_t)waves * kWaveLds;
     const size_t per_cu = std::max<size_t>(1, lds_max / lds);
     const int blocks = ctx.num_cu * (int)std::min<size_t>(per_cu, 4);
     const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
     ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
-    ctx.ensure(ctx.counters, 4096);
-    unsigned long long* stats = static_cast<unsigned long long*>(ctx.counters.p);
-    uint32_t* err = reinterpret_cast<uint32_t*>(stats + 4);
-    uint32_t* queues = err + 8;
-    HIP_CHECK(hipMemsetAsync(ctx.counters.p, 0, 4096, ctx.stream));
+
+    // per-box parameters and the tables of every box, concatenated
+    std::vector<BoxParams> bp(nbox);
+    uint64_t np = 0, nv = 0;
+    for (uint32_t k = 0; k < nbox; ++k) {
+        const Law& law = laws[k];
+        BoxParams& P = bp[k];
+        std::memset(&P, 0, sizeof P);
+        const double box = t.bbox[k];
+        P.box = box;
+        P.inv_box = 1.0 / box;
+        P.eps2 = law.eps * law.eps;
+        const double q = law.r_cut / box * 2097152.0;   // r_cut in half key units
+        P.R2 = q * q;
+        P.theta2 = law.theta * law.theta;
+        const double wl = std::floor(1048576.0 * (1.0 - 2.0 * law.r_cut / box)) - 1.0;
+        P.wrap_limit = wl < 0.0 ? 0u : (uint32_t)wl;
+        const double rc2 = law.r_cut * law.r_cut;
+        if (law.grid == NGR_GRID_R2) {
+            P.tscale = (float)((law.ntab - 1) / rc2);
+            P.toff = (float)(-P.eps2 * ((law.ntab - 1) / rc2));
+        } else {
+            P.tscale = (float)((law.ntab - 1) / law.r_cut);
+            P.toff = 0.0f;
+        }
+        P.tmax = (float)(law.ntab - 1);
+        for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = 1.5 * law.G[j];   // see eval_records
+        P.acc = accv[k];
+        P.in_off = t.boff[k];
+        P.n = t.boff[k + 1] - t.boff[k];
+        P.D = law.D;
+        P.ntab = law.ntab;
+        P.tab = np;
+        P.tabv = nv;
+        np += law.pair.size();
+        nv += law.value.size();
+    }
+    std::vector<float2> hp(np);
+    std::vector<float> hv(nv);
+    for (uint32_t k = 0; k < nbox; ++k) {
+        std::copy(laws[k].pair.begin(), laws[k].pair.end(), hp.begin() + bp[k].tab);
+        std::copy(laws[k].value.begin(), laws[k].value.end(), hv.begin() + bp[k].tabv);
+    }
+    float2* table = static_cast<float2*>(ctx.alloc(np * sizeof(float2)));
+    float* table_v = static_cast<float*>(ctx.alloc(nv * sizeof(float)));
+    BoxParams* boxes = static_cast<BoxParams*>(ctx.alloc(nbox * sizeof(BoxParams)));
+    ctx.to_device(table, hp.data(), np * sizeof(float2));
+    ctx.to_device(table_v, hv.data(), nv * sizeof(float));
+    ctx.to_device(boxes, bp.data(), nbox * sizeof(BoxParams));
+
+    // segments: first groups, queues, counts and the start schedule (most groups first)
+    const uint32_t nseg = g.nseg;
+    std::vector<uint32_t> sched;
+    for (uint32_t q = 0; q < nseg; ++q)
+        if (g.first[q + 1] > g.first[q]) sched.push_back(q);
+    std::stable_sort(sched.begin(), sched.end(), [&](uint32_t x, uint32_t y) {
+        return g.first[x + 1] - g.first[x] > g.first[y + 1] - g.first[y];
+    });
+    const uint32_t nsched = (uint32_t)sched.size();
+    // control block: seg_counts (2 x nseg u64) | queues (nseg) | cursor | error | seg_first (nseg+1) | sched
+    const size_t cnt_bytes = 2ull * nseg * sizeof(uint64_t);
+    const size_t ctl_words = (size_t)nseg + 2 + (nseg + 1) + nsched;
+    unsigned char* ctl = static_cast<unsigned char*>(ctx.alloc(cnt_bytes + ctl_words * sizeof(uint32_t)));
+    unsigned long long* seg_counts = reinterpret_cast<unsigned long long*>(ctl);
+    uint32_t* queues = reinterpret_cast<uint32_t*>(ctl + cnt_bytes);
+    uint32_t* cursor = queues + nseg;
+    uint32_t* err = cursor + 1;
+    uint32_t* seg_first = err + 1;
+    uint32_t* sched_dev = seg_first + nseg + 1;
+    {
+        std::vector<uint32_t> host((size_t)nseg + 2 + (nseg + 1) + nsched, 0);
+        host[nseg] = std::min<uint32_t>((uint32_t)blocks, nsched);   // cursor: entries the first workgroups take
+        for (uint32_t q = 0; q <= nseg; ++q) host[(size_t)nseg + 2 + q] = (uint32_t)g.first[q];
+        for (uint32_t q = 0; q < nsched; ++q) host[(size_t)nseg + 2 + nseg + 1 + q] = sched[q];
+        HIP_CHECK(hipMemsetAsync(seg_counts, 0, cnt_bytes, ctx.stream));
+        ctx.to_device(queues, host.data(), host.size() * sizeof(uint32_t));
+    }
     ctx.stage("walk: order");
-    uint32_t* order = order_groups(ctx, t, g, law.r_cut);
+    hipEvent_t e0, e1, e2;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventCreate(&e2));
+    HIP_CHECK(hipEventRecord(e0, ctx.stream));
+    uint32_t* order = order_groups(ctx, t, g, laws);
 
     WalkArgs A{};
     A.cell = t.cell;
@@ -823,78 +1000,80 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const Law& law, do
     A.glo = g.lo;
     A.ghi = g.hi;
     A.ng = g.ng;
-    A.order = order;
-    for (uint32_t a = 0; a <= D; ++a) A.first[a] = (uint32_t)g.first[a];
-    A.queues = queues;
     A.D = D;
-    A.ntab = law.ntab;
-    A.table = law.table;
-    A.table_v = law.table_v;
-    for (uint32_t k = 0; k < D * D; ++k) A.G[k] = 1.5 * law.G[k];   // see eval_records
-    A.box = t.box;
-    A.inv_box = 1.0 / t.box;
-    A.eps2 = law.eps * law.eps;
-    {
-        double q = law.r_cut / t.box * 2097152.0;
-        A.R2 = q * q;
-    }
-    A.theta2 = law.theta * law.theta;
-    {
-        double wl = std::floor(1048576.0 * (1.0 - 2.0 * law.r_cut / t.box)) - 1.0;
-        A.wrap_limit = wl < 0.0 ? 0u : (uint32_t)wl;
-    }
-    const double rc2 = law.r_cut * law.r_cut;
-    if (law.grid == NGR_GRID_R2) {
-        A.tscale = (float)((law.ntab - 1) / rc2);
-        A.toff = (float)(-A.eps2 * ((law.ntab - 1) / rc2));
-    } else {
-        A.tscale = (float)((law.ntab - 1) / law.r_cut);
-        A.toff = 0.0f;
-    }
-    A.tmax = (float)(law.ntab - 1);
-    A.acc = acc;
-    A.stats = stats;
+    A.nseg = nseg;
+    A.order = order;
+    A.seg_first = seg_first;
+    A.queues = queues;
+    A.sched = sched_dev;
+    A.nsched = nsched;
+    A.cursor = cursor;
+    A.boxes = boxes;
+    A.table = table;
+    A.table_v = table_v;
+    A.seg_counts = seg_counts;
     A.gcounts = reinterpret_cast<unsigned long long*>(group_counts_dev);
     A.stacks = static_cast<uint32_t*>(ctx.stacks.p);
     A.stack_cap = stack_cap;
     A.error_flag = err;
     A.max_steps = (uint32_t)std::min<uint64_t>(t.nn + 1, 0xffffffffull);
+    A.tab_bytes = (uint32_t)tab_bytes;
 
-    hipEvent_t e0, e1;
-    HIP_CHECK(hipEventCreate(&e0));
-    HIP_CHECK(hipEventCreate(&e1));
-    HIP_CHECK(hipEventRecord(e0, ctx.stream));
-    const bool eps0 = law.eps == 0.0;
+    HIP_CHECK(hipEventRecord(e1, ctx.stream));
     ctx.stage("walk: launch");
+    A.box0 = bp[0];
     auto launch = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(waves * 64), lds, ctx.stream, A);
         LAUNCH_CHECK("walk_kernel");
     };
-    const int sel = (law.grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
+    // a one-box call reads its box's parameters from the kernel arguments
+    const int sel = (nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
     switch (sel) {
-    case 0: launch(walk_kernel<NGR_GRID_R, kPair, false>); break;
-    case 1: launch(walk_kernel<NGR_GRID_R, kPair, true>); break;
-    case 2: launch(walk_kernel<NGR_GRID_R, kValue, false>); break;
-    case 3: launch(walk_kernel<NGR_GRID_R, kValue, true>); break;
-    case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false>); break;
-    case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true>); break;
-    case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false>); break;
-    default: launch(walk_kernel<NGR_GRID_R2, kValue, true>); break;
+    case 0: launch(walk_kernel<NGR_GRID_R, kPair, false, false>); break;
+    case 1: launch(walk_kernel<NGR_GRID_R, kPair, true, false>); break;
+    case 2: launch(walk_kernel<NGR_GRID_R, kValue, false, false>); break;
+    case 3: launch(walk_kernel<NGR_GRID_R, kValue, true, false>); break;
+    case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false, false>); break;
+    case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true, false>); break;
+    case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false, false>); break;
+    case 7: launch(walk_kernel<NGR_GRID_R2, kValue, true, false>); break;
+    case 8: launch(walk_kernel<NGR_GRID_R, kPair, false, true>); break;
+    case 9: launch(walk_kernel<NGR_GRID_R, kPair, true, true>); break;
+    case 10: launch(walk_kernel<NGR_GRID_R, kValue, false, true>); break;
+    case 11: launch(walk_kernel<NGR_GRID_R, kValue, true, true>); break;
+    case 12: launch(walk_kernel<NGR_GRID_R2, kPair, false, true>); break;
+    case 13: launch(walk_kernel<NGR_GRID_R2, kPair, true, true>); break;
+    case 14: launch(walk_kernel<NGR_GRID_R2, kValue, false, true>); break;
+    default: launch(walk_kernel<NGR_GRID_R2, kValue, true, true>); break;
     }
-    HIP_CHECK(hipEventRecord(e1, ctx.stream));
-    uint64_t words[40];
-    ctx.read_words(words, ctx.counters.p, 40);
+    HIP_CHECK(hipEventRecord(e2, ctx.stream));
+    std::vector<uint64_t> counts(2ull * nseg);
+    uint32_t herr = 0;
+    ctx.to_host(counts.data(), seg_counts, cnt_bytes);
+    ctx.to_host(&herr, err, sizeof herr);
     ctx.stage("walk: done");
     ctx.release(order);
-    float ms = 0.0f;
-    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ctx.release(ctl);
+    ctx.release(boxes);
+    ctx.release(table);
+    ctx.release(table_v);
+    float ms_order = 0.0f, ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms_order, e0, e1));
+    HIP_CHECK(hipEventElapsedTime(&ms, e1, e2));
     HIP_CHECK(hipEventDestroy(e0));
     HIP_CHECK(hipEventDestroy(e1));
-    const uint32_t herr = reinterpret_cast<const uint32_t*>(words)[2 * 4];
+    HIP_CHECK(hipEventDestroy(e2));
     if (herr) fail(NGR_ENOMEM, "walk stack or step capacity exceeded");
-    out.pp = words[0];
-    out.pn = words[1];
+    for (uint32_t q = 0; q < nseg; ++q) {
+        out.box_pp[q / D] += counts[2ull * q];
+        out.box_pn[q / D] += counts[2ull * q + 1];
+    }
+    for (uint32_t k = 0; k < nbox; ++k) {
+        out.pp += out.box_pp[k];
+        out.pn += out.box_pn[k];
+    }
     out.ms_walk = ms;
+    out.ms_order = ms_order;
 }
 
 }  // namespace ngr

@@ -1,0 +1,124 @@
+"""Many independent boxes in one call (ngr_batch_build_force): every box's
+accelerations and counts are bitwise those of its single-box calls, its
+counts equal the oracle's and its forces pass the oracle gate."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1502_07442_amd as ngr
+import synth
+from gpu_util import device_inputs, force_gate, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ("interactions_pp", "interactions_pn", "n_nodes", "n_leaves", "n_groups", "group_size", "depth")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ngr.Context(0)
+    yield c
+    c.close()
+
+
+def first_particles(p, n):
+    """The first n particles of p with p's laws and scales (n may be 0 or 1)."""
+    import dataclasses
+    return dataclasses.replace(p, n=n, name=f"{p.name}-first{n}", species=p.species[:n], mass=p.mass[:n],
+                               pos=p.pos[:, :n].copy())
+
+
+def run_batch(ctx, probs, group_sizes):
+    import torch
+    boxes, accs = [], []
+    for p, gs in zip(probs, group_sizes):
+        acc = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
+        boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut,
+                                  eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=gs,
+                                  **device_inputs(p)))
+        accs.append(acc)
+    st, pb = ngr.batch_build_force(ctx, boxes, per_box=True)
+    return st, pb, [a.cpu().numpy() for a in accs]
+
+
+def check_box(ctx, p, acc, stats, oracle_check=True):
+    """Single-box calls give the same bits; the oracle gives the same counts
+    and forces within the gate."""
+    acc1, st1, _, _ = gpu_solve(ctx, p, group_size=stats["group_size"])
+    assert np.array_equal(acc1, acc, equal_nan=True), p.name
+    for k in STAT_KEYS:
+        assert st1[k] == stats[k], (p.name, k, st1[k], stats[k])
+    if not oracle_check:
+        return
+    T = oracle.Tree.of(p, group_size=stats["group_size"])
+    ao, so, co, _ = T.force(oracle.law_of(p))
+    assert (stats["interactions_pp"], stats["interactions_pn"]) == (co["pp"], co["pn"]), p.name
+    assert stats["n_nodes"] == T.n_nodes
+    ok, worst, _, _ = force_gate(acc, ao, so)
+    print(f"  {p.name}: interactions={co['pp'] + co['pn']} worst/allowed={worst:.3g}", flush=True)
+    assert ok, (p.name, worst)
+
+
+def test_mixed_boxes_equal_single_box_calls(ctx):
+    R2 = synth.GRID_R2
+    probs = [synth.uniform_problem(300, 1, 2, grid=R2),
+             synth.clustered_problem(2048, 3, 5, ntab=512),
+             synth.uniform_problem(100, 2, 1, grid=R2, box=2.5),
+             synth.clustered_problem(1500, 6, 7, ntab=256, leaf_size=8),
+             synth.uniform_problem(64, 4, 3, grid=R2),
+             synth.clustered_problem(5000, 2, 9, f_cl=0.8, ntab=1024),
+             first_particles(synth.uniform_problem(64, 1, 4, grid=R2), 1)]
+    probs[4].eps = 0.0                       # one box without softening
+    sizes = [64, 32, 16, 64, 0, 32, 64]
+    print(f"case mixed batch of {len(probs)} boxes", flush=True)
+    st, pb, accs = run_batch(ctx, probs, sizes)
+    assert st["interactions_pp"] == sum(b["interactions_pp"] for b in pb)
+    assert st["interactions_pn"] == sum(b["interactions_pn"] for b in pb)
+    assert st["n_particles"] == sum(p.n for p in probs)
+    for p, acc, b in zip(probs, accs, pb):
+        check_box(ctx, p, acc, b)
+
+
+def test_workload_batch_of_256_boxes(ctx):
+    probs = [synth.batch_box(k) for k in range(256)]
+    print(f"case 256 boxes, {sum(p.n for p in probs)} particles", flush=True)
+    st, pb, accs = run_batch(ctx, probs, [0] * len(probs))
+    assert st["n_particles"] == sum(p.n for p in probs)
+    assert all(np.all(np.isfinite(a)) for a in accs)
+    for k in range(0, 256, 37):
+        check_box(ctx, probs[k], accs[k], pb[k])
+    for k in range(5, 256, 23):
+        check_box(ctx, probs[k], accs[k], pb[k], oracle_check=False)
+
+
+def test_batch_errors(ctx):
+    import torch
+    R2 = synth.GRID_R2
+    good = synth.uniform_problem(200, 2, 11, grid=R2)
+    bad = synth.uniform_problem(200, 2, 12, grid=R2)
+    bad.species = bad.species.copy()
+    bad.species[5] = 3
+    with pytest.raises(ngr.NgravsError) as e:
+        run_batch(ctx, [good, good, bad], [0, 0, 0])
+    assert e.value.status == ngr.EINVAL and "box 2" in str(e.value)
+    other = synth.uniform_problem(200, 2, 13, grid=synth.GRID_R)
+    with pytest.raises(ngr.NgravsError) as e:
+        run_batch(ctx, [good, other], [0, 0])
+    assert e.value.status == ngr.EINVAL
+    with pytest.raises(ngr.NgravsError) as e:
+        run_batch(ctx, [good, good], [0, 48])
+    assert e.value.status == ngr.EINVAL and "box 1" in str(e.value)
+    with pytest.raises(ngr.NgravsError) as e:
+        ngr.batch_build_force(ctx, [])
+    assert e.value.status == ngr.EINVAL
+    # an empty box inside a batch: nothing written for it, the others unchanged
+    empty = first_particles(synth.uniform_problem(64, 2, 14, grid=R2), 0)
+    st, pb, accs = run_batch(ctx, [good, empty, good], [0, 0, 0])
+    assert pb[1]["interactions_pp"] == 0 and pb[1]["n_groups"] == 0
+    assert np.array_equal(accs[0], accs[2])
+    acc1, _, _, _ = gpu_solve(ctx, good, group_size=pb[0]["group_size"])
+    assert np.array_equal(acc1, accs[0])
+    assert torch.cuda.is_available()
