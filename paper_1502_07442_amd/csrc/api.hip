@@ -1,5 +1,6 @@
 // The C-ABI of libngravs: argument checks on the host before any device
 // work, error statuses, and the context's stream and memory.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -83,7 +84,8 @@ void Context::ensure(DevMem& m, size_t bytes)
 void Context::stage(const char* what)
 {
     if (trace) {
-        std::fprintf(stderr, "[ngravs] %s\n", what);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_created).count();
+        std::fprintf(stderr, "[ngravs %10.3f ms] %s\n", ms, what);
         std::fflush(stderr);
     }
 }
@@ -223,6 +225,8 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         ngr::Context& c = *ctx;
         ngr::Groups g;
         std::vector<ngr::Law> laws(1);
+        std::vector<ngr::LawTables> tabs;
+        void* tab_block = nullptr;
         ngr::WalkOut wo;
         uint64_t* gc = nullptr;
         hipEvent_t e0, e1;
@@ -233,12 +237,14 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             ngr::make_groups(c, *tree, std::vector<uint32_t>{gs}, g);
             ngr::hip_check(hipEventRecord(e1, c.stream), "hipEventRecord", __FILE__, __LINE__);
             ngr::make_law(*fp, tree->D, laws[0]);
+            if (tree->n) tab_block = ngr::upload_tables(c, laws, tabs);
             if (group_counts_host && g.ng) gc = static_cast<uint64_t*>(c.alloc(g.ng * 4 * sizeof(uint64_t)));
-            ngr::walk_force(c, *tree, g, laws, std::vector<double*>{acc}, gc, wo);
+            ngr::walk_force(c, *tree, g, laws, tabs, std::vector<double*>{acc}, gc, wo);
             if (gc) c.to_host(group_counts_host, gc, g.ng * 4 * sizeof(uint64_t));
             c.sync();
         } catch (...) {
             c.release(gc);
+            c.release(tab_block);
             g.free(c);
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
@@ -261,6 +267,7 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             st->ms_walk = wo.ms_walk;
         }
         c.release(gc);
+        c.release(tab_block);
         g.free(c);
     });
 }
@@ -490,6 +497,8 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
         ngr::Tree t;
         ngr::Groups g;
         ngr::WalkOut wo;
+        std::vector<ngr::LawTables> tabs;
+        void* tab_block = nullptr;
         std::vector<uint64_t> bnodes, bleaves;
         std::vector<uint32_t> bdepth;
         hipEvent_t ev[4];
@@ -505,13 +514,15 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
             ngr::hip_check(hipEventRecord(ev[2], c.stream), "hipEventRecord", __FILE__, __LINE__);
             ngr::make_groups(c, t, gs, g);
             ngr::hip_check(hipEventRecord(ev[3], c.stream), "hipEventRecord", __FILE__, __LINE__);
-            ngr::walk_force(c, t, g, laws, acc, nullptr, wo);
+            tab_block = ngr::upload_tables(c, laws, tabs);
+            ngr::walk_force(c, t, g, laws, tabs, acc, nullptr, wo);
             if (per_box) ngr::box_node_counts(c, t, bnodes, bleaves, bdepth);
             c.sync();
         } catch (...) {
             try {
                 ngr::free_tree(c, t);
                 g.free(c);
+                c.release(tab_block);
             } catch (...) {
             }
             destroy();
@@ -549,5 +560,6 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
         }
         ngr::free_tree(c, t);
         g.free(c);
+        c.release(tab_block);
     });
 }

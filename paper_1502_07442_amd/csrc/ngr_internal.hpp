@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -47,6 +48,7 @@ struct Context {
     int num_cu = 0;
     size_t lds_per_block = 0;
     bool trace = false;
+    std::chrono::steady_clock::time_point t_created = std::chrono::steady_clock::now();
     std::string err;
     std::multimap<size_t, void*> free_blocks;     // size class -> block
     std::map<void*, size_t> live_blocks;          // block -> size class
@@ -166,15 +168,28 @@ struct Groups {
 // group_size: per box, 16, 32 or 64
 void make_groups(Context& ctx, const Tree& t, const std::vector<uint32_t>& group_size, Groups& g);
 
-// Force law and walk parameters of one box.
+// Force law and walk parameters of one box. The tables stay where the
+// caller keeps them (host) until upload_tables.
 struct Law {
     uint32_t D = 0, ntab = 0, grid = 0;
     double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
     double r_cut = 0, eps = 0, theta = 0;
-    std::vector<float2> pair;      // host, D x D x ntab (value, slope to next), last = (0, 0)
-    std::vector<float> value;      // host, D x D x (ntab + 1) samples plus a zero pad
+    const double* tables = nullptr;   // host, D x D x ntab samples, or NULL: def for every pair
+    std::vector<double> def;          // host, ntab samples of the Newtonian short-range factor
 };
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
+
+// A box's tables on the device in both LDS layouts (see the walk): PAIR,
+// D x D x ntab (value, slope to the next sample) with a (0, 0) last entry;
+// VALUE, D x D x (ntab + 1) samples and a zero pad.
+struct LawTables {
+    const float2* pair = nullptr;
+    const float* value = nullptr;
+};
+// Upload and convert the tables of every law (one conversion launch). The
+// returned memory block holds all of them; release it after the last walk
+// that uses them.
+void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawTables>& out);
 
 struct WalkOut {
     uint64_t pp = 0, pn = 0;
@@ -183,6 +198,7 @@ struct WalkOut {
 };
 // laws and acc: one per box of the tree; acc[k] is box k's 3 x n_k output.
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
-                const std::vector<double*>& acc, uint64_t* group_counts_dev, WalkOut& out);
+                const std::vector<LawTables>& tables, const std::vector<double*>& acc, uint64_t* group_counts_dev,
+                WalkOut& out);
 
 }  // namespace ngr

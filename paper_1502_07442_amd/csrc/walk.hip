@@ -241,7 +241,8 @@ struct BoxParams {
     double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // 1.5 G_ab, row a = sink species, D x D
     double* acc;               // 3 x n output, input order
     uint64_t in_off, n;        // first input index (over all boxes) and particles of the box
-    uint64_t tab, tabv;        // first entry of the box's tables in the PAIR (float2) and VALUE (float) arrays
+    const float2* pair;        // the box's tables, PAIR layout
+    const float* value;        // the box's tables, VALUE layout
     float tscale, toff, tmax;
     uint32_t wrap_limit, D, ntab;
 };
@@ -278,8 +279,6 @@ struct WalkArgs {
     uint32_t nsched;
     uint32_t* cursor;          // next entry of sched to start
     const BoxParams* boxes;
-    const float2* table;       // PAIR layout of every box
-    const float* table_v;      // VALUE layout of every box
     unsigned long long* seg_counts;   // nseg x 2: pp and pn interactions of each segment
     unsigned long long* gcounts;
     uint32_t* stacks;
@@ -404,11 +403,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         const uint32_t tstride = TAB == kPair ? ntab : ntab + 1;   // entries per table
         if (TAB == kPair) {
             float2* tab = reinterpret_cast<float2*>(tsm);
-            const float2* src = A.table + P.tab + (uint64_t)a * Dk * ntab;
+            const float2* src = P.pair + (uint64_t)a * Dk * ntab;
             for (uint32_t k = threadIdx.x; k < Dk * ntab; k += blockDim.x) tab[k] = src[k];
         } else {
             float* tab = reinterpret_cast<float*>(tsm);
-            const float* src = A.table_v + P.tabv + (uint64_t)a * Dk * (ntab + 1);
+            const float* src = P.value + (uint64_t)a * Dk * (ntab + 1);
             for (uint32_t k = threadIdx.x; k < Dk * (ntab + 1); k += blockDim.x) tab[k] = src[k];
         }
         __syncthreads();
@@ -699,6 +698,38 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 
 inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
 
+// One box's table conversion: where its FP64 samples are and where its two
+// layouts go.
+struct TableJob {
+    uint64_t raw, pair, value;   // first element in the raw, PAIR and VALUE arrays
+    uint32_t pairs, ntab;        // D * D tables of ntab samples
+    uint32_t shared;             // 1: one table of ntab samples for every pair
+    uint32_t pad;
+};
+
+// Both layouts of every table of box blockIdx.y (grid-stride over the box's
+// D * D * ntab entries): PAIR (value, slope to the next sample) with (0, 0)
+// as the last entry; VALUE the samples and a zero pad. Each float is the FP64
+// value (or difference) rounded once.
+__global__ void convert_tables(const TableJob* __restrict__ jobs, const double* __restrict__ raw,
+                               float2* __restrict__ pair, float* __restrict__ value)
+{
+    const TableJob J = jobs[blockIdx.y];
+    const uint64_t total = (uint64_t)J.pairs * J.ntab;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // the trip count is the same for every lane (the bound test is inside)
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const uint64_t e = base + threadIdx.x;
+        if (e >= total) continue;
+        const uint64_t ab = e / J.ntab, k = e % J.ntab;
+        const double* src = raw + J.raw + (J.shared ? 0 : ab * J.ntab);
+        pair[J.pair + e] = k + 1 < J.ntab ? make_float2((float)src[k], (float)(src[k + 1] - src[k]))
+                                          : make_float2(0.0f, 0.0f);
+        value[J.value + ab * (J.ntab + 1) + k] = (float)src[k];
+        if (k + 1 == J.ntab) value[J.value + ab * (J.ntab + 1) + J.ntab] = 0.0f;
+    }
+}
+
 }  // namespace
 
 void Groups::free(Context& ctx)
@@ -773,9 +804,6 @@ void make_groups(Context& ctx, const Tree& t, const std::vector<uint32_t>& group
     ctx.release(first_dev);
 }
 
-// Tables of every pair (a, b), in both LDS layouts (see TableMode): PAIR as
-// (value, slope to the next sample) for the ntab - 1 intervals plus a (0, 0)
-// entry; VALUE as the ntab samples plus a zero pad.
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
 {
     law.D = D;
@@ -785,29 +813,68 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.eps = fp.eps;
     law.theta = fp.theta;
     for (uint32_t k = 0; k < D * D; ++k) law.G[k] = fp.G[k];
-    const uint32_t ntab = fp.ntab;
-    std::vector<double> def;
-    const double* T = fp.tables;
-    if (!T) {
-        def.resize((size_t)ntab);
+    law.tables = fp.tables;
+    law.def.clear();
+    if (!fp.tables) {
+        const uint32_t ntab = fp.ntab;
+        law.def.resize((size_t)ntab);
         for (uint32_t k = 0; k < ntab; ++k) {
             double r = fp.grid == NGR_GRID_R ? k * (fp.r_cut / (ntab - 1))
                                              : std::sqrt(k * (fp.r_cut * fp.r_cut / (ntab - 1)));
             double x = r / (2.0 * fp.r_s);
-            def[k] = std::erfc(x) + r / (fp.r_s * std::sqrt(M_PI)) * std::exp(-x * x);
+            law.def[k] = std::erfc(x) + r / (fp.r_s * std::sqrt(M_PI)) * std::exp(-x * x);
         }
     }
-    law.pair.resize((size_t)D * D * ntab);
-    law.value.resize((size_t)D * D * (ntab + 1));
-    for (uint32_t ab = 0; ab < D * D; ++ab) {
-        const double* src = T ? T + (size_t)ab * ntab : def.data();
-        float2* dp = law.pair.data() + (size_t)ab * ntab;
-        float* dv = law.value.data() + (size_t)ab * (ntab + 1);
-        for (uint32_t k = 0; k + 1 < ntab; ++k) dp[k] = make_float2((float)src[k], (float)(src[k + 1] - src[k]));
-        dp[ntab - 1] = make_float2(0.0f, 0.0f);
-        for (uint32_t k = 0; k < ntab; ++k) dv[k] = (float)src[k];
-        dv[ntab] = 0.0f;
+}
+
+void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawTables>& out)
+{
+    const uint32_t nbox = (uint32_t)laws.size();
+    std::vector<TableJob> jobs(nbox);
+    uint64_t nraw = 0, np = 0, nv = 0;
+    uint32_t max_entries = 0;
+    for (uint32_t k = 0; k < nbox; ++k) {
+        const Law& L = laws[k];
+        TableJob& j = jobs[k];
+        j.pairs = L.D * L.D;
+        j.ntab = L.ntab;
+        j.shared = L.tables ? 0u : 1u;
+        j.raw = nraw;
+        j.pair = np;
+        j.value = nv;
+        nraw += L.tables ? (uint64_t)j.pairs * L.ntab : L.ntab;
+        np += (uint64_t)j.pairs * L.ntab;
+        nv += (uint64_t)j.pairs * (L.ntab + 1);
+        max_entries = std::max(max_entries, j.pairs * L.ntab);
     }
+    const size_t raw_bytes = nraw * sizeof(double), job_bytes = nbox * sizeof(TableJob);
+    const size_t pair_bytes = ((np * sizeof(float2)) + 255) & ~size_t(255);
+    const size_t value_bytes = ((nv * sizeof(float)) + 255) & ~size_t(255);
+    unsigned char* block = static_cast<unsigned char*>(ctx.alloc(pair_bytes + value_bytes));
+    float2* pair = reinterpret_cast<float2*>(block);
+    float* value = reinterpret_cast<float*>(block + pair_bytes);
+    unsigned char* stage = static_cast<unsigned char*>(ctx.alloc(raw_bytes + job_bytes));
+    double* raw = reinterpret_cast<double*>(stage);
+    TableJob* jobs_dev = reinterpret_cast<TableJob*>(stage + raw_bytes);
+    ctx.sync();
+    for (uint32_t k = 0; k < nbox; ++k) {
+        const Law& L = laws[k];
+        const double* src = L.tables ? L.tables : L.def.data();
+        const size_t cnt = L.tables ? (size_t)jobs[k].pairs * L.ntab : L.ntab;
+        HIP_CHECK(hipMemcpyAsync(raw + jobs[k].raw, src, cnt * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+    }
+    HIP_CHECK(hipMemcpyAsync(jobs_dev, jobs.data(), job_bytes, hipMemcpyHostToDevice, ctx.stream));
+    const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(max_entries, 256), 64));
+    hipLaunchKernelGGL(convert_tables, dim3(gx, nbox), dim3(256), 0, ctx.stream, jobs_dev, raw, pair, value);
+    LAUNCH_CHECK("convert_tables");
+    ctx.sync();                        // the caller's host tables are no longer read after this
+    ctx.release(stage);
+    out.resize(nbox);
+    for (uint32_t k = 0; k < nbox; ++k) {
+        out[k].pair = pair + jobs[k].pair;
+        out[k].value = value + jobs[k].value;
+    }
+    return block;
 }
 
 // Group indices segment by segment, each segment's groups in descending
@@ -866,7 +933,8 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
 }
 
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
-                const std::vector<double*>& accv, uint64_t* group_counts_dev, WalkOut& out)
+                const std::vector<LawTables>& tables, const std::vector<double*>& accv, uint64_t* group_counts_dev,
+                WalkOut& out)
 {
     out = WalkOut{};
     const uint32_t nbox = t.nbox, D = t.D;
@@ -899,9 +967,8 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
     ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
 
-    // per-box parameters and the tables of every box, concatenated
+    // per-box parameters
     std::vector<BoxParams> bp(nbox);
-    uint64_t np = 0, nv = 0;
     for (uint32_t k = 0; k < nbox; ++k) {
         const Law& law = laws[k];
         BoxParams& P = bp[k];
@@ -930,22 +997,10 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         P.n = t.boff[k + 1] - t.boff[k];
         P.D = law.D;
         P.ntab = law.ntab;
-        P.tab = np;
-        P.tabv = nv;
-        np += law.pair.size();
-        nv += law.value.size();
+        P.pair = tables[k].pair;
+        P.value = tables[k].value;
     }
-    std::vector<float2> hp(np);
-    std::vector<float> hv(nv);
-    for (uint32_t k = 0; k < nbox; ++k) {
-        std::copy(laws[k].pair.begin(), laws[k].pair.end(), hp.begin() + bp[k].tab);
-        std::copy(laws[k].value.begin(), laws[k].value.end(), hv.begin() + bp[k].tabv);
-    }
-    float2* table = static_cast<float2*>(ctx.alloc(np * sizeof(float2)));
-    float* table_v = static_cast<float*>(ctx.alloc(nv * sizeof(float)));
     BoxParams* boxes = static_cast<BoxParams*>(ctx.alloc(nbox * sizeof(BoxParams)));
-    ctx.to_device(table, hp.data(), np * sizeof(float2));
-    ctx.to_device(table_v, hv.data(), nv * sizeof(float));
     ctx.to_device(boxes, bp.data(), nbox * sizeof(BoxParams));
 
     // segments: first groups, queues, counts and the start schedule (most groups first)
@@ -1009,8 +1064,6 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     A.nsched = nsched;
     A.cursor = cursor;
     A.boxes = boxes;
-    A.table = table;
-    A.table_v = table_v;
     A.seg_counts = seg_counts;
     A.gcounts = reinterpret_cast<unsigned long long*>(group_counts_dev);
     A.stacks = static_cast<uint32_t*>(ctx.stacks.p);
@@ -1055,8 +1108,6 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     ctx.release(order);
     ctx.release(ctl);
     ctx.release(boxes);
-    ctx.release(table);
-    ctx.release(table_v);
     float ms_order = 0.0f, ms = 0.0f;
     HIP_CHECK(hipEventElapsedTime(&ms_order, e0, e1));
     HIP_CHECK(hipEventElapsedTime(&ms, e1, e2));
