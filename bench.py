@@ -100,6 +100,127 @@ def batched(ngr, synth, nbox=256, reps=3):
             "group_size": "library choice (32)"}
 
 
+def served(ngr, synth, nreq=200, warm=25, steps=8, dt=1e-3, loads=(0.5, 0.9)):
+    """The served workload: requests of `steps` kick-drift-kick steps on new
+    boxes (N log-uniform in [2^14, 2^20], D in 1..6), advanced by one request
+    server, one force evaluation of every admitted request per tick. The
+    saturated rate comes from submitting every request at once; Poisson
+    streams at fractions of it give latencies (arrival to completion; the
+    first `warm` requests are not counted). Baseline: the same requests one
+    at a time (FIFO) through the single-box calls, each one's service time
+    measured alone and queued on the same arrival times."""
+    import numpy as np
+    import torch
+    probs = [synth.serve_request(r) for r in range(nreq)]
+    dev = torch.device("cuda", 0)
+    inputs = [dict(species=torch.from_numpy(np.ascontiguousarray(q.species, np.uint8)).to(dev),
+                   mass=torch.from_numpy(q.mass).to(dev), pos=torch.from_numpy(q.pos).to(dev)) for q in probs]
+    torch.cuda.synchronize()
+    ctx = ngr.Context(0)
+
+    def submit(srv, j):
+        q = probs[j]
+        return srv.submit(D=q.D, box=q.box, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps,
+                          theta=q.theta, r_s=q.r_s, dt=dt, steps=steps, leaf_size=q.leaf_size, group_size=0,
+                          **inputs[j])
+
+    def drive(arrivals):
+        """Submit at the arrival times (None: all at once), tick while there is
+        work; returns completion times (s from the start) and tick count."""
+        srv = ngr.Server(ctx)
+        done, ids, k, ticks = {}, {}, 0, 0
+        t0 = time.perf_counter()
+        while len(done) < nreq:
+            now = time.perf_counter() - t0
+            while k < nreq and (arrivals is None or arrivals[k] <= now):
+                ids[k] = submit(srv, k)
+                k += 1
+            if not ids:
+                time.sleep(max(0.0, min(arrivals[k] - now, 0.01)))
+                continue
+            srv.tick()
+            ticks += 1
+            t = time.perf_counter() - t0
+            for j, rid in list(ids.items()):
+                if srv.status(rid)[0] == ngr.FINISHED:
+                    srv.take(rid)
+                    done[j] = t
+                    del ids[j]
+        srv.close()
+        return np.array([done[j] for j in range(nreq)]), ticks
+
+    comp, ticks = drive(None)
+    sat_s = float(comp.max())
+    sat_rate = nreq / sat_s
+
+    # baseline service times: each request alone through the single-box calls,
+    # from its lattice (the library's conversion of its positions, taken
+    # before timing)
+    def lattice0(j):
+        q = probs[j]
+        tree = ngr.tree_build(ctx, D=q.D, box=q.box, leaf_size=q.leaf_size, **inputs[j])
+        ex = ngr.tree_export(ctx, tree)
+        ngr.tree_free(ctx, tree)
+        X = np.empty((3, q.n), np.uint64)
+        X[:, ex["perm"]] = ex["lattice"]
+        return torch.from_numpy(X.view(np.int64)).to(dev)
+
+    def alone(j):
+        q = probs[j]
+        h = 0.5 * dt
+        X = lattice0(j)
+
+        def force(lat):
+            tree = ngr.tree_build(ctx, D=q.D, box=q.box, leaf_size=q.leaf_size, species=inputs[j]["species"],
+                                  mass=inputs[j]["mass"], lattice=lat)
+            ngr.compute_monopoles(ctx, tree)
+            a = torch.empty((3, q.n), dtype=torch.float64, device=dev)
+            ngr.tree_force(ctx, tree, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps, theta=q.theta,
+                           r_s=q.r_s, group_size=0, acc=a)
+            ngr.tree_free(ctx, tree)
+            return a
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = force(X)
+        v = torch.zeros_like(a)
+        for _ in range(steps):
+            v.add_(a, alpha=h)
+            d = v * (dt / q.box)
+            d -= torch.round(d)
+            d.clamp_(-0.5, 0.5 - 2.0 ** -53)
+            X += (d * 2.0 ** 64).to(torch.int64)
+            a = force(X)
+            v.add_(a, alpha=h)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    service = np.array([alone(j) for j in range(nreq)])
+    out = {"workload": f"requests of {steps} kick-drift-kick steps (dt {dt}) on new clustered boxes: N log-uniform "
+                       f"in [2^14, 2^20], D in 1..6, laws of their own; Poisson arrivals",
+           "requests": nreq, "warmup_requests": warm, "steps_per_request": steps,
+           "particles_mean": float(np.mean([q.n for q in probs])),
+           "saturated": {"requests_per_s": sat_rate, "steps_per_s": steps * nreq / sat_s, "ticks": ticks},
+           "fifo_service_ms_mean": float(service.mean() * 1e3)}
+    for f in loads:
+        rate = f * sat_rate
+        arr = synth.poisson_arrivals(nreq, rate, seed=5)
+        comp, ticks = drive(arr)
+        lat = (comp - arr)[warm:] * 1e3
+        fin = np.empty(nreq)
+        t = 0.0
+        for j in range(nreq):                       # FIFO queue on the same arrivals
+            t = max(t, arr[j]) + service[j]
+            fin[j] = t
+        flat = (fin - arr)[warm:] * 1e3
+        out[f"load_{f}"] = {"rate_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                            "p99_ms": float(np.percentile(lat, 99)),
+                            "steps_per_s": steps * (nreq - warm) / float(comp[warm:].max() - arr[warm]),
+                            "fifo_p50_ms": float(np.percentile(flat, 50)), "fifo_p99_ms": float(np.percentile(flat, 99))}
+    ctx.close()
+    return out
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -137,6 +258,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
@@ -210,6 +333,10 @@ def main():
         log("many-box workload: one batched call against the single-box loop")
         out["batched"] = batched(ngr, synth)
         log(f"batched: {out['batched']['ms_per_batch']:.1f} ms per batch, loop {out['batched']['loop_ms']:.1f} ms")
+    if not args.no_served:
+        log(f"served workload: {args.serve_requests} requests")
+        out["served"] = served(ngr, synth, nreq=args.serve_requests)
+        log("served: " + json.dumps({k: v for k, v in out["served"].items() if k.startswith(("load", "satur"))}))
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(p, inter, args.cpu_seconds)

@@ -270,6 +270,77 @@ typedef struct {
 ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes,
                                  ngr_batch_stats* st, ngr_force_stats* per_box);
 
+/* ---- served requests ---- */
+
+typedef struct ngr_server ngr_server;
+
+/* hbm_budget: device bytes the server may hold for admitted requests plus
+ * the trees of one tick (0 means 200e9); max_active: admitted requests at
+ * most (0: no limit). */
+typedef struct {
+    uint64_t hbm_budget;
+    uint32_t max_active;
+} ngr_server_params;
+
+/* One request: a box, its initial state, its law and a number of
+ * kick-drift-kick leapfrog steps of length dt. The state is the 64-bit
+ * lattice X (positions X * 2^-64 * box), velocities (box units per time) and
+ * the short-range accelerations of this library's force. steps K means K + 1
+ * force evaluations: a(X0), then per step v += a dt/2, X += v dt (wrapping in
+ * the periodic box), a = a(X), v += a dt/2.
+ *   particles  device arrays, copied at submit (pos or lattice)
+ *   vel        device 3 x n float64 initial velocities, copied, or NULL for 0
+ *   tree, force  as the single-box calls; host arrays copied at submit
+ *   dt > 0 and finite; steps 0..2^20 */
+typedef struct {
+    ngr_particles particles;
+    const double* vel;
+    ngr_tree_params tree;
+    ngr_force_params force;
+    double dt;
+    uint32_t steps;
+} ngr_request;
+
+/* What one tick did (host). */
+typedef struct {
+    uint32_t admitted;        /* requests admitted at the start of the tick */
+    uint32_t evaluated;       /* requests that got a force evaluation */
+    uint32_t finished;        /* requests that finished in this tick */
+    uint32_t active;          /* admitted and not finished, after the tick */
+    uint32_t pending;         /* submitted and not admitted, after the tick */
+    uint64_t particles;       /* particles of the tick's force evaluation */
+    uint64_t interactions;    /* pp + pn interactions of the tick */
+    uint64_t resident_bytes;  /* device bytes held for admitted requests */
+    double ms;                /* GPU time of the tick (hipEvents) */
+} ngr_tick_stats;
+
+/*
+ * A request server on a context (continuous batching). Requests wait in
+ * submission order; a tick admits the waiting ones that fit the HBM budget
+ * (in order, stopping at the first that does not fit), then runs one
+ * kick-drift, one force evaluation of every admitted request as one batch
+ * (ngr_batch_build_force's engine) and one kick, and marks the requests whose
+ * last force evaluation it was as finished. A request's trajectory does not
+ * depend on which other requests share its ticks: it is bitwise the one it
+ * has alone. The server runs on the context's stream; calls return after
+ * their work is complete. Not thread safe.
+ */
+ngr_status ngr_server_create(ngr_context* ctx, const ngr_server_params* sp, ngr_server** out);
+/* Submit a request: checks it (NGR_EINVAL as the single-box calls), copies its
+ * data and uploads its tables; *id identifies it. NGR_ENOMEM if it can never
+ * fit the budget. */
+ngr_status ngr_server_submit(ngr_server* s, const ngr_request* r, uint64_t* id);
+/* One tick (see above). With nothing admitted or waiting it does nothing. */
+ngr_status ngr_server_tick(ngr_server* s, ngr_tick_stats* st);
+/* state: 0 waiting, 1 admitted, 2 finished; evals: force evaluations done.
+ * NGR_EINVAL for an unknown (or taken) id. */
+ngr_status ngr_server_status(const ngr_server* s, uint64_t id, int* state, uint32_t* evals);
+/* Copy a finished request's final state to caller device arrays (any may be
+ * NULL): lattice 3 x n uint64, vel 3 x n float64, acc 3 x n float64; then
+ * release the request. NGR_ESTATE if it has not finished. */
+ngr_status ngr_server_take(ngr_server* s, uint64_t id, uint64_t* lattice, double* vel, double* acc);
+void ngr_server_destroy(ngr_server* s);
+
 #ifdef __cplusplus
 }
 #endif

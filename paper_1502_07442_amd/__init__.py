@@ -23,7 +23,8 @@ MAX_SPECIES = 6
 EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_tree_build",
             "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_free",
             "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
-            "ngr_batch_build_force"]
+            "ngr_batch_build_force", "ngr_server_create", "ngr_server_submit", "ngr_server_tick",
+            "ngr_server_status", "ngr_server_take", "ngr_server_destroy"]
 
 
 class NgravsError(RuntimeError):
@@ -60,6 +61,24 @@ class Box(C.Structure):
     _fields_ = [("particles", Particles), ("tree", TreeParams), ("force", ForceParams), ("acc", C.c_void_p)]
 
 
+class RequestDesc(C.Structure):
+    _fields_ = [("particles", Particles), ("vel", C.c_void_p), ("tree", TreeParams), ("force", ForceParams),
+                ("dt", C.c_double), ("steps", C.c_uint32)]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_active", C.c_uint32)]
+
+
+class TickStats(C.Structure):
+    _fields_ = [("admitted", C.c_uint32), ("evaluated", C.c_uint32), ("finished", C.c_uint32), ("active", C.c_uint32),
+                ("pending", C.c_uint32), ("particles", C.c_uint64), ("interactions", C.c_uint64),
+                ("resident_bytes", C.c_uint64), ("ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BatchStats(C.Structure):
     _fields_ = [("n_particles", C.c_uint64), ("n_nodes", C.c_uint64), ("n_groups", C.c_uint64),
                 ("interactions_pp", C.c_uint64), ("interactions_pn", C.c_uint64), ("ms_build", C.c_double),
@@ -94,6 +113,12 @@ def lib():
             "ngr_monopoles_export": (i32, [P] * 4),
             "ngr_groups_export": (i32, [P, P, u32, P, P, P, P, P, P]),
             "ngr_batch_build_force": (i32, [P, u32, P, P, P]),
+            "ngr_server_create": (i32, [P, P, P]),
+            "ngr_server_submit": (i32, [P, P, P]),
+            "ngr_server_tick": (i32, [P, P]),
+            "ngr_server_status": (i32, [P, u64, P, P]),
+            "ngr_server_take": (i32, [P, u64, P, P, P]),
+            "ngr_server_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -279,3 +304,56 @@ def batch_build_force(ctx: Context, boxes, per_box: bool = False):
     if per_box:
         return st.as_dict(), [pb[k].as_dict() for k in range(len(boxes))]
     return st.as_dict()
+
+
+WAITING, ADMITTED, FINISHED = 0, 1, 2
+
+
+class Server:
+    """ngr_server_*: requests of leapfrog steps on many boxes, advanced
+    together one force evaluation per tick (continuous batching)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 0, max_active: int = 0):
+        self.ctx = ctx
+        self._h = C.c_void_p()
+        sp = ServerParams(int(hbm_budget), int(max_active))
+        ctx._check(lib().ngr_server_create(ctx.handle, C.byref(sp), C.byref(self._h)), "server create")
+
+    def submit(self, *, D, box, species, mass, G, tables, grid, r_cut, eps, theta, dt, steps, pos=None, lattice=None,
+               vel=None, leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None) -> int:
+        """Device tensors species, mass, pos or lattice, vel (or None); host G
+        and tables. The data are copied; returns the request id."""
+        n = int(species.shape[0])
+        rq = RequestDesc(Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass)), _dev(vel),
+                         TreeParams(leaf_size), _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab),
+                         float(dt), int(steps))
+        rid = C.c_uint64()
+        self.ctx._check(lib().ngr_server_submit(self._h, C.byref(rq), C.byref(rid)), "server submit")
+        return rid.value
+
+    def tick(self) -> dict:
+        st = TickStats()
+        self.ctx._check(lib().ngr_server_tick(self._h, C.byref(st)), "server tick")
+        return st.as_dict()
+
+    def status(self, rid: int):
+        state, evals = C.c_int(), C.c_uint32()
+        self.ctx._check(lib().ngr_server_status(self._h, rid, C.byref(state), C.byref(evals)), "server status")
+        return state.value, evals.value
+
+    def take(self, rid: int, lattice=None, vel=None, acc=None):
+        """Copy a finished request's lattice (uint64 as int64), velocities and
+        accelerations (device tensors, 3 x n, any may be None) and release it."""
+        self.ctx._check(lib().ngr_server_take(self._h, rid, C.c_void_p(_dev(lattice)), C.c_void_p(_dev(vel)),
+                                              C.c_void_p(_dev(acc))), "server take")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ngr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

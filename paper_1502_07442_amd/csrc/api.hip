@@ -13,6 +13,10 @@
 
 struct ngr_context : ngr::Context {};
 struct ngr_tree : ngr::Tree {};
+struct ngr_server {
+    ngr_context* ctx;
+    ngr::Server* impl;
+};
 
 namespace ngr {
 
@@ -127,31 +131,10 @@ void Context::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchro
 
 }  // namespace ngr
 
-namespace {
-
-template <class F>
-ngr_status guarded(ngr_context* ctx, F&& f)
-{
-    if (!ctx) return NGR_EINVAL;
-    if (ctx->poisoned) return NGR_EDEVICE;
-    try {
-        ngr::hip_check(hipSetDevice(ctx->device), "hipSetDevice", __FILE__, __LINE__);
-        f();
-        ctx->err.clear();
-        return NGR_OK;
-    } catch (const ngr::Error& e) {
-        ctx->err = e.msg;
-        if (e.status == NGR_EDEVICE) ctx->poisoned = true;
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        ctx->err = "host memory exhausted";
-        return NGR_ENOMEM;
-    }
-}
+namespace ngr {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-void free_tree_memory(ngr::Context& c, ngr::Tree& t) { ngr::free_tree(c, t); }
 
 // Checks of one box's force parameters (D species, box side); returns the
 // group size (0 resolved by the caller's rule).
@@ -163,11 +146,11 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     if (fp->ntab < 2) fail(NGR_EINVAL, where + "ntab must be >= 2");
     if ((uint64_t)D * fp->ntab > NGR_MAX_TABLE) fail(NGR_EINVAL, where + "D * ntab exceeds NGR_MAX_TABLE");
     if (fp->grid != NGR_GRID_R && fp->grid != NGR_GRID_R2) fail(NGR_EINVAL, where + "grid must be NGR_GRID_R or NGR_GRID_R2");
-    if (!finite_pos(fp->r_cut)) fail(NGR_EINVAL, where + "r_cut must be finite and > 0");
+    if (!ngr::finite_pos(fp->r_cut)) fail(NGR_EINVAL, where + "r_cut must be finite and > 0");
     if (!(fp->r_cut < 0.5 * box)) fail(NGR_EINVAL, where + "r_cut must be < box / 2");
     if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, where + "eps must be finite and >= 0");
-    if (!finite_pos(fp->theta)) fail(NGR_EINVAL, where + "theta must be finite and > 0");
-    if (!fp->tables && !finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
+    if (!ngr::finite_pos(fp->theta)) fail(NGR_EINVAL, where + "theta must be finite and > 0");
+    if (!fp->tables && !ngr::finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
     const uint32_t gs = fp->group_size;
     if (gs != 0 && gs != 16 && gs != 32 && gs != 64) fail(NGR_EINVAL, where + "group_size must be 16, 32 or 64 (or 0)");
     for (uint32_t k = 0; k < D * D; ++k)
@@ -194,7 +177,7 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
     using ngr::fail;
     if (!p) fail(NGR_EINVAL, where + "particles are NULL");
     if (p->D < 1 || p->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, where + "D must be in 1..6");
-    if (!finite_pos(p->box)) fail(NGR_EINVAL, where + "box must be finite and > 0");
+    if (!ngr::finite_pos(p->box)) fail(NGR_EINVAL, where + "box must be finite and > 0");
     if (p->n >= (1ull << 32) - 1) fail(NGR_EINVAL, where + "n must be < 2^32 - 1");
     const uint32_t B = tp && tp->leaf_size ? tp->leaf_size : 16;
     if (B > 64) fail(NGR_EINVAL, where + "leaf_size must be in 1..64");
@@ -212,6 +195,32 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
     b.mass = p->mass;
 }
 
+}  // namespace ngr
+
+namespace {
+
+void free_tree_memory(ngr::Context& c, ngr::Tree& t) { ngr::free_tree(c, t); }
+
+template <class F>
+ngr_status guarded(ngr_context* ctx, F&& f)
+{
+    if (!ctx) return NGR_EINVAL;
+    if (ctx->poisoned) return NGR_EDEVICE;
+    try {
+        ngr::hip_check(hipSetDevice(ctx->device), "hipSetDevice", __FILE__, __LINE__);
+        f();
+        ctx->err.clear();
+        return NGR_OK;
+    } catch (const ngr::Error& e) {
+        ctx->err = e.msg;
+        if (e.status == NGR_EDEVICE) ctx->poisoned = true;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host memory exhausted";
+        return NGR_ENOMEM;
+    }
+}
+
 ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
                       ngr_force_stats* st, uint64_t* group_counts_host)
 {
@@ -219,8 +228,8 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         using ngr::fail;
         if (!tree) fail(NGR_EINVAL, "tree is NULL");
         if (!tree->has_monopoles) fail(NGR_ESTATE, "ngr_compute_monopoles must precede ngr_tree_force");
-        uint32_t gs = check_force_params(tree->D, tree->box, fp, "");
-        if (!gs) gs = chosen_group_size(tree->n, tree->D);
+        uint32_t gs = ngr::check_force_params(tree->D, tree->box, fp, "");
+        if (!gs) gs = ngr::chosen_group_size(tree->n, tree->D);
         if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
         ngr::Context& c = *ctx;
         ngr::Groups g;
@@ -323,7 +332,7 @@ NGR_API ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p, cons
         using ngr::fail;
         if (!p || !out) fail(NGR_EINVAL, "particles or out is NULL");
         std::vector<ngr::BoxIn> boxes(1);
-        check_particles(p, tp, "", boxes[0]);
+        ngr::check_particles(p, tp, "", boxes[0]);
         ngr_tree* t = new ngr_tree();
         try {
             ngr::build_forest(*ctx, boxes, *t);
@@ -448,7 +457,7 @@ NGR_API ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree, uin
 {
     return guarded(ctx, [&] {
         if (!tree || !n_groups) ngr::fail(NGR_EINVAL, "tree or n_groups is NULL");
-        uint32_t gs = group_size ? group_size : chosen_group_size(tree->n, tree->D);
+        uint32_t gs = group_size ? group_size : ngr::chosen_group_size(tree->n, tree->D);
         if (gs != 16 && gs != 32 && gs != 64) ngr::fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
         ngr::Groups g;
         try {
@@ -485,9 +494,9 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
         std::vector<double*> acc(nbox);
         for (uint32_t k = 0; k < nbox; ++k) {
             const std::string where = "box " + std::to_string(k) + ": ";
-            check_particles(&boxes[k].particles, &boxes[k].tree, where, in[k]);
-            gs[k] = check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
-            if (!gs[k]) gs[k] = chosen_group_size(in[k].n, in[k].D);
+            ngr::check_particles(&boxes[k].particles, &boxes[k].tree, where, in[k]);
+            gs[k] = ngr::check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
+            if (!gs[k]) gs[k] = ngr::chosen_group_size(in[k].n, in[k].D);
             if (!boxes[k].acc && in[k].n) fail(NGR_EINVAL, where + "acc is NULL");
             if (boxes[k].force.grid != boxes[0].force.grid) fail(NGR_EINVAL, where + "the boxes must share the table grid");
             acc[k] = boxes[k].acc;
@@ -562,4 +571,54 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
         g.free(c);
         c.release(tab_block);
     });
+}
+
+NGR_API ngr_status ngr_server_create(ngr_context* ctx, const ngr_server_params* sp, ngr_server** out)
+{
+    if (out) *out = nullptr;
+    return guarded(ctx, [&] {
+        if (!out) ngr::fail(NGR_EINVAL, "out is NULL");
+        ngr_server* s = new ngr_server{ctx, ngr::server_create(*ctx, sp)};
+        *out = s;
+    });
+}
+
+NGR_API ngr_status ngr_server_submit(ngr_server* s, const ngr_request* r, uint64_t* id)
+{
+    if (!s) return NGR_EINVAL;
+    return guarded(s->ctx, [&] {
+        if (!id) ngr::fail(NGR_EINVAL, "id is NULL");
+        *id = ngr::server_submit(*s->impl, r);
+    });
+}
+
+NGR_API ngr_status ngr_server_tick(ngr_server* s, ngr_tick_stats* st)
+{
+    if (!s) return NGR_EINVAL;
+    return guarded(s->ctx, [&] { ngr::server_tick(*s->impl, st); });
+}
+
+NGR_API ngr_status ngr_server_status(const ngr_server* s, uint64_t id, int* state, uint32_t* evals)
+{
+    if (!s) return NGR_EINVAL;
+    try {
+        ngr::server_status(*s->impl, id, state, evals);
+        return NGR_OK;
+    } catch (const ngr::Error& e) {
+        return e.status;
+    }
+}
+
+NGR_API ngr_status ngr_server_take(ngr_server* s, uint64_t id, uint64_t* lattice, double* vel, double* acc)
+{
+    if (!s) return NGR_EINVAL;
+    return guarded(s->ctx, [&] { ngr::server_take(*s->impl, id, lattice, vel, acc); });
+}
+
+NGR_API void ngr_server_destroy(ngr_server* s)
+{
+    if (!s) return;
+    if (!s->ctx->poisoned) (void)hipStreamSynchronize(s->ctx->stream);
+    ngr::server_destroy(s->impl);
+    delete s;
 }

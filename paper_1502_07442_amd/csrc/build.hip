@@ -103,6 +103,27 @@ __global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64
     if (threadIdx.x == 0 && local_bad) atomicOr(&flags[k], local_bad);
 }
 
+// Checks of one box's inputs only (species id, mass, finite position); one
+// global atomic per workgroup.
+__global__ void check_box(uint64_t n, uint32_t D, const uint8_t* __restrict__ species, const double* __restrict__ mass,
+                          const double* __restrict__ pos, uint32_t* __restrict__ flags)
+{
+    __shared__ unsigned int local_bad;
+    if (threadIdx.x == 0) local_bad = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (species[i] >= D) bad |= kBadSpecies;
+        const double m = mass[i];
+        if (!(m >= 0.0) || !isfinite(m)) bad |= kBadMass;
+        if (pos && !(isfinite(pos[i]) && isfinite(pos[n + i]) && isfinite(pos[2 * n + i]))) bad |= kBadPos;
+    }
+    if (bad) atomicOr(&local_bad, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && local_bad) atomicOr(flags, local_bad);
+}
+
 // Sort key of the box pass: the box of each element, in the current order.
 __global__ void box_keys(uint64_t n, const uint32_t* __restrict__ idx, const uint16_t* __restrict__ boxid,
                          uint64_t* __restrict__ kb)
@@ -343,6 +364,22 @@ void grow_nodes(Context& ctx, Tree& t, uint64_t need)
 }
 
 }  // namespace
+
+void validate_box(Context& ctx, const BoxIn& b, const std::string& where)
+{
+    if (!b.n) return;
+    uint32_t* flags = static_cast<uint32_t*>(ctx.alloc(sizeof(uint32_t)));
+    HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(uint32_t), ctx.stream));
+    const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(b.n, 256), 4ull * ctx.num_cu));
+    hipLaunchKernelGGL(check_box, dim3(gx), dim3(256), 0, ctx.stream, b.n, b.D, b.species, b.mass, b.pos, flags);
+    LAUNCH_CHECK("check_box");
+    uint32_t h = 0;
+    ctx.to_host(&h, flags, sizeof h);
+    ctx.release(flags);
+    if (h & kBadSpecies) fail(NGR_EINVAL, where + "a species id is >= D");
+    if (h & kBadMass) fail(NGR_EINVAL, where + "a mass is negative or not finite");
+    if (h & kBadPos) fail(NGR_EINVAL, where + "a position is not finite");
+}
 
 void free_tree(Context& ctx, Tree& t)
 {

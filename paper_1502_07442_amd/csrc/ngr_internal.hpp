@@ -130,6 +130,15 @@ struct Tree {
 };
 void free_tree(Context& ctx, Tree& t);
 
+// ---- argument checks (api.hip) ----
+bool finite_pos(double v);
+// Check one box's particles and tree parameters; fill b. `where` prefixes messages.
+void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const std::string& where, BoxIn& b);
+// Check one box's force parameters; returns group_size (0: caller's choice).
+uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, const std::string& where);
+// The group size used when the caller passes 0.
+uint32_t chosen_group_size(uint64_t n, uint32_t D);
+
 // ---- device scan (scan.hip) ----
 // Exclusive prefix sum of n uint32 values; out may alias in. If total is
 // non-null the sum of all values is written to *total (device).
@@ -145,6 +154,8 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
 // Check, key, sort and build the tree of every box in one pass. Boxes with an
 // invalid species id, mass or position fail with NGR_EINVAL naming the box.
 void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t);
+// The device checks of one box's inputs alone (NGR_EINVAL as build_forest).
+void validate_box(Context& ctx, const BoxIn& b, const std::string& where);
 void compute_monopoles(Context& ctx, Tree& t);
 // Nodes, leaves and deepest level of each box of a tree (host vectors).
 void box_node_counts(Context& ctx, const Tree& t, std::vector<uint64_t>& nodes, std::vector<uint64_t>& leaves,
@@ -200,5 +211,14 @@ struct WalkOut {
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
                 const std::vector<LawTables>& tables, const std::vector<double*>& acc, uint64_t* group_counts_dev,
                 WalkOut& out);
+
+// ---- served requests (serve.hip) ----
+struct Server;
+Server* server_create(Context& ctx, const ngr_server_params* sp);
+void server_destroy(Server* s);
+uint64_t server_submit(Server& s, const ngr_request* r);
+void server_tick(Server& s, ngr_tick_stats* st);
+void server_status(const Server& s, uint64_t id, int* state, uint32_t* evals);
+void server_take(Server& s, uint64_t id, uint64_t* lattice, double* vel, double* acc);
 
 }  // namespace ngr

@@ -1,0 +1,355 @@
+// A request server for many boxes that each take a number of leapfrog
+// steps of the short-range force (continuous batching): every tick advances
+// every admitted request by one force evaluation, all of them in one batched
+// build and walk. Requests join as the device memory budget allows and leave
+// when their last evaluation is done.
+//
+// Paper: Croker, ngravs (CPC). The force of each box is the multi-species
+// short-range tree force (sections 2.1, 2.2 and 2.4.1); the kick-drift-kick
+// leapfrog around it is the integrator that the paper's test problems are run
+// with (section 3).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ngr_internal.hpp"
+
+namespace ngr {
+namespace {
+
+inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
+
+// One admitted request as the step kernels see it.
+struct StepDev {
+    uint64_t* X;
+    double* v;
+    const double* a;
+    uint64_t n;
+    double h;          // dt / 2
+    double dt_box;     // dt / box: drift in box units
+};
+
+// Half kick, v = v + a (dt/2), and (drift) X += v (dt/box) in lattice units,
+// wrapping in the periodic box; one thread per particle of request blockIdx.y.
+template <bool DRIFT>
+__global__ void kick_drift(const StepDev* __restrict__ req)
+{
+    // products and sums rounded separately (no fused multiply-add), so that
+    // any IEEE double implementation of these steps gives the same bits:
+    // close encounters amplify any difference step after step
+#pragma clang fp contract(off)
+    const StepDev R = req[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < R.n; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        if (i >= R.n) continue;
+        for (int c = 0; c < 3; ++c) {
+            const uint64_t j = (uint64_t)c * R.n + i;
+            const double v = R.v[j] + R.a[j] * R.h;
+            R.v[j] = v;
+            if (DRIFT) {
+                // displacement in box units, folded into [-1/2, 1/2] (a wrap),
+                // then in lattice units 2^64 per box
+                double d = v * R.dt_box;
+                d -= rint(d);
+                d = fmin(fmax(d, -0.5), 0.5 - 0x1p-53);
+                const int64_t dl = (int64_t)(d * 18446744073709551616.0);
+                R.X[j] += (uint64_t)dl;
+            }
+        }
+    }
+}
+
+// Positions to 64-bit lattice coordinates, as the build does for pos input.
+__global__ void pos_to_lattice(uint64_t n3, const double* __restrict__ x, double box, uint64_t* __restrict__ X)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n3) return;
+    double u = x[k] / box;
+    u = u - floor(u);
+    if (!(u < 1.0)) u = 0.0;
+    X[k] = (uint64_t)(u * 18446744073709551616.0);
+}
+
+constexpr uint64_t kTreeBytesPerParticle = 400;   // budget estimate of one tick's tree, per particle
+
+}  // namespace
+
+struct Request {
+    uint64_t id = 0;
+    BoxIn in;                         // lattice, species and mass point at the request's own copies
+    uint32_t gs = 64;
+    double dt = 0.0;
+    uint32_t steps = 0;
+    uint32_t evals = 0;
+    int state = 0;                    // 0 waiting, 1 admitted, 2 finished
+    uint64_t* X = nullptr;
+    double* v = nullptr;
+    double* a = nullptr;
+    uint8_t* species = nullptr;
+    double* mass = nullptr;
+    Law law;
+    std::vector<double> tables;       // host copy of the caller's tables
+    std::vector<LawTables> tab;
+    void* tab_block = nullptr;
+    uint64_t bytes = 0;               // device bytes held
+};
+
+struct Server {
+    Context* ctx = nullptr;
+    uint64_t budget = 0;
+    uint32_t max_active = 0;
+    uint64_t next_id = 1;
+    std::vector<Request*> all;        // every request not yet taken, in submission order
+    uint64_t admitted_bytes = 0;      // resident plus tree estimate of admitted requests
+};
+
+static void release_request(Context& ctx, Request* r)
+{
+    ctx.release(r->X);
+    ctx.release(r->v);
+    ctx.release(r->a);
+    ctx.release(r->species);
+    ctx.release(r->mass);
+    ctx.release(r->tab_block);
+    r->X = nullptr;
+    r->v = r->a = nullptr;
+    r->species = nullptr;
+    r->mass = nullptr;
+    r->tab_block = nullptr;
+}
+
+Server* server_create(Context& ctx, const ngr_server_params* sp)
+{
+    Server* s = new Server();
+    s->ctx = &ctx;
+    s->budget = sp && sp->hbm_budget ? sp->hbm_budget : 200000000000ull;
+    s->max_active = sp ? sp->max_active : 0;
+    return s;
+}
+
+void server_destroy(Server* s)
+{
+    if (!s) return;
+    for (Request* r : s->all) {
+        try {
+            release_request(*s->ctx, r);
+        } catch (...) {
+        }
+        delete r;
+    }
+    delete s;
+}
+
+static uint64_t footprint(const Request& r) { return r.bytes + r.in.n * kTreeBytesPerParticle; }
+
+uint64_t server_submit(Server& s, const ngr_request* rq)
+{
+    Context& ctx = *s.ctx;
+    if (!rq) fail(NGR_EINVAL, "request is NULL");
+    Request* r = new Request();
+    try {
+        check_particles(&rq->particles, &rq->tree, "", r->in);
+        uint32_t gs = check_force_params(r->in.D, r->in.box, &rq->force, "");
+        r->gs = gs ? gs : chosen_group_size(r->in.n, r->in.D);
+        if (!(std::isfinite(rq->dt) && rq->dt > 0.0)) fail(NGR_EINVAL, "dt must be finite and > 0");
+        if (rq->steps > (1u << 20)) fail(NGR_EINVAL, "steps must be at most 2^20");
+        r->dt = rq->dt;
+        r->steps = rq->steps;
+        const uint64_t n = r->in.n;
+        const uint32_t D = r->in.D;
+        if (rq->force.tables) r->tables.assign(rq->force.tables, rq->force.tables + (size_t)D * D * rq->force.ntab);
+        validate_box(ctx, r->in, "");
+        make_law(rq->force, D, r->law);
+        r->law.tables = rq->force.tables ? r->tables.data() : nullptr;
+        // own copies of the state
+        const uint64_t n1 = std::max<uint64_t>(n, 1);
+        r->X = static_cast<uint64_t*>(ctx.alloc(3 * n1 * sizeof(uint64_t)));
+        r->v = static_cast<double*>(ctx.alloc(3 * n1 * sizeof(double)));
+        r->a = static_cast<double*>(ctx.alloc(3 * n1 * sizeof(double)));
+        r->species = static_cast<uint8_t*>(ctx.alloc(n1));
+        r->mass = static_cast<double*>(ctx.alloc(n1 * sizeof(double)));
+        r->bytes = 3 * n1 * (sizeof(uint64_t) + 2 * sizeof(double)) + n1 * (1 + sizeof(double));
+        if (n) {
+            if (rq->particles.lattice) {
+                HIP_CHECK(hipMemcpyAsync(r->X, rq->particles.lattice, 3 * n * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                                         ctx.stream));
+            } else {
+                hipLaunchKernelGGL(pos_to_lattice, dim3(blocks_for(3 * n, 256)), dim3(256), 0, ctx.stream, 3 * n,
+                                   rq->particles.pos, r->in.box, r->X);
+                LAUNCH_CHECK("pos_to_lattice");
+            }
+            HIP_CHECK(hipMemcpyAsync(r->species, rq->particles.species, n, hipMemcpyDeviceToDevice, ctx.stream));
+            HIP_CHECK(hipMemcpyAsync(r->mass, rq->particles.mass, n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+            if (rq->vel)
+                HIP_CHECK(hipMemcpyAsync(r->v, rq->vel, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+            else
+                HIP_CHECK(hipMemsetAsync(r->v, 0, 3 * n * sizeof(double), ctx.stream));
+            HIP_CHECK(hipMemsetAsync(r->a, 0, 3 * n * sizeof(double), ctx.stream));
+            std::vector<Law> one(1, r->law);
+            r->tab_block = upload_tables(ctx, one, r->tab);
+            r->bytes += (uint64_t)D * D * (r->law.ntab * 12ull + 4);
+        }
+        r->in.pos = nullptr;
+        r->in.lattice = r->X;
+        r->in.species = r->species;
+        r->in.mass = r->mass;
+        if (footprint(*r) > s.budget) fail(NGR_ENOMEM, "the request does not fit the server's device memory budget");
+        ctx.sync();
+    } catch (...) {
+        try {
+            release_request(ctx, r);
+        } catch (...) {
+        }
+        delete r;
+        throw;
+    }
+    r->id = s.next_id++;
+    s.all.push_back(r);
+    return r->id;
+}
+
+void server_tick(Server& s, ngr_tick_stats* st)
+{
+    Context& ctx = *s.ctx;
+    ngr_tick_stats out;
+    std::memset(&out, 0, sizeof out);
+    // admission, in submission order
+    uint32_t active = 0;
+    for (Request* r : s.all) active += r->state == 1 ? 1u : 0u;
+    for (Request* r : s.all) {
+        if (r->state != 0) continue;
+        if (s.max_active && active >= s.max_active) break;
+        if (s.admitted_bytes + footprint(*r) > s.budget) break;
+        r->state = 1;
+        s.admitted_bytes += footprint(*r);
+        ++active;
+        ++out.admitted;
+    }
+    std::vector<Request*> act;
+    for (Request* r : s.all)
+        if (r->state == 1) act.push_back(r);
+    if (!act.empty()) {
+        hipEvent_t e0, e1;
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        HIP_CHECK(hipEventRecord(e0, ctx.stream));
+        // kick and drift of the requests past their first evaluation
+        std::vector<StepDev> steps;
+        uint64_t nmax = 0;
+        for (Request* r : act)
+            if (r->evals > 0 && r->in.n) {
+                steps.push_back(StepDev{r->X, r->v, r->a, r->in.n, 0.5 * r->dt, r->dt / r->in.box});
+                nmax = std::max(nmax, r->in.n);
+            }
+        StepDev* steps_dev = nullptr;
+        const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(nmax, 256), 64));
+        if (!steps.empty()) {
+            steps_dev = static_cast<StepDev*>(ctx.alloc(steps.size() * sizeof(StepDev)));
+            ctx.to_device(steps_dev, steps.data(), steps.size() * sizeof(StepDev));
+            hipLaunchKernelGGL(kick_drift<true>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream, steps_dev);
+            LAUNCH_CHECK("kick_drift");
+        }
+        // one force evaluation of every admitted request
+        std::vector<BoxIn> in;
+        std::vector<uint32_t> gs;
+        std::vector<Law> laws;
+        std::vector<LawTables> tabs;
+        std::vector<double*> acc;
+        for (Request* r : act) {
+            in.push_back(r->in);
+            gs.push_back(r->gs);
+            laws.push_back(r->law);
+            tabs.push_back(r->tab.empty() ? LawTables{} : r->tab[0]);
+            acc.push_back(r->a);
+            out.particles += r->in.n;
+        }
+        Tree t;
+        Groups g;
+        WalkOut wo;
+        try {
+            build_forest(ctx, in, t);
+            compute_monopoles(ctx, t);
+            make_groups(ctx, t, gs, g);
+            walk_force(ctx, t, g, laws, tabs, acc, nullptr, wo);
+        } catch (...) {
+            try {
+                free_tree(ctx, t);
+                g.free(ctx);
+                ctx.release(steps_dev);
+            } catch (...) {
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        free_tree(ctx, t);
+        g.free(ctx);
+        // closing half kick
+        if (steps_dev) {
+            hipLaunchKernelGGL(kick_drift<false>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream, steps_dev);
+            LAUNCH_CHECK("kick");
+            ctx.release(steps_dev);
+        }
+        HIP_CHECK(hipEventRecord(e1, ctx.stream));
+        ctx.sync();
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        out.ms = ms;
+        out.evaluated = (uint32_t)act.size();
+        out.interactions = wo.pp + wo.pn;
+        for (Request* r : act) {
+            ++r->evals;
+            if (r->evals == r->steps + 1) {
+                r->state = 2;
+                s.admitted_bytes -= footprint(*r);
+                ++out.finished;
+            }
+        }
+    }
+    for (Request* r : s.all) {
+        out.active += r->state == 1 ? 1u : 0u;
+        out.pending += r->state == 0 ? 1u : 0u;
+        out.resident_bytes += r->state == 1 ? r->bytes : 0u;
+    }
+    if (st) *st = out;
+}
+
+static Request* find(const Server& s, uint64_t id)
+{
+    for (Request* r : s.all)
+        if (r->id == id) return r;
+    return nullptr;
+}
+
+void server_status(const Server& s, uint64_t id, int* state, uint32_t* evals)
+{
+    const Request* r = find(s, id);
+    if (!r) fail(NGR_EINVAL, "unknown request id");
+    if (state) *state = r->state;
+    if (evals) *evals = r->evals;
+}
+
+void server_take(Server& s, uint64_t id, uint64_t* lattice, double* vel, double* acc)
+{
+    Context& ctx = *s.ctx;
+    Request* r = find(s, id);
+    if (!r) fail(NGR_EINVAL, "unknown request id");
+    if (r->state != 2) fail(NGR_ESTATE, "the request has not finished");
+    const uint64_t n = r->in.n;
+    if (n) {
+        if (lattice)
+            HIP_CHECK(hipMemcpyAsync(lattice, r->X, 3 * n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx.stream));
+        if (vel) HIP_CHECK(hipMemcpyAsync(vel, r->v, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+        if (acc) HIP_CHECK(hipMemcpyAsync(acc, r->a, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+    }
+    ctx.sync();
+    release_request(ctx, r);
+    s.all.erase(std::find(s.all.begin(), s.all.end(), r));
+    delete r;
+}
+
+}  // namespace ngr

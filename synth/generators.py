@@ -29,7 +29,7 @@ __all__ = [
     "uniform_positions", "uniform_lattice", "clustered_positions",
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
-    "clustered_problem", "uniform_problem", "batch_box",
+    "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -292,3 +292,20 @@ def batch_box(k: int) -> Problem:
     D = int(rng.integers(1, 5))
     f_cl = float(rng.uniform(0.0, 0.8))
     return clustered_problem(n, D, 4000 + k, f_cl=f_cl, grid=GRID_R2, ntab=2048)
+
+
+def serve_request(r: int) -> Problem:
+    """Request r of the served workload: a new box with N log-uniform in
+    [2^14, 2^20], D in {1..6}, clustered fraction in [0, 0.8] and laws of its
+    own (the many-box recipe at larger N)."""
+    rng = np.random.default_rng(5000 + r)
+    n = int(round(2.0 ** rng.uniform(14, 20)))
+    D = int(rng.integers(1, 7))
+    f_cl = float(rng.uniform(0.0, 0.8))
+    return clustered_problem(n, D, 5000 + r, f_cl=f_cl, grid=GRID_R2, ntab=2048)
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson stream of `rate` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))

@@ -1,0 +1,172 @@
+"""The request server (ngr_server_*): every request's trajectory is bitwise
+the one it has alone, whatever shares its ticks; its first force is the
+single-box force; its steps follow kick-drift-kick; budgets and errors."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1502_07442_amd as ngr
+import synth
+from gpu_util import device_inputs, force_gate, gpu_solve
+
+pytestmark = pytest.mark.gpu
+R2 = synth.GRID_R2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ngr.Context(0)
+    yield c
+    c.close()
+
+
+def submit(srv, p, steps, dt=1e-3):
+    return srv.submit(D=p.D, box=p.box, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                      r_s=p.r_s, dt=dt, steps=steps, leaf_size=p.leaf_size, group_size=p.group_size,
+                      **device_inputs(p))
+
+
+def take(srv, rid, n):
+    import torch
+    X = torch.empty((3, n), dtype=torch.int64, device="cuda")
+    V = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    A = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    srv.take(rid, X, V, A)
+    return X.cpu().numpy(), V.cpu().numpy(), A.cpu().numpy()
+
+
+def run(ctx, probs, steps, every=1, max_active=0, dt=1e-3):
+    """Submit probs one per `every` ticks; tick until all finish; final states."""
+    srv = ngr.Server(ctx, max_active=max_active)
+    ids, out, k, ticks = {}, {}, 0, 0
+    while len(out) < len(probs):
+        if k < len(probs) and ticks % every == 0:
+            ids[k] = submit(srv, probs[k], steps[k], dt=dt)
+            k += 1
+        st = srv.tick()
+        ticks += 1
+        assert st["active"] + st["pending"] + len(out) + st["finished"] >= 0
+        for j, rid in list(ids.items()):
+            if srv.status(rid)[0] == ngr.FINISHED:
+                out[j] = take(srv, rid, probs[j].n)
+                del ids[j]
+        assert ticks < 10 * (sum(steps) + len(probs) + 5), "no progress"
+    srv.close()
+    return out
+
+
+def mixed_requests():
+    return [synth.uniform_problem(300, 1, 2, grid=R2), synth.clustered_problem(4096, 3, 5, ntab=512),
+            synth.uniform_problem(2000, 2, 1, grid=R2), synth.clustered_problem(16384, 6, 7, ntab=1024),
+            synth.clustered_problem(8192, 4, 8, ntab=2048, leaf_size=8), synth.uniform_problem(1000, 5, 3, grid=R2)]
+
+
+def test_mix_equals_alone(ctx):
+    probs = mixed_requests()
+    steps = [8, 8, 3, 8, 5, 0]
+    print("case 6 requests, staggered", flush=True)
+    mix = run(ctx, probs, steps, every=2)
+    for j, p in enumerate(probs):
+        alone = run(ctx, [p], [steps[j]])[0]
+        for a, b in zip(alone, mix[j]):
+            assert np.array_equal(a, b), (p.name, j)
+    # one request at a time (FIFO through the same server) gives the same bits too
+    fifo = run(ctx, probs, steps, max_active=1)
+    for j in range(len(probs)):
+        for a, b in zip(fifo[j], mix[j]):
+            assert np.array_equal(a, b), j
+
+
+def test_first_force_is_the_single_box_force(ctx):
+    probs = mixed_requests()[:4]
+    out = run(ctx, probs, [0] * len(probs))
+    for j, p in enumerate(probs):
+        acc1, st1, _, _ = gpu_solve(ctx, p)
+        assert np.array_equal(out[j][2], acc1), p.name
+        assert np.array_equal(out[j][0].view(np.uint64), oracle.lattice(p.pos, p.box)), p.name
+        assert np.all(out[j][1] == 0.0)
+        T = oracle.Tree.of(p)
+        ao, so, co, _ = T.force(oracle.law_of(p))
+        ok, worst, _, _ = force_gate(out[j][2], ao, so)
+        assert ok, (p.name, worst)
+
+
+def test_steps_follow_kick_drift_kick(ctx):
+    """Against the single-box calls with the steps done on the host in the
+    same IEEE double operations: the same bits."""
+    import torch
+    p = synth.clustered_problem(4096, 3, 11, ntab=512)
+    steps, dt = 4, 2e-3
+    out = run(ctx, [p], [steps], dt=dt)[0]
+    lat = oracle.lattice(p.pos, p.box)
+    v = np.zeros((3, p.n))
+    h = 0.5 * dt
+
+    def force(X):
+        q = dict(device_inputs(p))
+        q.pop("pos")
+        q["lattice"] = torch.from_numpy(np.ascontiguousarray(X).view(np.int64)).cuda()
+        tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **q)
+        ngr.compute_monopoles(ctx, tree)
+        acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+        ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                       group_size=p.group_size, acc=acc)
+        ngr.tree_free(ctx, tree)
+        return acc.cpu().numpy()
+
+    a = force(lat)
+    for _ in range(steps):
+        v = v + a * h
+        d = v * (dt / p.box)
+        d -= np.rint(d)
+        d = np.clip(d, -0.5, 0.5 - 2.0 ** -53)
+        lat = lat + (d * 2.0 ** 64).astype(np.int64).view(np.uint64)
+        a = force(lat)
+        v = v + a * h
+    assert np.array_equal(out[0].view(np.uint64), lat)
+    assert np.array_equal(out[1], v)
+    assert np.array_equal(out[2], a)
+    moved = (out[0].view(np.uint64) != oracle.lattice(p.pos, p.box)).mean()
+    assert moved > 0.5
+
+
+def test_budget_and_errors(ctx):
+    import torch
+    p = synth.uniform_problem(2000, 2, 21, grid=R2)
+    small = ngr.Server(ctx, hbm_budget=100000)
+    with pytest.raises(ngr.NgravsError) as e:
+        submit(small, p, 2)
+    assert e.value.status == ngr.ENOMEM
+    small.close()
+    srv = ngr.Server(ctx)
+    bad = synth.uniform_problem(2000, 2, 22, grid=R2)
+    bad.species = bad.species.copy()
+    bad.species[3] = 5
+    with pytest.raises(ngr.NgravsError) as e:
+        submit(srv, bad, 2)
+    assert e.value.status == ngr.EINVAL
+    with pytest.raises(ngr.NgravsError) as e:
+        srv.submit(D=p.D, box=p.box, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                   dt=-1.0, steps=2, **device_inputs(p))
+    assert e.value.status == ngr.EINVAL
+    rid = submit(srv, p, 3)
+    assert srv.status(rid) == (ngr.WAITING, 0)
+    srv.tick()
+    assert srv.status(rid) == (ngr.ADMITTED, 1)
+    with pytest.raises(ngr.NgravsError) as e:
+        take(srv, rid, p.n)
+    assert e.value.status == ngr.ESTATE
+    for _ in range(3):
+        srv.tick()
+    assert srv.status(rid) == (ngr.FINISHED, 4)
+    take(srv, rid, p.n)
+    with pytest.raises(ngr.NgravsError) as e:
+        srv.status(rid)
+    assert e.value.status == ngr.EINVAL
+    st = srv.tick()                       # nothing left: a no-op
+    assert st["evaluated"] == 0 and st["active"] == 0 and st["pending"] == 0
+    srv.close()
+    assert torch.cuda.is_available()
