@@ -33,7 +33,7 @@
 // Records evaluated per iteration of the pair loop (independent chains for
 // the scheduler to interleave).
 #ifndef NGR_EVAL_UNROLL
-#define NGR_EVAL_UNROLL 2
+#define NGR_EVAL_UNROLL 4
 #endif
 #define NGR_STR2(x) #x
 #define NGR_PRAGMA_UNROLL(n) _Pragma(NGR_STR2(unroll n))
@@ -474,11 +474,13 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             else eval_records<GRID, TAB, EPS0, false, 4>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
         };
 
-        // Accepted nodes: one record per non-empty species monopole.
+        // Accepted nodes: one record per non-empty species monopole. The next
+        // species' monopoles are loaded while this species is evaluated.
         auto flush_nodes = [&](uint32_t k) {
+            const uint32_t node = (uint32_t)lane < k ? pnb[lane] : 0u;
+            double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+            if ((uint32_t)lane < k) r = A.mono[node];
             for (uint32_t b = 0; b < Dk; ++b) {
-                double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
-                if ((uint32_t)lane < k) r = A.mono[(uint64_t)b * A.nn + pnb[lane]];
                 const bool v = (uint32_t)lane < k && r.w > 0.0;
                 const uint64_t m = __ballot(v);
                 const uint32_t nrec = (uint32_t)__popcll(m);
@@ -491,50 +493,102 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 }
                 if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
                 wave_sync();
+                if (b + 1 < Dk && (uint32_t)lane < k) r = A.mono[(uint64_t)(b + 1) * A.nn + node];
                 if (nrec) eval(b, nrec);
                 pn_src += nrec;
                 wave_sync();
             }
         };
 
-        // Opened leaves: every particle, one source species at a time.
+        // Opened leaves: every particle, one source species at a time, in
+        // chunks of up to 64 records. Each chunk's particle loads are issued
+        // before the previous chunk is evaluated, so that their latency hides
+        // behind the pair loop.
         auto flush_leaves = [&](uint32_t k) {
-            for (uint32_t b = 0; b < Dk; ++b) {
-                uint32_t c = 0, st = 0;
-                if ((uint32_t)lane < k) {
-                    uint32_t leaf = ppb[lane];
-                    c = A.count[(uint64_t)leaf * D + b];
-                    st = A.start[(uint64_t)leaf * D + b];
+            const uint32_t leaf = (uint32_t)lane < k ? ppb[lane] : 0u;
+            uint32_t cnt[NGR_MAX_SPECIES], stv[NGR_MAX_SPECIES];
+#pragma unroll
+            for (uint32_t q = 0; q < NGR_MAX_SPECIES; ++q) {
+                cnt[q] = 0u;
+                stv[q] = 0u;
+                if ((uint32_t)lane < k && q < Dk) {
+                    cnt[q] = A.count[(uint64_t)leaf * D + q];
+                    stv[q] = A.start[(uint64_t)leaf * D + q];
                 }
-                const uint32_t incl = wave_incl(c, lane);
+            }
+            auto pick = [&](const uint32_t* arr, uint32_t b) {   // arr[b], b wave-uniform
+                uint32_t v = 0u;
+#pragma unroll
+                for (uint32_t q = 0; q < NGR_MAX_SPECIES; ++q) v = q == b ? arr[q] : v;
+                return v;
+            };
+            // species b's running counts into LDS; its particle total
+            auto prep = [&](uint32_t b) -> uint32_t {
+                const uint32_t incl = wave_incl(pick(cnt, b), lane);
                 const uint32_t T = uniform(__shfl(incl, 63, 64));
-                if (T == 0) continue;
-                scanb[lane + 1] = incl;
-                scanb[0] = 0;                  // every lane stores the same value
-                pst[lane] = st;
-                wave_sync();
-                for (uint32_t base = 0; base < T; base += 64) {
-                    const uint32_t r = base + lane;
-                    if (r < T) {
-                        // leaf q with scanb[q] <= r < scanb[q+1]
-                        uint32_t lo2 = 0, hi2 = k;
-                        while (hi2 - lo2 > 1) {
-                            uint32_t mid = (lo2 + hi2) >> 1;
-                            if (scanb[mid] <= r) lo2 = mid;
-                            else hi2 = mid;
-                        }
-                        const uint64_t j = pst[lo2] + (r - scanb[lo2]);
-                        rec[lane] = make_double4((double)(int64_t)(A.X[j] - C0) * scale,
-                                                 (double)(int64_t)(A.X[n + j] - C1) * scale,
-                                                 (double)(int64_t)(A.X[2 * n + j] - C2) * scale,
-                                                 Ga[b] * A.mass[j]);
-                    }
-                    if (K > 1u && (uint32_t)lane < 3u) rec[min(64u, T - base) + lane] = pad;
-                    wave_sync();
-                    eval(b, min(64u, T - base));
+                if (T) {
+                    scanb[lane + 1] = incl;
+                    scanb[0] = 0;              // every lane stores the same value
+                    pst[lane] = pick(stv, b);
                     wave_sync();
                 }
-                pp_src += T;
+                return T;
+            };
+            uint64_t sx = 0, sy = 0, sz = 0;
+            double sm = 0.0;
+            bool sv = false;
+            // loads of record base + lane of the current species
+            auto stage = [&](uint32_t base, uint32_t T) {
+                const uint32_t r = base + lane;
+                sv = r < T;
+                if (sv) {
+                    // leaf q with scanb[q] <= r < scanb[q+1]
+                    uint32_t lo2 = 0, hi2 = k;
+                    while (hi2 - lo2 > 1) {
+                        uint32_t mid = (lo2 + hi2) >> 1;
+                        if (scanb[mid] <= r) lo2 = mid;
+                        else hi2 = mid;
+                    }
+                    const uint64_t j = pst[lo2] + (r - scanb[lo2]);
+                    sx = A.X[j];
+                    sy = A.X[n + j];
+                    sz = A.X[2 * n + j];
+                    sm = A.mass[j];
+                }
+            };
+            uint32_t b = 0, T = 0;
+            for (; b < Dk; ++b) {
+                T = prep(b);
+                if (T) break;
+            }
+            if (b >= Dk) return;
+            uint32_t base = 0;
+            stage(base, T);
+            for (;;) {
+                const uint32_t nrec = min(64u, T - base);
+                if (sv)
+                    rec[lane] = make_double4((double)(int64_t)(sx - C0) * scale, (double)(int64_t)(sy - C1) * scale,
+                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm);
+                if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
+                wave_sync();
+                // the next chunk: the rest of this species, else the next species with particles
+                uint32_t nb = b, nbase = base + 64u, nT = T;
+                if (nbase >= T) {
+                    nbase = 0;
+                    nT = 0;
+                    for (nb = b + 1; nb < Dk; ++nb) {
+                        nT = prep(nb);
+                        if (nT) break;
+                    }
+                }
+                if (nb < Dk) stage(nbase, nT);
+                eval(b, nrec);
+                pp_src += nrec;
+                wave_sync();
+                if (nb >= Dk) break;
+                b = nb;
+                base = nbase;
+                T = nT;
             }
         };
 
