@@ -62,6 +62,7 @@ def lib():
             "orc_tree_force": (C.c_int, [P, P, P, u64, P, P, P, P]),
             "orc_direct": (C.c_int, [u64, u32, dbl, P, P, P, P, P, u64, P, P]),
             "orc_factor": (dbl, [P, u32, u32, dbl, dbl]),
+            "orc_cored_radial": (dbl, [dbl, dbl]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -76,23 +77,40 @@ def _p(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
+LAW_TABLE, LAW_ACCUMULATOR = 0, 1
+
+
 class Law(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32),
                 ("grid", C.c_uint32), ("r_cut", C.c_double), ("eps", C.c_double),
-                ("theta", C.c_double)]
+                ("theta", C.c_double), ("kind", C.c_uint32), ("cored", C.c_uint32),
+                ("beta", C.c_double), ("track_counts", C.c_uint32)]
 
 
-def make_law(G, tables, grid, r_cut, eps, theta):
+def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=0.0, track_counts=True):
+    """cored: species indices with a core (accumulator laws)."""
     G = np.ascontiguousarray(G, dtype=np.float64)
     tables = np.ascontiguousarray(tables, dtype=np.float64)
+    mask = 0
+    for b in cored:
+        mask |= 1 << int(b)
     law = Law(G.ctypes.data, tables.ctypes.data, tables.shape[-1], GRID[grid],
-              float(r_cut), float(eps), float(theta))
+              float(r_cut), float(eps), float(theta), int(kind), mask, float(beta), int(bool(track_counts)))
     law._keep = (G, tables)  # keep the buffers alive with the struct
     return law
 
 
-def law_of(p):
-    return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta)
+def law_of(p, track_counts=True):
+    acc = getattr(p, "accumulator", None)
+    if acc is None:
+        return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta)
+    return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, kind=LAW_ACCUMULATOR,
+                    cored=acc["cored"], beta=acc["beta"], track_counts=track_counts)
+
+
+def cored_radial(r: float, s: float) -> float:
+    """orc_cored_radial: the accumulator laws' radial factor (see the C source)."""
+    return float(lib().orc_cored_radial(float(r), float(s)))
 
 
 def num_threads() -> int:

@@ -16,6 +16,8 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+
+#define ORC_PI 3.14159265358979323846
 #endif
 
 #define KEY_BITS 60u
@@ -534,11 +536,50 @@ double orc_factor(const double* T, uint32_t ntab, uint32_t grid, double r2, doub
 }
 
 /*
+ * The accumulator ("Mahalo") laws of section 3.3. A cored object of mass M
+ * has the density of Eq. (15); two objects whose cores are M_1 and m_1 (0 for
+ * a point-like one) have the mutual potential of Eq. (14),
+ *     Phi(r) = -(2 M m / (pi r)) atan(r / s),  s = (M_1 + m_1) / (4 pi beta),
+ * which is Newton's potential for s = 0. The acceleration of the passive
+ * object is -(1/m) dPhi/dr toward the source:
+ *     (2 M / pi) [atan(r/s) - r s / (r^2 + s^2)] / r^3  =  M * orc_cored_radial(r, s).
+ * Readings: the printed core radius of Eq. (15), M / (2 beta pi), makes the
+ * density integrate to M / 2; M / (4 beta pi) integrates to M and, since the
+ * mutual potential of two such densities has the sum of their core radii as
+ * its scale, reproduces the scale (M_1 + m_1) / (4 pi beta) of Eq. (14). In
+ * Eq. (10) (cored sink, point-like sources) the source carries no core, so
+ * its body count N_perp cannot enter the scale: s = m_1 / (4 pi beta) (the
+ * printed form agrees for N_perp = 1). A monopole of N_perp bodies of a cored
+ * species weighs M / N_perp per body (section 2.2's optional N_perp tracking);
+ * without tracking it counts as one body of mass M.
+ * For r / s below 1e-2 the bracket is taken from its series,
+ *     atan x - x / (1 + x^2) = (2/3) x^3 - (4/5) x^5 + (6/7) x^7 - ...,
+ * which avoids the cancellation of the two terms.
+ */
+double orc_cored_radial(double r, double s)
+{
+    if (!(s > 0.0)) return 1.0 / (r * r * r);
+    const double x = r / s;
+    double h;   /* [atan x - x / (1 + x^2)] / x^3 */
+    if (x < 1e-2) {
+        const double x2 = x * x;
+        h = 2.0 / 3.0 - 0.8 * x2 + (6.0 / 7.0) * x2 * x2;
+    } else {
+        h = (atan(x) - x / (1.0 + x * x)) / (x * x * x);
+    }
+    return (2.0 / ORC_PI) * h / (s * s * s);
+}
+
+/*
  * One pair term (Eq. (1) with the active mass as a multiplier and the
  * passive mass divided out, section 2.1): the acceleration of a sink of
  * species a due to a source of species b and active mass mu at offset d
  * (source minus sink, minimum image) is
  *     G_ab * mu * f_ab(r) * d / (r^2 + eps^2)^(3/2)      for r < r_cut,
+ * with the tabulated law; with the accumulator laws the Plummer factor of a
+ * pair with a core (s > 0) is replaced by orc_cored_radial(r, s), where
+ * s = (mu_body [b cored] + m_sink [a cored]) / (4 pi beta) and mu_body is
+ * the mass of one source body.
  * Readings: a single Plummer softening; f evaluated at the unsoftened r;
  * G_ab * f > 0 attracts.
  * Pairs within 1e-6 r_cut^2 of the cut-off add their magnitude to the
@@ -547,10 +588,12 @@ double orc_factor(const double* T, uint32_t ntab, uint32_t grid, double r2, doub
 typedef struct {
     const double* G; const double* tab; uint32_t ntab, grid, D;
     double rc, rc2, eps2, band;
+    uint32_t kind, cored;
+    double inv4pib;
 } pair_ctx;
 
-static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu,
-                      const double d[3], double acc[3], double* slack)
+static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, double mu_body,
+                      double m_sink, const double d[3], double acc[3], double* slack)
 {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (r2 == 0.0) return;           /* coincident: no direction, no force */
@@ -559,8 +602,18 @@ static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu,
     if (!inside && !tie) return;
     const double* T = P->tab + ((uint64_t)a * P->D + b) * P->ntab;
     double f = orc_factor(T, P->ntab, P->grid, r2, P->rc);
-    double re2 = r2 + P->eps2;
-    double k = P->G[a * P->D + b] * mu * f / (re2 * sqrt(re2));
+    double radial;
+    double s = 0.0;
+    if (P->kind == ORC_LAW_ACCUMULATOR)
+        s = (((P->cored >> b) & 1u) ? mu_body : 0.0) * P->inv4pib +
+            (((P->cored >> a) & 1u) ? m_sink : 0.0) * P->inv4pib;
+    if (s > 0.0) {
+        radial = orc_cored_radial(sqrt(r2), s);
+    } else {
+        double re2 = r2 + P->eps2;
+        radial = 1.0 / (re2 * sqrt(re2));
+    }
+    double k = P->G[a * P->D + b] * mu * f * radial;
     if (inside)
         for (unsigned x = 0; x < 3; ++x) acc[x] += k * d[x];
     if (tie) *slack += fabs(k) * sqrt(r2);
@@ -571,6 +624,9 @@ static void make_pair_ctx(pair_ctx* P, const orc_law* law, uint32_t D)
     P->G = law->G; P->tab = law->tables; P->ntab = law->ntab; P->grid = law->grid; P->D = D;
     P->rc = law->r_cut; P->rc2 = law->r_cut * law->r_cut; P->eps2 = law->eps * law->eps;
     P->band = 1e-6 * P->rc2;
+    P->kind = law->kind;
+    P->cored = law->cored;
+    P->inv4pib = law->kind == ORC_LAW_ACCUMULATOR ? 1.0 / (4.0 * ORC_PI * law->beta) : 0.0;
 }
 
 static double wrap_periodic(double d, double box)
@@ -644,7 +700,9 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
                             double d[3];
                             for (unsigned x = 0; x < 3; ++x)
                                 d[x] = wrap_periodic(t->com[b][x][node] - xi[x], t->box);
-                            pair_term(&P, a, b, Mb, d, ai, &sl);
+                            double body = Mb;
+                            if (law->track_counts && t->count[b][node]) body = Mb / (double)t->count[b][node];
+                            pair_term(&P, a, b, Mb, body, t->m[i], d, ai, &sl);
                         }
                     } else {
                         for (uint32_t b = 0; b < t->D; ++b) {
@@ -654,7 +712,7 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
                                 double d[3];
                                 for (unsigned x = 0; x < 3; ++x)
                                     d[x] = (double)(int64_t)(t->X[x][j] - t->X[x][i]) * scale;
-                                pair_term(&P, a, b, t->m[j], d, ai, &sl);
+                                pair_term(&P, a, b, t->m[j], t->m[j], t->m[i], d, ai, &sl);
                             }
                         }
                     }
@@ -728,7 +786,7 @@ int orc_direct(uint64_t n, uint32_t D, double box, const uint64_t* X,
                             double d[3];
                             for (unsigned x = 0; x < 3; ++x)
                                 d[x] = (double)(int64_t)(X[x * n + j] - X[x * n + i]) * scale;
-                            pair_term(&P, a, species[j], mass[j], d, ai, &sl);
+                            pair_term(&P, a, species[j], mass[j], mass[j], mass[i], d, ai, &sl);
                         }
                     }
         } else {
@@ -737,7 +795,7 @@ int orc_direct(uint64_t n, uint32_t D, double box, const uint64_t* X,
                 double d[3];
                 for (unsigned x = 0; x < 3; ++x)
                     d[x] = (double)(int64_t)(X[x * n + j] - X[x * n + i]) * scale;
-                pair_term(&P, a, species[j], mass[j], d, ai, &sl);
+                pair_term(&P, a, species[j], mass[j], mass[j], mass[i], d, ai, &sl);
             }
         }
         for (unsigned x = 0; x < 3; ++x) acc[x * n_sinks + q] = ai[x];

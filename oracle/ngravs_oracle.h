@@ -39,7 +39,14 @@ typedef struct {
     double r_cut;          /* cut-off radius, 0 < r_cut < box/2                 */
     double eps;            /* Plummer softening, >= 0                           */
     double theta;          /* opening angle, > 0                                */
+    uint32_t kind;         /* ORC_LAW_TABLE or ORC_LAW_ACCUMULATOR              */
+    uint32_t cored;        /* accumulator: bit b set = species b is cored       */
+    double beta;           /* accumulator: dimensionless scale, > 0             */
+    uint32_t track_counts; /* accumulator: 1 = monopole bodies weigh M/N_perp,
+                              0 = a monopole counts as one body of mass M        */
 } orc_law;
+
+enum { ORC_LAW_TABLE = 0, ORC_LAW_ACCUMULATOR = 1 };
 
 int      orc_num_threads(void);
 
@@ -83,6 +90,7 @@ int      orc_direct(uint64_t n, uint32_t D, double box, const uint64_t* X,
                     const uint8_t* species, const double* mass, const orc_law* law,
                     const uint32_t* sinks, uint64_t n_sinks, double* acc, double* slack);
 double   orc_factor(const double* T, uint32_t ntab, uint32_t grid, double r2, double r_cut);
+double   orc_cored_radial(double r, double s);
 
 #ifdef __cplusplus
 }
