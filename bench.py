@@ -221,6 +221,49 @@ def served(ngr, synth, nreq=200, warm=25, steps=8, dt=1e-3, loads=(0.5, 0.9)):
     return out
 
 
+def accumulator(ngr, synth, n=2 ** 22, steps=3):
+    """The accumulator laws (section 3.3) on the two-species workload: one
+    Newtonian and one cored species, N_perp tracked; a step is the build,
+    the monopoles and the force, timed like the main workload. The same
+    particles under the table law (no cores) give the overhead of the cored
+    pair term."""
+    import numpy as np
+    import torch
+    p = synth.accumulator_problem(n, 3)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(p.pos).to(dev)
+    species = torch.from_numpy(np.ascontiguousarray(p.species, np.uint8)).to(dev)
+    mass = torch.from_numpy(p.mass).to(dev)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device=dev)
+    ctx = ngr.Context(0)
+
+    def step(law):
+        tree = ngr.tree_build(ctx, D=p.D, box=p.box, pos=pos, species=species, mass=mass, leaf_size=p.leaf_size)
+        ngr.compute_monopoles(ctx, tree, track_counts=True)
+        st = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
+                            theta=p.theta, group_size=p.group_size, acc=acc, accumulator=law)
+        ngr.tree_free(ctx, tree)
+        return st
+
+    res = {}
+    for name, law in (("accumulator", p.accumulator), ("table", None)):
+        step(law)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step(law) for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        inter = sts[-1]["interactions_pp"] + sts[-1]["interactions_pn"]
+        res[name] = (ms, float(np.mean([s["ms_walk"] for s in sts])), inter)
+    ctx.close()
+    ms, walk, inter = res["accumulator"]
+    return {"workload": f"clustered box, {p.n} particles, 2 species (one cored, beta {p.accumulator['beta']:.4g}: "
+                        f"one body's core 0.25 of the mean spacing), N_perp tracked",
+            "n": p.n, "ms_per_step": ms, "interactions": inter, "interactions_per_s": inter / (ms * 1e-3),
+            "walk_ms": walk, "walk_interactions_per_s": inter / (walk * 1e-3),
+            "table_law_walk_ms": res["table"][1], "cored_walk_over_table_walk": walk / res["table"][1]}
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -260,6 +303,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-accumulator", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
@@ -337,6 +381,11 @@ def main():
         log(f"served workload: {args.serve_requests} requests")
         out["served"] = served(ngr, synth, nreq=args.serve_requests)
         log("served: " + json.dumps({k: v for k, v in out["served"].items() if k.startswith(("load", "satur"))}))
+    if not args.no_accumulator:
+        log("accumulator laws: two-species workload")
+        out["accumulator"] = accumulator(ngr, synth)
+        log(f"accumulator: walk {out['accumulator']['walk_ms']:.2f} ms, "
+            f"{out['accumulator']['cored_walk_over_table_walk']:.2f}x the table-law walk")
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(p, inter, args.cpu_seconds)

@@ -52,6 +52,8 @@ typedef int32_t ngr_status;
 #define NGR_MAX_SPECIES 6      /* section 2: 1 <= D <= 6                                */
 #define NGR_GRID_R      0      /* table samples uniform in r   on [0, r_cut], both ends */
 #define NGR_GRID_R2     1      /* table samples uniform in r^2 on [0, r_cut^2]          */
+#define NGR_LAW_TABLE        0   /* f_ab(r) times the softened Newtonian force            */
+#define NGR_LAW_ACCUMULATOR  1   /* section 3.3: cored species, Eqs. (13)-(17)            */
 #define NGR_MAX_TABLE   12288  /* D * ntab must not exceed this (one sink species' D
                                   tables are held on chip during the walk)              */
 
@@ -110,8 +112,10 @@ ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p,
 /*
  * Per-node, per-species monopoles (section 2.2): mass M_b (float64) and
  * centre of mass (float64), reduced bottom-up level by level. Must precede
- * ngr_tree_force. `track_counts` is accepted for the N_perp option of
- * section 2.2; counts are always available from the build.
+ * ngr_tree_force. track_counts selects the N_perp option of section 2.2
+ * for the accumulator laws (ngr_force_params.law): nonzero, a species
+ * monopole of M over N_perp particles stands for N_perp bodies of mass
+ * M / N_perp; zero, for one body of mass M. Table laws do not depend on it.
  */
 ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_counts);
 
@@ -128,6 +132,21 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   eps      Plummer softening, >= 0
  *   theta    opening angle, > 0
  *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice, 32)
+ *   law      NGR_LAW_TABLE (0), or NGR_LAW_ACCUMULATOR: the accumulator
+ *            laws of section 3.3. A pair in which neither species is cored
+ *            keeps the law above. Otherwise the Newtonian factor
+ *            (r^2 + eps^2)^(-3/2) is replaced by the force of the Eq. (14)
+ *            potential, (2/pi) [atan(r/s) - (r/s) / (1 + (r/s)^2)] / r^3,
+ *            whose scale s = (c_b mu + c_a m) / (4 pi beta) adds the core
+ *            of the source body (c_b = 1 if source species b is cored; mu =
+ *            its mass, or M / N_perp for a tracked monopole, M untracked)
+ *            and of the sink (c_a, its mass m). Readings: the core radius
+ *            of the Eq. (15) density is M / (4 pi beta), the radius with
+ *            which it holds mass M; a point-like source adds no core, in
+ *            Eq. (10) as elsewhere. A pair with s = 0 (massless cored
+ *            bodies) keeps the softened law. f_ab still multiplies.
+ *   cored    accumulator: bit b set = species b is cored (< 2^D)
+ *   beta     accumulator: the dimensionless scale of Eqs. (13)-(15), > 0
  */
 typedef struct {
     const double* G;
@@ -139,6 +158,9 @@ typedef struct {
     double eps;
     double theta;
     uint32_t group_size;
+    uint32_t law;
+    uint32_t cored;
+    double beta;
 } ngr_force_params;
 
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the

@@ -45,7 +45,7 @@ class TreeParams(C.Structure):
 class ForceParams(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32), ("grid", C.c_uint32),
                 ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
-                ("group_size", C.c_uint32)]
+                ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double)]
 
 
 class ForceStats(C.Structure):
@@ -202,23 +202,34 @@ def compute_monopoles(ctx: Context, tree: Tree, track_counts: bool = True):
     ctx._check(lib().ngr_compute_monopoles(ctx.handle, tree.handle, int(track_counts)), "monopoles")
 
 
-def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None):
+LAW_TABLE, LAW_ACCUMULATOR = 0, 1
+
+
+def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None, accumulator=None):
+    """accumulator: None for a table law, else {"cored": species indices,
+    "beta": beta} for the accumulator laws."""
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
     if tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
         ntab = tables.shape[-1]
+    law, mask, beta = LAW_TABLE, 0, 0.0
+    if accumulator is not None:
+        law, beta = LAW_ACCUMULATOR, float(accumulator["beta"])
+        for b in accumulator["cored"]:
+            mask |= 1 << int(b)
     fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS.get(grid, grid),
-                     float(r_s), float(r_cut), float(eps), float(theta), int(group_size))
+                     float(r_s), float(r_cut), float(eps), float(theta), int(group_size), law, mask, beta)
     fp._keep = (G, tables)
     return fp
 
 
 def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
-               group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False):
+               group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None):
     """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
-    G (D x D) and tables (D x D x ntab, or None) are host arrays. Returns the
-    statistics as a dict (and per-group counts when asked)."""
-    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab)
+    G (D x D) and tables (D x D x ntab, or None) are host arrays;
+    accumulator {"cored": [...], "beta": b} selects the accumulator laws.
+    Returns the statistics as a dict (and per-group counts when asked)."""
+    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator)
     st = ForceStats()
     if group_counts:
         ng = groups_count(ctx, tree, group_size)
@@ -282,11 +293,12 @@ class BatchBox:
     group_size 0 lets the library choose."""
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
-                 leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None):
+                 leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
+                 accumulator=None):
         self.n = int(species.shape[0])
         self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
         self.tree = TreeParams(leaf_size)
-        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab)
+        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator)
         self.acc = _dev(acc)
         self._keep = (species, mass, pos, lattice, acc)
 
@@ -320,12 +332,14 @@ class Server:
         ctx._check(lib().ngr_server_create(ctx.handle, C.byref(sp), C.byref(self._h)), "server create")
 
     def submit(self, *, D, box, species, mass, G, tables, grid, r_cut, eps, theta, dt, steps, pos=None, lattice=None,
-               vel=None, leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None) -> int:
+               vel=None, leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
+               accumulator=None) -> int:
         """Device tensors species, mass, pos or lattice, vel (or None); host G
         and tables. The data are copied; returns the request id."""
         n = int(species.shape[0])
         rq = RequestDesc(Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass)), _dev(vel),
-                         TreeParams(leaf_size), _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab),
+                         TreeParams(leaf_size),
+                         _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator),
                          float(dt), int(steps))
         rid = C.c_uint64()
         self.ctx._check(lib().ngr_server_submit(self._h, C.byref(rq), C.byref(rid)), "server submit")

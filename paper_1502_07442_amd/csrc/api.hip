@@ -153,6 +153,12 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     if (!fp->tables && !ngr::finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
     const uint32_t gs = fp->group_size;
     if (gs != 0 && gs != 16 && gs != 32 && gs != 64) fail(NGR_EINVAL, where + "group_size must be 16, 32 or 64 (or 0)");
+    if (fp->law != NGR_LAW_TABLE && fp->law != NGR_LAW_ACCUMULATOR)
+        fail(NGR_EINVAL, where + "law must be NGR_LAW_TABLE or NGR_LAW_ACCUMULATOR");
+    if (fp->law == NGR_LAW_ACCUMULATOR) {
+        if (fp->cored >> D) fail(NGR_EINVAL, where + "cored names a species >= D");
+        if (!ngr::finite_pos(fp->beta)) fail(NGR_EINVAL, where + "beta must be finite and > 0");
+    }
     for (uint32_t k = 0; k < D * D; ++k)
         if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, where + "G has a non-finite entry");
     if (fp->tables)
@@ -246,6 +252,7 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             ngr::make_groups(c, *tree, std::vector<uint32_t>{gs}, g);
             ngr::hip_check(hipEventRecord(e1, c.stream), "hipEventRecord", __FILE__, __LINE__);
             ngr::make_law(*fp, tree->D, laws[0]);
+            laws[0].track = tree->track_counts ? 1u : 0u;
             if (tree->n) tab_block = ngr::upload_tables(c, laws, tabs);
             if (group_counts_host && g.ng) gc = static_cast<uint64_t*>(c.alloc(g.ng * 4 * sizeof(uint64_t)));
             ngr::walk_force(c, *tree, g, laws, tabs, std::vector<double*>{acc}, gc, wo);
@@ -351,10 +358,10 @@ NGR_API ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p, cons
 
 NGR_API ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_counts)
 {
-    (void)track_counts;
     return guarded(ctx, [&] {
         if (!tree) ngr::fail(NGR_EINVAL, "tree is NULL");
         ngr::compute_monopoles(*ctx, *tree);
+        tree->track_counts = track_counts != 0;
         ctx->sync();
     });
 }

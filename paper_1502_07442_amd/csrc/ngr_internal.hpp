@@ -55,6 +55,7 @@ struct Context {
     // persistent scratch reused across calls
     DevMem stacks;          // per-wave traversal stacks of the walk
     DevMem counters;        // small device counters (queues, statistics, flags)
+    DevMem core;            // core-factor table of the accumulator laws (built on first use)
     uint64_t* pinned = nullptr;                   // pinned host staging, kPinnedWords
     static constexpr size_t kPinnedWords = 64;
 
@@ -127,6 +128,7 @@ struct Tree {
     // monopoles: D x nn records {com_x, com_y, com_z (box fraction), M}
     double4* mono = nullptr;
     bool has_monopoles = false;
+    bool track_counts = true;      // N_perp option of the monopoles (accumulator laws)
 };
 void free_tree(Context& ctx, Tree& t);
 
@@ -187,6 +189,10 @@ struct Law {
     double r_cut = 0, eps = 0, theta = 0;
     const double* tables = nullptr;   // host, D x D x ntab samples, or NULL: def for every pair
     std::vector<double> def;          // host, ntab samples of the Newtonian short-range factor
+    uint32_t kind = NGR_LAW_TABLE;    // accumulator laws: cored species mask, beta, N_perp tracking
+    uint32_t cored = 0;
+    uint32_t track = 1;
+    double beta = 0;
 };
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
 

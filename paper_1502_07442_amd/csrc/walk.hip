@@ -229,6 +229,13 @@ constexpr int kRec = 68;               // record slots per wave: 64 and up to 3 
 constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
 constexpr int kMaxWaves = 16;          // waves per workgroup
 constexpr int kCtrlBytes = 512;        // LDS control area ahead of the tables
+// Accumulator laws: per wave, the core scale of each record (float64) after
+// the other buffers; per workgroup, the core-factor table after the force
+// tables (kCoreN intervals on u = r / (s + r) in [0, 1], PAIR layout, the
+// last entry (1, 0)).
+constexpr int kWaveLdsAcc = kWaveLds + kRec * 8;
+constexpr int kCoreN = 2048;
+constexpr int kCoreBytes = ((kCoreN + 1) * 8 + 255) & ~255;
 // Table layouts in LDS. PAIR: per interval (value, slope to the next sample),
 // with a (0, 0) entry that the clamped index reaches for r >= r_cut. VALUE:
 // the samples only (plus one pad), the slope taken from the next sample and
@@ -245,6 +252,8 @@ struct BoxParams {
     const float* value;        // the box's tables, VALUE layout
     float tscale, toff, tmax;
     uint32_t wrap_limit, D, ntab;
+    double inv4pib;            // accumulator laws: 1 / (4 pi beta); 0 for a table law
+    uint32_t cored, track;     // cored species mask (0 for a table law); N_perp tracking
 };
 
 // Per-lane-invariant values of the pair term, taken from the box.
@@ -287,6 +296,7 @@ struct WalkArgs {
     uint32_t max_steps;        // traversal batches per group never exceed the node count
     uint32_t tab_bytes;        // LDS bytes of the largest segment's tables
     BoxParams box0;            // the box of a one-box call (read from the arguments)
+    const float2* core;        // accumulator laws: the core-factor table (kCoreN + 1 entries)
 };
 
 __device__ inline void wave_sync()
@@ -360,6 +370,72 @@ __device__ inline void eval_records(const PairParams& A, const double4* __restri
     }
 }
 
+// Pair terms of a cored pair of species (accumulator laws). With s the
+// pair's core scale (record's core plus the sink's), the force of the
+// Eq. (14) potential is (2/pi) [atan x - x / (1 + x^2)] / r^3, x = r / s.
+// Written as C(u) / (s + r)^3 with u = r / (s + r), C is smooth and between
+// 0.42 and 1.54 on [0, 1] and is read, linearly interpolated, from a table
+// of kCoreN intervals (relative error below 3e-7); C(1) = 1 gives the
+// Newtonian factor, so a pair without a core (s = 0) takes the softened law
+// from r -> sqrt(r^2 + eps^2). r and 1 / (s + r) come from the float32
+// hardware estimates refined by one float64 Newton step each. The records
+// carry G m (not 1.5 G m) and rs[] the source's core scale.
+template <int GRID, int TAB, bool WRAP, uint32_t K>
+__device__ inline void eval_cored(const PairParams& A, const double4* __restrict__ rec, const double* __restrict__ rs,
+                                  uint32_t iters, const void* __restrict__ tbv, const float2* __restrict__ core,
+                                  double s_sink, double ox, double oy, double oz, double& ax, double& ay, double& az)
+{
+    const double eps2 = A.eps2;
+    const float tscale = A.tscale, tmax = A.tmax;
+    NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
+    for (uint32_t it = 0; it < iters; ++it) {
+        const double4 s = rec[it * K];
+        const double sc = rs[it * K] + s_sink;
+        double dx = s.x - ox, dy = s.y - oy, dz = s.z - oz;
+        if (WRAP) {
+            dx -= A.box * rint(dx * A.inv_box);
+            dy -= A.box * rint(dy * A.inv_box);
+            dz -= A.box * rint(dz * A.inv_box);
+        }
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double re2 = sc > 0.0 ? r2 : r2 + eps2;
+        const double z = (double)__builtin_amdgcn_rsqf((float)re2);
+        const double h = re2 * z;                          // r estimate
+        const double rr = h * fma(-0.5 * h, z, 1.5);       // one Newton step on 1 / sqrt
+        const double wd = sc + rr;
+        double y = (double)__builtin_amdgcn_rcpf((float)wd);
+        y = y * fma(-wd, y, 2.0);                          // one Newton step on 1 / w
+        float tu = (float)(rr * y) * (float)kCoreN;
+        tu = __builtin_amdgcn_fmed3f(tu, 0.0f, (float)kCoreN);
+        // r = 0 makes tu NaN (its term is dropped below): the unsigned clamp
+        // keeps the index inside the table whatever the conversion gives
+        const uint32_t ku = min((uint32_t)(int)tu, (uint32_t)kCoreN);
+        const float2 Cu = core[ku];
+        const float c = fmaf(__builtin_amdgcn_fractf(tu), Cu.y, Cu.x);
+        float t;
+        if (GRID == NGR_GRID_R2) t = (float)r2 * tscale;
+        else t = __builtin_sqrtf((float)r2) * tscale;
+        t = __builtin_amdgcn_fmed3f(t, 0.0f, tmax);
+        const int k = (int)t;
+        const float w = __builtin_amdgcn_fractf(t);
+        float f;
+        if (TAB == kPair) {
+            const float2 T = static_cast<const float2*>(tbv)[k];
+            f = fmaf(w, T.y, T.x);
+        } else {
+            const float* tv = static_cast<const float*>(tbv);
+            const float t0 = tv[k], t1 = tv[k + 1];
+            f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
+        }
+        const double y3 = y * y * y;
+        double coef = (double)(f * c) * s.w * y3;
+        coef = r2 > 0.0 ? coef : 0.0;
+        ax = fma(coef, dx, ax);
+        ay = fma(coef, dy, ay);
+        az = fma(coef, dz, az);
+    }
+}
+
 // Bytes of LDS the tables of one sink species take in a layout.
 __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t ntab)
 {
@@ -367,7 +443,7 @@ __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t n
     return (raw + 255u) & ~255u;
 }
 
-template <int GRID, int TAB, bool EPS0, bool ONE>
+template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC>
 __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
     HIP_DYNAMIC_SHARED(unsigned char, smem);
@@ -378,8 +454,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
     unsigned long long* part = reinterpret_cast<unsigned long long*>(smem + 256);   // 2 per wave
     unsigned char* tsm = smem + kCtrlBytes;
-    unsigned char* wb = tsm + A.tab_bytes + wave * kWaveLds;
+    constexpr int kWL = ACC ? kWaveLdsAcc : kWaveLds;
+    unsigned char* wb = tsm + A.tab_bytes + wave * kWL;
     double4* rec = reinterpret_cast<double4*>(wb);
+    double* recs = reinterpret_cast<double*>(wb + kWaveLds);            // ACC: core scale of each record
+    float2* core_tab = reinterpret_cast<float2*>(tsm + A.tab_bytes - kCoreBytes);   // ACC
     uint32_t* pnb = reinterpret_cast<uint32_t*>(wb + kRec * 32);
     uint32_t* ppb = pnb + kBuf;
     uint32_t* scanb = ppb + kBuf;        // 68 entries
@@ -396,6 +475,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     // segment has started, joins the one with the most groups left.
     uint32_t seg = A.sched[blockIdx.x % A.nsched];
     bool any_overflow = false;
+    if (ACC)   // the core-factor table is the same for every segment; the first segment's barrier publishes it
+        for (uint32_t k = threadIdx.x; k <= (uint32_t)kCoreN; k += blockDim.x) core_tab[k] = A.core[k];
     for (;;) {
         const uint32_t bxi = seg / D, a = seg % D;
         const BoxParams& P = ONE ? A.box0 : A.boxes[bxi];
@@ -418,6 +499,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         const uint64_t in_off = P.in_off, nbx = P.n;
         const double* const Ga = P.G + a * Dk;
         const uint32_t g_begin = A.seg_first[seg], g_count = A.seg_first[seg + 1] - g_begin;
+        const uint32_t cmask = ACC ? P.cored : 0u;          // cored species (accumulator laws)
+        const bool core_a = (cmask >> a) & 1u;
+        const double inv4pib = P.inv4pib;
+        const bool track = P.track != 0u;
         uint32_t* const queue = A.queues + seg;
         unsigned long long tot_pp = 0, tot_pn = 0;
 
@@ -464,10 +549,23 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         }
         double ax = 0.0, ay = 0.0, az = 0.0;
         unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
+        // the sink's own core scale (accumulator laws, cored sink species)
+        double s_sink = 0.0;
+        if (ACC && core_a && sink < ns) s_sink = A.mass[s0 + sink] * inv4pib;
+        // a pair of species (a, b) takes the cored law when either is cored
+        auto cored_pair = [&](uint32_t b) { return ACC && (core_a || ((cmask >> b) & 1u)); };
 
         auto eval = [&](uint32_t b, uint32_t nrec) {
             const unsigned char* tb = tsm + (TAB == kPair ? 8u : 4u) * b * tstride;
             const uint32_t iters = (nrec + K - 1u) >> lk;
+            if (cored_pair(b)) {
+                const double* rrs = recs + replica;
+                if (wrap) eval_cored<GRID, TAB, true, 1>(pp, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else eval_cored<GRID, TAB, false, 4>(pp, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                return;
+            }
             if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
             else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
             else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
@@ -484,14 +582,25 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 const bool v = (uint32_t)lane < k && r.w > 0.0;
                 const uint64_t m = __ballot(v);
                 const uint32_t nrec = (uint32_t)__popcll(m);
+                const bool cp = cored_pair(b);
                 if (v) {
                     double d0 = r.x - cf0, d1 = r.y - cf1, d2 = r.z - cf2;
                     d0 -= rint(d0);
                     d1 -= rint(d1);
                     d2 -= rint(d2);
-                    rec[__popcll(m & lt)] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w);
+                    const uint32_t slot = (uint32_t)__popcll(m & lt);
+                    rec[slot] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w * (cp ? 2.0 / 3.0 : 1.0));
+                    if (cp) {
+                        // a monopole of N_perp bodies: each of mass M / N_perp when tracked
+                        double body = r.w;
+                        if (track) body /= (double)A.count[(uint64_t)node * D + b];
+                        recs[slot] = ((cmask >> b) & 1u) ? body * inv4pib : 0.0;
+                    }
                 }
-                if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
+                if (K > 1u && (uint32_t)lane < 3u) {
+                    rec[nrec + lane] = pad;
+                    if (cp) recs[nrec + lane] = 1.0;
+                }
                 wave_sync();
                 if (b + 1 < Dk && (uint32_t)lane < k) r = A.mono[(uint64_t)(b + 1) * A.nn + node];
                 if (nrec) eval(b, nrec);
@@ -566,10 +675,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             stage(base, T);
             for (;;) {
                 const uint32_t nrec = min(64u, T - base);
-                if (sv)
+                const bool cp = cored_pair(b);
+                if (sv) {
                     rec[lane] = make_double4((double)(int64_t)(sx - C0) * scale, (double)(int64_t)(sy - C1) * scale,
-                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm);
-                if (K > 1u && (uint32_t)lane < 3u) rec[nrec + lane] = pad;
+                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm * (cp ? 2.0 / 3.0 : 1.0));
+                    if (cp) recs[lane] = ((cmask >> b) & 1u) ? sm * inv4pib : 0.0;
+                }
+                if (K > 1u && (uint32_t)lane < 3u) {
+                    rec[nrec + lane] = pad;
+                    if (cp) recs[nrec + lane] = 1.0;
+                }
                 wave_sync();
                 // the next chunk: the rest of this species, else the next species with particles
                 uint32_t nb = b, nbase = base + 64u, nT = T;
@@ -868,6 +983,10 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.theta = fp.theta;
     for (uint32_t k = 0; k < D * D; ++k) law.G[k] = fp.G[k];
     law.tables = fp.tables;
+    law.kind = fp.law;
+    law.cored = fp.law == NGR_LAW_ACCUMULATOR ? fp.cored : 0u;
+    law.beta = fp.beta;
+    law.track = 1;
     law.def.clear();
     if (!fp.tables) {
         const uint32_t ntab = fp.ntab;
@@ -929,6 +1048,35 @@ void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawT
         out[k].value = value + jobs[k].value;
     }
     return block;
+}
+
+// The core factor of the accumulator laws, C(u) = (2/pi) g(x) (1 + x)^3 with
+// x = u / (1 - u) and g(x) = [atan x - x / (1 + x^2)] / x^3 (2/3 - 4x^2/5 +
+// 6x^4/7 below x = 1e-2, where the difference cancels), at u = k / kCoreN,
+// in the PAIR layout (value, slope to the next sample); C(1) = 1. Built in
+// float64 on the host once per context.
+static void upload_core_table(Context& ctx)
+{
+    if (ctx.core.p) return;
+    std::vector<double> c(kCoreN + 1);
+    for (int k = 0; k < kCoreN; ++k) {
+        const double u = (double)k / kCoreN, x = u / (1.0 - u);
+        double v;
+        if (x < 1e-2) {
+            const double x2 = x * x;
+            v = (2.0 / 3.0 - 0.8 * x2 + (6.0 / 7.0) * x2 * x2) * (1.0 + x) * (1.0 + x) * (1.0 + x);
+        } else {
+            const double q = 1.0 + 1.0 / x;
+            v = (std::atan(x) - x / (1.0 + x * x)) * q * q * q;
+        }
+        c[k] = v * (2.0 / M_PI);
+    }
+    c[kCoreN] = 1.0;
+    std::vector<float2> t(kCoreN + 1);
+    for (int k = 0; k < kCoreN; ++k) t[k] = make_float2((float)c[k], (float)(c[k + 1] - c[k]));
+    t[kCoreN] = make_float2(1.0f, 0.0f);
+    ctx.ensure(ctx.core, t.size() * sizeof(float2));
+    ctx.to_device(ctx.core.p, t.data(), t.size() * sizeof(float2));
 }
 
 // Group indices segment by segment, each segment's groups in descending
@@ -996,7 +1144,9 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     out.box_pn.assign(nbox, 0);
     if (t.n == 0 || g.ng == 0) return;
     const uint32_t grid = laws[0].grid;
-    bool eps0 = false;
+    bool eps0 = false, acc_law = false;
+    for (uint32_t k = 0; k < nbox; ++k) acc_law |= laws[k].kind == NGR_LAW_ACCUMULATOR;
+    if (acc_law) upload_core_table(ctx);
     uint32_t pair_max = 0, value_max = 0;
     for (uint32_t k = 0; k < nbox; ++k) {
         if (laws[k].grid != grid) fail(NGR_EINVAL, "the boxes of one call must share the table grid");
@@ -1006,16 +1156,18 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     }
     // layout and workgroup shape within the LDS of one workgroup: the
     // (value, slope) tables when at least 8 waves still fit beside them
+    // (accumulator laws add the core-factor table and a core scale per record)
     const size_t lds_max = ctx.lds_per_block;
+    const size_t wave_lds = acc_law ? kWaveLdsAcc : kWaveLds, extra = acc_law ? kCoreBytes : 0;
     int mode = kPair;
-    size_t tab_bytes = pair_max;
-    if (kCtrlBytes + tab_bytes + 8 * (size_t)kWaveLds > lds_max) {
+    size_t tab_bytes = pair_max + extra;
+    if (kCtrlBytes + tab_bytes + 8 * wave_lds > lds_max) {
         mode = kValue;
-        tab_bytes = value_max;
+        tab_bytes = value_max + extra;
     }
-    if (kCtrlBytes + tab_bytes + kWaveLds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
-    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - kCtrlBytes - tab_bytes) / kWaveLds);
-    const size_t lds = kCtrlBytes + tab_bytes + (size_t)waves * kWaveLds;
+    if (kCtrlBytes + tab_bytes + wave_lds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
+    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - kCtrlBytes - tab_bytes) / wave_lds);
+    const size_t lds = kCtrlBytes + tab_bytes + (size_t)waves * wave_lds;
     const size_t per_cu = std::max<size_t>(1, lds_max / lds);
     const int blocks = ctx.num_cu * (int)std::min<size_t>(per_cu, 4);
     const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
@@ -1053,6 +1205,11 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         P.ntab = law.ntab;
         P.pair = tables[k].pair;
         P.value = tables[k].value;
+        if (law.kind == NGR_LAW_ACCUMULATOR) {
+            P.cored = law.cored;
+            P.inv4pib = 1.0 / (4.0 * M_PI * law.beta);
+        }
+        P.track = law.track;
     }
     BoxParams* boxes = static_cast<BoxParams*>(ctx.alloc(nbox * sizeof(BoxParams)));
     ctx.to_device(boxes, bp.data(), nbox * sizeof(BoxParams));
@@ -1125,6 +1282,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     A.error_flag = err;
     A.max_steps = (uint32_t)std::min<uint64_t>(t.nn + 1, 0xffffffffull);
     A.tab_bytes = (uint32_t)tab_bytes;
+    A.core = acc_law ? static_cast<const float2*>(ctx.core.p) : nullptr;
 
     HIP_CHECK(hipEventRecord(e1, ctx.stream));
     ctx.stage("walk: launch");
@@ -1133,25 +1291,35 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(waves * 64), lds, ctx.stream, A);
         LAUNCH_CHECK("walk_kernel");
     };
-    // a one-box call reads its box's parameters from the kernel arguments
-    const int sel = (nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
+    // a one-box call reads its box's parameters from the kernel arguments;
+    // the accumulator laws read them from the table in device memory
+    const int sel = (acc_law ? 16 : nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) +
+                    (eps0 ? 1 : 0);
     switch (sel) {
-    case 0: launch(walk_kernel<NGR_GRID_R, kPair, false, false>); break;
-    case 1: launch(walk_kernel<NGR_GRID_R, kPair, true, false>); break;
-    case 2: launch(walk_kernel<NGR_GRID_R, kValue, false, false>); break;
-    case 3: launch(walk_kernel<NGR_GRID_R, kValue, true, false>); break;
-    case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false, false>); break;
-    case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true, false>); break;
-    case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false, false>); break;
-    case 7: launch(walk_kernel<NGR_GRID_R2, kValue, true, false>); break;
-    case 8: launch(walk_kernel<NGR_GRID_R, kPair, false, true>); break;
-    case 9: launch(walk_kernel<NGR_GRID_R, kPair, true, true>); break;
-    case 10: launch(walk_kernel<NGR_GRID_R, kValue, false, true>); break;
-    case 11: launch(walk_kernel<NGR_GRID_R, kValue, true, true>); break;
-    case 12: launch(walk_kernel<NGR_GRID_R2, kPair, false, true>); break;
-    case 13: launch(walk_kernel<NGR_GRID_R2, kPair, true, true>); break;
-    case 14: launch(walk_kernel<NGR_GRID_R2, kValue, false, true>); break;
-    default: launch(walk_kernel<NGR_GRID_R2, kValue, true, true>); break;
+    case 0: launch(walk_kernel<NGR_GRID_R, kPair, false, false, false>); break;
+    case 1: launch(walk_kernel<NGR_GRID_R, kPair, true, false, false>); break;
+    case 2: launch(walk_kernel<NGR_GRID_R, kValue, false, false, false>); break;
+    case 3: launch(walk_kernel<NGR_GRID_R, kValue, true, false, false>); break;
+    case 4: launch(walk_kernel<NGR_GRID_R2, kPair, false, false, false>); break;
+    case 5: launch(walk_kernel<NGR_GRID_R2, kPair, true, false, false>); break;
+    case 6: launch(walk_kernel<NGR_GRID_R2, kValue, false, false, false>); break;
+    case 7: launch(walk_kernel<NGR_GRID_R2, kValue, true, false, false>); break;
+    case 8: launch(walk_kernel<NGR_GRID_R, kPair, false, true, false>); break;
+    case 9: launch(walk_kernel<NGR_GRID_R, kPair, true, true, false>); break;
+    case 10: launch(walk_kernel<NGR_GRID_R, kValue, false, true, false>); break;
+    case 11: launch(walk_kernel<NGR_GRID_R, kValue, true, true, false>); break;
+    case 12: launch(walk_kernel<NGR_GRID_R2, kPair, false, true, false>); break;
+    case 13: launch(walk_kernel<NGR_GRID_R2, kPair, true, true, false>); break;
+    case 14: launch(walk_kernel<NGR_GRID_R2, kValue, false, true, false>); break;
+    case 15: launch(walk_kernel<NGR_GRID_R2, kValue, true, true, false>); break;
+    case 16: launch(walk_kernel<NGR_GRID_R, kPair, false, false, true>); break;
+    case 17: launch(walk_kernel<NGR_GRID_R, kPair, true, false, true>); break;
+    case 18: launch(walk_kernel<NGR_GRID_R, kValue, false, false, true>); break;
+    case 19: launch(walk_kernel<NGR_GRID_R, kValue, true, false, true>); break;
+    case 20: launch(walk_kernel<NGR_GRID_R2, kPair, false, false, true>); break;
+    case 21: launch(walk_kernel<NGR_GRID_R2, kPair, true, false, true>); break;
+    case 22: launch(walk_kernel<NGR_GRID_R2, kValue, false, false, true>); break;
+    default: launch(walk_kernel<NGR_GRID_R2, kValue, true, false, true>); break;
     }
     HIP_CHECK(hipEventRecord(e2, ctx.stream));
     std::vector<uint64_t> counts(2ull * nseg);

@@ -30,6 +30,7 @@ __all__ = [
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
+    "accumulator_problem",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -64,6 +65,8 @@ class Problem:
     pos: Optional[np.ndarray] = None       # (3, n) float64
     lattice: Optional[np.ndarray] = None   # (3, n) uint64
     seed: int = 0
+    # accumulator laws (section 3.3): {"cored": species indices, "beta": beta}, or None
+    accumulator: Optional[dict] = None
 
     @property
     def ntab(self) -> int:
@@ -309,3 +312,27 @@ def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson stream of `rate` per second."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def accumulator_problem(n: int, seed: int, *, D: int = 2, cored=(1,), core_frac: float = 0.25,
+                        f_cl: float = 0.7, grid: str = GRID_R2, ntab: int = 2048, theta: float = 0.5,
+                        leaf_size: int = 16, group_size: int = 64, box: float = 1.0) -> Problem:
+    """The two-species setting of the accumulator test (section 3.3, Fig. 6)
+    on the short-range path: clustered box, equal species fractions, unit
+    masses 1/n, G = 1 and the Newtonian short-range factor for every pair,
+    the species in `cored` cored. beta makes the core radius of one body,
+    m / (4 pi beta), core_frac of the mean spacing (the paper's beta is in
+    the units of its own runs)."""
+    rng = np.random.default_rng(seed)
+    halos = max(1, int(round(2000 * n / 2 ** 21)))
+    pos = clustered_positions(n, box, rng, f_cl=f_cl, halos=halos)
+    species = exact_species(n, np.ones(D), rng)
+    r_s, r_cut, eps = scaled_params(n, box)
+    t = sample_table(lambda r: newtonian_treepm_factor(r, r_s), ntab, r_cut, grid)
+    tables = np.broadcast_to(t, (D, D, ntab)).copy()
+    m = 1.0 / n
+    beta = m / (4.0 * math.pi * core_frac * box / n ** (1.0 / 3.0))
+    return Problem(name=f"accumulator-{n}-D{D}-seed{seed}", n=n, D=D, box=box, species=species,
+                   mass=np.full(n, m), G=np.ones((D, D)), tables=tables, grid=grid, r_s=r_s, r_cut=r_cut,
+                   eps=eps, theta=theta, leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed,
+                   accumulator={"cored": [int(b) for b in cored], "beta": float(beta)})

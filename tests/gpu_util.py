@@ -19,17 +19,19 @@ def device_inputs(p):
     return dict(species=species, mass=mass, pos=pos, lattice=lat)
 
 
-def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None):
-    """Build, monopoles and force on the GPU. Returns (acc (3, n) numpy,
-    stats, per-group counts or None, tree or None)."""
+def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None, track_counts=True):
+    """Build, monopoles and force on the GPU (the accumulator laws when p
+    has them). Returns (acc (3, n) numpy, stats, per-group counts or None,
+    tree or None)."""
     import torch
     t = device_inputs(p)
     tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
-    ngr.compute_monopoles(ctx, tree)
+    ngr.compute_monopoles(ctx, tree, track_counts=track_counts)
     acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
     gs = p.group_size if group_size is None else group_size
     res = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
-                         theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts)
+                         theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts,
+                         accumulator=getattr(p, "accumulator", None))
     st, gc = (res if group_counts else (res, None))
     out = acc.cpu().numpy()
     if not keep_tree:

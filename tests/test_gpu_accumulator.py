@@ -1,0 +1,132 @@
+"""Accumulator laws (section 3.3, Eqs. (13)-(17)) on the HIP path against the
+oracle: exact interaction counts, forces per particle within
+1e-5 rms|a| + slack (the gate of the table laws), with N_perp tracked and
+untracked, every group-size path (one, two and four copies of a group per
+wave), both table grids, softened and unsoftened, the periodic-wrap groups,
+massless cored bodies, and boxes of both law kinds in one batched call."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1502_07442_amd as ngr
+import synth
+from gpu_util import device_inputs, force_gate, gpu_solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ngr.Context(0)
+    yield c
+    c.close()
+
+
+def parity(ctx, p, group_size=None, track=True):
+    gs = group_size or p.group_size
+    print(f"case {p.name} n={p.n} D={p.D} grid={p.grid} Ng={gs} cored={p.accumulator['cored']} "
+          f"track={track} eps={p.eps:.3g}", flush=True)
+    acc, st, gc, _ = gpu_solve(ctx, p, group_counts=True, group_size=gs, track_counts=track)
+    T = oracle.Tree.of(p, group_size=gs)
+    ao, so, co, gco = T.force(oracle.law_of(p, track_counts=track), group_counts=True)
+    assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"])
+    assert np.array_equal(gc, gco)
+    ok, worst, rms, mx = force_gate(acc, ao, so)
+    print(f"  interactions={co['pp'] + co['pn']} worst/allowed={worst:.3g} max|da|/rms={mx:.3g}", flush=True)
+    assert ok, f"force gate: worst ratio {worst}"
+    return acc, ao
+
+
+@pytest.mark.parametrize("gs", [64, 32, 16])
+@pytest.mark.parametrize("track", [True, False])
+def test_two_species(ctx, gs, track):
+    parity(ctx, synth.accumulator_problem(20000, 3), group_size=gs, track=track)
+
+
+@pytest.mark.parametrize("grid,cored,D", [(synth.GRID_R, (1, 2), 3), (synth.GRID_R2, (0, 1), 2),
+                                          (synth.GRID_R2, (0, 2, 5), 6)])
+def test_species_mixes(ctx, grid, cored, D):
+    parity(ctx, synth.accumulator_problem(15000, 7 + D, D=D, cored=cored, grid=grid, ntab=1024), group_size=32)
+
+
+def test_random_laws_unsoftened(ctx):
+    """Random G and Yukawa-product tables under the cores, eps = 0."""
+    p = synth.clustered_problem(12000, 3, 21, grid=synth.GRID_R2, ntab=512)
+    p = dataclasses.replace(p, eps=0.0, accumulator={"cored": [0, 2], "beta": 1.0 / (4 * np.pi * 12000 * 0.01)})
+    parity(ctx, p, group_size=32)
+
+
+def test_wrap_groups(ctx):
+    """Few particles: groups wide enough to need the periodic wrap per pair."""
+    p = synth.uniform_problem(300, 2, 4, grid=synth.GRID_R2)
+    p = dataclasses.replace(p, accumulator={"cored": [1], "beta": 1.0 / (4 * np.pi * 300 * 0.05)})
+    parity(ctx, p, group_size=64)
+
+
+def test_massless_cored_bodies(ctx):
+    """Massless bodies of the cored species: pairs of a massless cored sink
+    and a point-like source have no core and keep the softened law."""
+    p = synth.accumulator_problem(8000, 5)
+    m = p.mass.copy()
+    m[(p.species == 1) & (np.arange(p.n) % 3 == 0)] = 0.0
+    parity(ctx, dataclasses.replace(p, mass=m), group_size=32)
+
+
+def test_tracking_matters(ctx):
+    """Tracked and untracked results differ well beyond the gate (section 3.3)."""
+    p = synth.accumulator_problem(20000, 3)
+    a1, _, _, _ = gpu_solve(ctx, p, track_counts=True)
+    a0, _, _, _ = gpu_solve(ctx, p, track_counts=False)
+    rms = np.sqrt(np.mean(np.sum(a1 ** 2, axis=0)))
+    assert np.max(np.linalg.norm(a1 - a0, axis=0)) > 1e-3 * rms
+
+
+def test_batch_mixed_law_kinds(ctx):
+    """A table-law box and accumulator boxes in one call: each bitwise equal
+    to its single-box call, counts equal to the oracle's."""
+    import torch
+    probs = [synth.clustered_problem(6000, 2, 31, grid=synth.GRID_R2, ntab=512),
+             synth.accumulator_problem(9000, 32, ntab=512),
+             synth.accumulator_problem(5000, 33, D=3, cored=(0, 2), ntab=512)]
+    boxes, accs = [], []
+    for p in probs:
+        acc = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
+        boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut,
+                                  eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=32,
+                                  accumulator=p.accumulator, **device_inputs(p)))
+        accs.append(acc)
+    _, pb = ngr.batch_build_force(ctx, boxes, per_box=True)
+    for p, acc, st in zip(probs, accs, pb):
+        a = acc.cpu().numpy()
+        a1, st1, _, _ = gpu_solve(ctx, p, group_size=32)
+        assert np.array_equal(a1, a), p.name
+        ao, so, co, _ = oracle.Tree.of(p, group_size=32).force(oracle.law_of(p))
+        assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"]), p.name
+        assert force_gate(a, ao, so)[0], p.name
+
+
+@pytest.mark.parametrize("bad", [dict(beta=0.0), dict(beta=float("nan")), dict(cored=[2]), dict(law=2)])
+def test_invalid_parameters(ctx, bad):
+    import torch
+    p = synth.accumulator_problem(1000, 2)
+    t = device_inputs(p)
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
+    try:
+        ngr.compute_monopoles(ctx, tree)
+        acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+        accd = dict(p.accumulator)
+        accd.update({k: v for k, v in bad.items() if k != "law"})
+        fp = ngr._force_params(p.D, p.G, p.tables, p.grid, p.r_s, p.r_cut, p.eps, p.theta, 32, None, accd)
+        if "law" in bad:
+            fp.law = bad["law"]
+        import ctypes as C
+        st = ngr.ForceStats()
+        rc = ngr.lib().ngr_tree_force(ctx.handle, tree.handle, C.byref(fp), C.c_void_p(acc.data_ptr()), C.byref(st))
+        assert rc == -1
+    finally:
+        ngr.tree_free(ctx, tree)
