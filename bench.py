@@ -30,7 +30,8 @@ def log(*a):
 def walk_traffic():
     """HBM bytes of one walk launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
-    None when the walk sources have changed since the counters were taken."""
+    None when the walk kernel's source has changed since the counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "walk_clustered_2p24_D6_counters.md")
     if not os.path.exists(path):
@@ -41,9 +42,8 @@ def walk_traffic():
         if k in ("walk_traffic_bytes", "source_sha256"):
             fields[k] = v.strip()
     h = hashlib.sha256()
-    for f in ("walk.hip", "ngr_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1502_07442_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1502_07442_amd", "csrc", "walk.hip"), "rb") as fh:
+        h.update(fh.read())
     if fields.get("source_sha256") != h.hexdigest() or "walk_traffic_bytes" not in fields:
         return None
     return float(fields["walk_traffic_bytes"])
@@ -264,6 +264,36 @@ def accumulator(ngr, synth, n=2 ** 22, steps=3):
             "table_law_walk_ms": res["table"][1], "cored_walk_over_table_walk": walk / res["table"][1]}
 
 
+def short_tables(ngr, synth, D=6, ntab=2048, reps=5):
+    """Exact short-range tables (section 2.4.1) for D x D random Newton and
+    Yukawa laws at the benchmark box's r_s and r_cut: the time of one
+    ngr_short_range_tables call (host samples in, host tables out), and the
+    Newtonian pairs' largest deviation from the closed-form factor."""
+    import numpy as np
+    r_s, r_cut, _ = synth.scaled_params(2 ** 24)
+    laws = synth.exact_split_laws(D, 7)
+    rng = max(l[2] for row in laws for l in row)
+    nk, dk = ngr.short_range_grid(r_s, r_cut, rng)
+    ks = np.arange(nk) * dk
+    radii = synth.table_abscissae(ntab, r_cut, synth.GRID_R2)
+    phib = np.array([[laws[a][b][0](ks) for b in range(D)] for a in range(D)])
+    full = np.array([[laws[a][b][1](radii) for b in range(D)] for a in range(D)])
+    ctx = ngr.Context(0)
+    t = ngr.short_range_tables(ctx, phibar=phib, f_full=full, r_s=r_s, r_cut=r_cut, grid=synth.GRID_R2, dk=dk)
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        t = ngr.short_range_tables(ctx, phibar=phib, f_full=full, r_s=r_s, r_cut=r_cut, grid=synth.GRID_R2, dk=dk)
+        times.append(time.perf_counter() - t0)
+    ctx.close()
+    newton = [(a, b) for a in range(D) for b in range(D) if laws[a][b][2] == 0.0]
+    ref = synth.newtonian_treepm_factor(radii, r_s)
+    err = max((float(np.max(np.abs(t[a, b] - ref))) for a, b in newton), default=None)
+    return {"workload": f"{D}x{D} random Newton/Yukawa laws, {ntab} samples on the r^2 grid, r_s and r_cut of "
+                        f"the 2^24 box", "nk": nk, "ms": float(np.median(times)) * 1e3,
+            "newton_max_abs_err_vs_closed_form": err}
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -381,6 +411,9 @@ def main():
         log(f"served workload: {args.serve_requests} requests")
         out["served"] = served(ngr, synth, nreq=args.serve_requests)
         log("served: " + json.dumps({k: v for k, v in out["served"].items() if k.startswith(("load", "satur"))}))
+    log("exact short-range tables")
+    out["short_tables"] = short_tables(ngr, synth)
+    log(f"short-range tables: {out['short_tables']['ms']:.2f} ms")
     if not args.no_accumulator:
         log("accumulator laws: two-species workload")
         out["accumulator"] = accumulator(ngr, synth)

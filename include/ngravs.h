@@ -196,6 +196,55 @@ ngr_status ngr_tree_force(ngr_context* ctx, const ngr_tree* tree,
                           const ngr_force_params* fp, double* acc,
                           ngr_force_stats* st);
 
+/* ---- exact short-range tables (section 2.4.1, Eqs. (8)-(11)) ----
+ *
+ * A law given by phibar(k) = k^2 phi(k), phi(k) the 3-D transform
+ * int phi(x) exp(-i k.x) d^3x of its pair potential per unit masses (Newton:
+ * -4 pi; Yukawa -(1 + alpha exp(-r/lam))/r: -4 pi (1 + alpha k^2/(k^2 +
+ * lam^-2))), and by its full force factor relative to Newton's 1/r^2,
+ * f_full(r) = r^2 dphi/dr (Newton: 1). Its short-range factor for the
+ * Gaussian split of scale r_s is
+ *   f_short(r) = f_full(r) + 1/(2 pi^2) int_0^inf phibar(k) exp(-k^2 r_s^2)
+ *                                       [sin(kr)/k - r cos(kr)] dk,
+ * the derivative of phi - F^-1[phi(k) exp(-k^2 r_s^2)] (Eqs. (10), (11) with
+ * the r'-integral in closed form); for Newton it is the factor
+ * erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2). The integral is the
+ * trapezoid rule on k_m = m dk, m = 0 .. nk-1, evaluated on the device.
+ *   D, ntab, grid, r_cut   the tables' shape and radii, as in ngr_force_params
+ *   r_s     split scale, > 0
+ *   nk, dk  the k grid of phibar (nk >= 2, dk > 0); ngr_short_range_grid
+ *           gives one with aliasing and truncation below ~1e-16 for laws
+ *           whose r-space kernel decays as exp(-r/range) beyond the Gaussian
+ */
+typedef struct {
+    uint32_t D;
+    uint32_t ntab;
+    uint32_t grid;
+    uint32_t nk;
+    double r_s;
+    double r_cut;
+    double dk;
+} ngr_short_params;
+
+/* A k grid for ngr_short_range_tables: period 2 pi / dk covering r_cut +
+ * 12.5 r_s + 37 range, k up to where exp(-k^2 r_s^2) < 1e-17.
+ * range >= 0 is the law's longest decay length (0 for Newton).
+ * Errors: NGR_EINVAL for r_s, r_cut not finite and > 0, range < 0, or more
+ * than 2^24 samples. */
+ngr_status ngr_short_range_grid(double r_s, double r_cut, double range, uint32_t* nk, double* dk);
+
+/* Tables of f_short at the ntab table radii of every species pair.
+ *   phibar  host, D x D x nk float64: phibar_ab(m dk), row a = sink species
+ *   f_full  host, D x D x ntab float64: f_full_ab at the table radii
+ *   tables  host, D x D x ntab float64, written (usable as
+ *           ngr_force_params.tables)
+ * Errors: NGR_EINVAL for D outside 1..6, ntab < 2, a bad grid, r_s, r_cut
+ * or dk not finite and > 0, nk < 2 or > 2^24, NULL arrays, non-finite
+ * entries. */
+ngr_status ngr_short_range_tables(ngr_context* ctx, const ngr_short_params* sp,
+                                  const double* phibar, const double* f_full,
+                                  double* tables);
+
 /* Release a tree. NULL is accepted. */
 ngr_status ngr_tree_free(ngr_context* ctx, ngr_tree* tree);
 

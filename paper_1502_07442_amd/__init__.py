@@ -24,7 +24,8 @@ EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_
             "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_free",
             "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
             "ngr_batch_build_force", "ngr_server_create", "ngr_server_submit", "ngr_server_tick",
-            "ngr_server_status", "ngr_server_take", "ngr_server_destroy"]
+            "ngr_server_status", "ngr_server_take", "ngr_server_destroy", "ngr_short_range_grid",
+            "ngr_short_range_tables"]
 
 
 class NgravsError(RuntimeError):
@@ -119,6 +120,8 @@ def lib():
             "ngr_server_status": (i32, [P, u64, P, P]),
             "ngr_server_take": (i32, [P, u64, P, P, P]),
             "ngr_server_destroy": (None, [P]),
+            "ngr_short_range_grid": (i32, [C.c_double, C.c_double, C.c_double, P, P]),
+            "ngr_short_range_tables": (i32, [P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -282,6 +285,35 @@ def groups_export(ctx: Context, tree: Tree, group_size: int = 64) -> dict:
     ctx._check(lib().ngr_groups_export(ctx.handle, tree.handle, group_size, C.byref(n2),
                                        *[_np(out[k]) for k in ("species", "start", "count", "lo", "hi")]),
                "groups export")
+    return out
+
+
+class ShortParams(C.Structure):
+    _fields_ = [("D", C.c_uint32), ("ntab", C.c_uint32), ("grid", C.c_uint32), ("nk", C.c_uint32),
+                ("r_s", C.c_double), ("r_cut", C.c_double), ("dk", C.c_double)]
+
+
+def short_range_grid(r_s: float, r_cut: float, range_: float = 0.0):
+    """ngr_short_range_grid: (nk, dk) for ngr_short_range_tables."""
+    nk, dk = C.c_uint32(), C.c_double()
+    rc = lib().ngr_short_range_grid(C.c_double(r_s), C.c_double(r_cut), C.c_double(range_), C.byref(nk), C.byref(dk))
+    if rc != 0:
+        raise NgravsError(rc, "short_range_grid: bad arguments")
+    return nk.value, dk.value
+
+
+def short_range_tables(ctx: Context, *, phibar, f_full, r_s: float, r_cut: float, grid, dk: float) -> np.ndarray:
+    """ngr_short_range_tables. phibar: host D x D x nk samples of k^2 phi(k)
+    at k = m dk; f_full: host D x D x ntab full force factors at the table
+    radii. Returns the D x D x ntab short-range tables (host)."""
+    phibar = np.ascontiguousarray(phibar, dtype=np.float64)
+    f_full = np.ascontiguousarray(f_full, dtype=np.float64)
+    D, _, nk = phibar.shape
+    ntab = f_full.shape[-1]
+    out = np.empty((D, D, ntab))
+    sp = ShortParams(D, ntab, GRIDS.get(grid, grid), nk, float(r_s), float(r_cut), float(dk))
+    ctx._check(lib().ngr_short_range_tables(ctx.handle, C.byref(sp), _np(phibar), _np(f_full), _np(out)),
+               "short-range tables")
     return out
 
 

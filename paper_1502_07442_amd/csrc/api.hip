@@ -580,6 +580,39 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
     });
 }
 
+NGR_API ngr_status ngr_short_range_grid(double r_s, double r_cut, double range, uint32_t* nk, double* dk)
+{
+    if (!nk || !dk || !ngr::finite_pos(r_s) || !ngr::finite_pos(r_cut) || !(std::isfinite(range) && range >= 0.0))
+        return NGR_EINVAL;
+    const double period = r_cut + 12.5 * r_s + 37.0 * range;
+    if (std::sqrt(17.0 * std::log(10.0)) / r_s / (2.0 * M_PI / period) > (double)(1u << 24)) return NGR_EINVAL;
+    ngr::short_range_grid(r_s, r_cut, range, nk, dk);
+    return NGR_OK;
+}
+
+NGR_API ngr_status ngr_short_range_tables(ngr_context* ctx, const ngr_short_params* sp, const double* phibar,
+                                          const double* f_full, double* tables)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!sp) fail(NGR_EINVAL, "short-range params are NULL");
+        if (sp->D < 1 || sp->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, "D must be in 1..6");
+        if (sp->ntab < 2) fail(NGR_EINVAL, "ntab must be >= 2");
+        if (sp->grid != NGR_GRID_R && sp->grid != NGR_GRID_R2) fail(NGR_EINVAL, "grid must be NGR_GRID_R or NGR_GRID_R2");
+        if (!ngr::finite_pos(sp->r_s)) fail(NGR_EINVAL, "r_s must be finite and > 0");
+        if (!ngr::finite_pos(sp->r_cut)) fail(NGR_EINVAL, "r_cut must be finite and > 0");
+        if (!ngr::finite_pos(sp->dk)) fail(NGR_EINVAL, "dk must be finite and > 0");
+        if (sp->nk < 2 || sp->nk > (1u << 24)) fail(NGR_EINVAL, "nk must be in 2..2^24");
+        if (!phibar || !f_full || !tables) fail(NGR_EINVAL, "phibar, f_full and tables must not be NULL");
+        const uint64_t pairs = (uint64_t)sp->D * sp->D;
+        for (uint64_t k = 0; k < pairs * sp->nk; ++k)
+            if (!std::isfinite(phibar[k])) fail(NGR_EINVAL, "phibar has a non-finite entry");
+        for (uint64_t k = 0; k < pairs * sp->ntab; ++k)
+            if (!std::isfinite(f_full[k])) fail(NGR_EINVAL, "f_full has a non-finite entry");
+        ngr::short_range_tables(*ctx, *sp, phibar, f_full, tables);
+    });
+}
+
 NGR_API ngr_status ngr_server_create(ngr_context* ctx, const ngr_server_params* sp, ngr_server** out)
 {
     if (out) *out = nullptr;

@@ -214,6 +214,10 @@ struct WalkOut {
     double ms_walk = 0.0, ms_order = 0.0;
 };
 // laws and acc: one per box of the tree; acc[k] is box k's 3 x n_k output.
+// Exact short-range tables (short.hip).
+void short_range_grid(double r_s, double r_cut, double range, uint32_t* nk, double* dk);
+void short_range_tables(Context& ctx, const ngr_short_params& sp, const double* phibar, const double* f_full,
+                        double* tables);
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
                 const std::vector<LawTables>& tables, const std::vector<double*>& acc, uint64_t* group_counts_dev,
                 WalkOut& out);

@@ -30,7 +30,7 @@ __all__ = [
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
-    "accumulator_problem",
+    "accumulator_problem", "yukawa_law", "exact_split_laws",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -336,3 +336,31 @@ def accumulator_problem(n: int, seed: int, *, D: int = 2, cored=(1,), core_frac:
                    mass=np.full(n, m), G=np.ones((D, D)), tables=tables, grid=grid, r_s=r_s, r_cut=r_cut,
                    eps=eps, theta=theta, leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed,
                    accumulator={"cored": [int(b) for b in cored], "beta": float(beta)})
+
+
+def yukawa_law(alpha: float, lam: float):
+    """The pair law -(1 + alpha exp(-r/lam)) / r per unit masses (alpha = 0:
+    Newton) as the inputs of the exact short-range tables: (phibar(k) =
+    k^2 phi(k), f_full(r) = r^2 dphi/dr, decay length). Vectorised."""
+    if alpha == 0.0:
+        return (lambda k: np.full(np.shape(k), -4.0 * math.pi) if np.ndim(k) else -4.0 * math.pi,
+                lambda r: np.ones(np.shape(r)) if np.ndim(r) else 1.0, 0.0)
+    mu2 = 1.0 / (lam * lam)
+    return (lambda k: -4.0 * math.pi * (1.0 + alpha * k * k / (k * k + mu2)),
+            lambda r: 1.0 + alpha * (1.0 + r / lam) * np.exp(-r / lam), lam)
+
+
+def exact_split_laws(D: int, seed: int, lam_range=(0.003, 0.03), box: float = 1.0):
+    """D x D laws (symmetric): Newton with probability 1/2, else Yukawa with
+    lam log-uniform in lam_range and alpha uniform in [-0.5, 1]."""
+    rng = np.random.default_rng(seed)
+    laws = [[None] * D for _ in range(D)]
+    for a in range(D):
+        for b in range(a, D):
+            if rng.random() < 0.5:
+                law = yukawa_law(0.0, 1.0)
+            else:
+                lam = math.exp(rng.uniform(math.log(lam_range[0]), math.log(lam_range[1]))) * box
+                law = yukawa_law(float(rng.uniform(-0.5, 1.0)), lam)
+            laws[a][b] = laws[b][a] = law
+    return laws

@@ -49,3 +49,21 @@ def test_context_create_rejects_bad_device_without_gpu():
     assert ngr.lib().ngr_context_create(-1, None, ctypes.byref(out)) == ngr.EINVAL
     assert ngr.lib().ngr_tree_build(None, None, None, None) == ngr.EINVAL
     assert ngr.lib().ngr_tree_free(None, None) == ngr.OK
+
+
+def test_short_range_grid_host_rule():
+    """ngr_short_range_grid is host arithmetic: its period covers r_cut +
+    12.5 r_s + 37 range and its last k is past the Gaussian's 1e-17 point;
+    bad arguments are rejected."""
+    import math
+    import paper_1502_07442_amd as ngr
+    if not os.path.exists(ngr.LIB_PATH):
+        pytest.skip("library not built")
+    for r_s, r_cut, rng in ((0.01, 0.045, 0.0), (0.0012, 0.0055, 0.03), (1.0, 4.5, 2.0)):
+        nk, dk = ngr.short_range_grid(r_s, r_cut, rng)
+        assert 2 * math.pi / dk >= r_cut + 12.5 * r_s + 37 * rng - 1e-12 * r_cut
+        assert math.exp(-((nk - 1) * dk * r_s) ** 2) < 1e-17
+        assert math.exp(-((nk - 2) * dk * r_s) ** 2) >= 1e-17 or nk == 2
+    for bad in ((0.0, 0.045, 0.0), (0.01, -1.0, 0.0), (0.01, 0.045, -1.0), (1e-9, 0.045, 1e3)):
+        with pytest.raises(ngr.NgravsError):
+            ngr.short_range_grid(*bad)
