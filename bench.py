@@ -294,6 +294,49 @@ def short_tables(ngr, synth, D=6, ntab=2048, reps=5):
             "newton_max_abs_err_vs_closed_form": err}
 
 
+def pm_leg(ngr, synth, p, tensors, reps=3):
+    """The PM long-range force of the benchmark box (sections 2, 2.4.1): a
+    mesh of N = 1.25 box / r_s points per side (the workload's r_s is 1.25
+    mesh cells, the usual TreePM choice), D = 6 species, the benchmark's G
+    and Newtonian laws. A plan is made once; each force call runs the
+    deposit, the forward FFTs, the k-space step, the inverse FFTs and the
+    interpolation. The FFT roofline counts one read and one write of every
+    mesh per 1-D pass (three passes per 3-D transform)."""
+    import math
+    import numpy as np
+    import torch
+    N = int(round(1.25 * p.box / p.r_s))
+    q = np.arange(3 * (N // 2) ** 2 + 1)
+    phib = np.broadcast_to(np.full(len(q), -4.0 * math.pi), (p.D, p.D, len(q))).copy()
+    ctx = ngr.Context(0)
+    t0 = time.perf_counter()
+    plan = ngr.PM(ctx, N=N, D=p.D, box=p.box, r_s=p.r_s, G=p.G, phibar=phib)
+    t_plan = time.perf_counter() - t0
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **tensors)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    plan.force(tree, acc)
+    walls, stats = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(plan.force(tree, acc))
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    ngr.tree_free(ctx, tree)
+    plan.close()
+    ctx.close()
+    st = {k: float(np.median([s[k] for s in stats])) for k in stats[0]}
+    ngrid = (p.D + 1) // 2
+    fft_bytes = 3 * 2 * 16.0 * N ** 3 * ngrid            # one 3-D transform of every mesh
+    fft_ms = st["ms_fft_forward"]
+    achieved = fft_bytes / (fft_ms * 1e-3) / 1e9
+    return {"workload": f"PM of the benchmark box: {p.n} particles, {p.D} species, mesh {N}^3, "
+                        f"{ngrid} complex float64 meshes", "N": N, "ms_per_force": float(np.median(walls)) * 1e3,
+            "plan_ms": t_plan * 1e3, **st,
+            "fft_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                             "frac": achieved / 8000.0, "traffic": None}}
+
+
 def cpu_baseline(p, gpu_counts, seconds):
     """The FP64 oracle on a bounded, seeded sample of groups of the same
     workload: interactions per second of its walk on the host cores."""
@@ -334,6 +377,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-accumulator", action="store_true")
+    ap.add_argument("--no-pm", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
@@ -411,6 +455,10 @@ def main():
         log(f"served workload: {args.serve_requests} requests")
         out["served"] = served(ngr, synth, nreq=args.serve_requests)
         log("served: " + json.dumps({k: v for k, v in out["served"].items() if k.startswith(("load", "satur"))}))
+    if not args.no_pm:
+        log("PM long-range force of the benchmark box")
+        out["pm"] = pm_leg(ngr, synth, p, dict(pos=pos, species=species, mass=mass))
+        log(f"pm: {out['pm']['ms_per_force']:.1f} ms per force, mesh {out['pm']['N']}^3")
     log("exact short-range tables")
     out["short_tables"] = short_tables(ngr, synth)
     log(f"short-range tables: {out['short_tables']['ms']:.2f} ms")

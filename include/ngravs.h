@@ -245,6 +245,66 @@ ngr_status ngr_short_range_tables(ngr_context* ctx, const ngr_short_params* sp,
                                   const double* phibar, const double* f_full,
                                   double* tables);
 
+/* ---- particle-mesh long-range force (sections 2, 2.4 and 2.4.1) ----
+ *
+ * The PM half of TreePM for D species: cloud-in-cell assignment of each
+ * species to a periodic mesh of N^3 points, FFT, the Gaussian-filtered
+ * Green's function of every species pair (the window divided out twice),
+ * summed over source species, inverse FFT, the 4-point centred difference
+ * and cloud-in-cell interpolation to the particles. On a tree of the same
+ * box and laws, ngr_tree_force (short range, with the tables of
+ * ngr_short_range_tables for the same r_s) plus ngr_pm_force (long range)
+ * is the TreePM force.
+ *   N     mesh points per side, a power of two in 16..1024
+ *   D     species, 1..6
+ *   box   periodic box side, > 0
+ *   r_s   split scale, > 0 (the filter exp(-k^2 r_s^2))
+ * The plan holds ceil(D/2) complex float64 meshes (16 N^3 bytes each) and
+ * the Green's function table until ngr_pm_destroy.
+ */
+typedef struct {
+    uint32_t N;
+    uint32_t D;
+    double box;
+    double r_s;
+} ngr_pm_params;
+
+typedef struct ngr_pm ngr_pm;
+
+/* Device time of the last ngr_pm_force, per step (ms). */
+typedef struct {
+    double ms_deposit;
+    double ms_fft_forward;
+    double ms_green;
+    double ms_fft_inverse;
+    double ms_interp;
+} ngr_pm_stats;
+
+/* Create a PM plan.
+ *   G       host, D x D float64, row = sink species a (as ngr_force_params)
+ *   phibar  host, D x D x (3 (N/2)^2 + 1) float64: phibar_ab = k^2 phi_ab(k)
+ *           (as ngr_short_range_tables) at the mesh's |k| = 2 pi sqrt(q) / box,
+ *           q = 0 .. 3 (N/2)^2 (entry q = 0 is not used: the mean is dropped).
+ *           A per-pair constant in phibar scales that pair's long range only,
+ *           e.g. the exp(-y^2 r_s^2) correction of a Yukawa law of section
+ *           3.2 (give the short-range tables the same phibar).
+ * Errors: NGR_EINVAL for N not a power of two in 16..1024, D outside 1..6,
+ * box or r_s not finite and > 0, NULL or non-finite G or phibar;
+ * NGR_ENOMEM when the meshes do not fit. */
+ngr_status ngr_pm_create(ngr_context* ctx, const ngr_pm_params* pp, const double* G,
+                         const double* phibar, ngr_pm** out);
+
+/* Long-range accelerations of the particles of a one-box tree with the
+ * plan's D and box: written to (accumulate == 0) or added to (nonzero) acc,
+ * device, 3 x n float64 in input order. st may be NULL.
+ * Errors: NGR_EINVAL for NULL pm or tree, a batch tree, a tree whose D or
+ * box differs from the plan's, NULL acc with n > 0. */
+ngr_status ngr_pm_force(ngr_context* ctx, ngr_pm* pm, const ngr_tree* tree, double* acc,
+                        int accumulate, ngr_pm_stats* st);
+
+/* Release a plan. NULL is accepted. */
+ngr_status ngr_pm_destroy(ngr_context* ctx, ngr_pm* pm);
+
 /* Release a tree. NULL is accepted. */
 ngr_status ngr_tree_free(ngr_context* ctx, ngr_tree* tree);
 

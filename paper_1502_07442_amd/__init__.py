@@ -25,7 +25,7 @@ EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_
             "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
             "ngr_batch_build_force", "ngr_server_create", "ngr_server_submit", "ngr_server_tick",
             "ngr_server_status", "ngr_server_take", "ngr_server_destroy", "ngr_short_range_grid",
-            "ngr_short_range_tables"]
+            "ngr_short_range_tables", "ngr_pm_create", "ngr_pm_force", "ngr_pm_destroy"]
 
 
 class NgravsError(RuntimeError):
@@ -122,6 +122,9 @@ def lib():
             "ngr_server_destroy": (None, [P]),
             "ngr_short_range_grid": (i32, [C.c_double, C.c_double, C.c_double, P, P]),
             "ngr_short_range_tables": (i32, [P, P, P, P, P]),
+            "ngr_pm_create": (i32, [P, P, P, P, P]),
+            "ngr_pm_force": (i32, [P, P, P, P, C.c_int, P]),
+            "ngr_pm_destroy": (i32, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -315,6 +318,48 @@ def short_range_tables(ctx: Context, *, phibar, f_full, r_s: float, r_cut: float
     ctx._check(lib().ngr_short_range_tables(ctx.handle, C.byref(sp), _np(phibar), _np(f_full), _np(out)),
                "short-range tables")
     return out
+
+
+class PmParams(C.Structure):
+    _fields_ = [("N", C.c_uint32), ("D", C.c_uint32), ("box", C.c_double), ("r_s", C.c_double)]
+
+
+class PmStats(C.Structure):
+    _fields_ = [("ms_deposit", C.c_double), ("ms_fft_forward", C.c_double), ("ms_green", C.c_double),
+                ("ms_fft_inverse", C.c_double), ("ms_interp", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def pm_q_count(N: int) -> int:
+    """Entries of a PM plan's phibar table per species pair: q = 0 .. 3 (N/2)^2."""
+    return 3 * (N // 2) ** 2 + 1
+
+
+class PM:
+    """A PM plan (ngr_pm_create): N, D, box, r_s; host G (D x D) and phibar
+    (D x D x pm_q_count(N), k^2 phi_ab(k) at |k| = 2 pi sqrt(q) / box)."""
+
+    def __init__(self, ctx: Context, *, N: int, D: int, box: float, r_s: float, G, phibar):
+        self.ctx = ctx
+        G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
+        phibar = np.ascontiguousarray(phibar, dtype=np.float64).reshape(D, D, pm_q_count(N))
+        self._h = C.c_void_p()
+        ctx._check(lib().ngr_pm_create(ctx.handle, C.byref(PmParams(N, D, float(box), float(r_s))), _np(G),
+                                       _np(phibar), C.byref(self._h)), "pm create")
+
+    def force(self, tree: Tree, acc, accumulate: bool = False) -> dict:
+        """Long-range accelerations into the device tensor acc (3 x n, input order)."""
+        st = PmStats()
+        self.ctx._check(lib().ngr_pm_force(self.ctx.handle, self._h, tree.handle, C.c_void_p(_dev(acc)),
+                                           int(bool(accumulate)), C.byref(st)), "pm force")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            self.ctx._check(lib().ngr_pm_destroy(self.ctx.handle, self._h), "pm destroy")
+            self._h = None
 
 
 class BatchBox:

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libngravs.so")
-SOURCES = ["api.hip", "build.hip", "scan.hip", "sort.hip", "walk.hip", "serve.hip", "short.hip"]
+SOURCES = ["api.hip", "build.hip", "scan.hip", "sort.hip", "walk.hip", "serve.hip", "short.hip", "pm.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
     # no packed FP32 instructions: some of their forms have given wrong results on these machines

@@ -17,6 +17,7 @@ struct ngr_server {
     ngr_context* ctx;
     ngr::Server* impl;
 };
+struct ngr_pm : ngr::PmPlan {};
 
 namespace ngr {
 
@@ -611,6 +612,69 @@ NGR_API ngr_status ngr_short_range_tables(ngr_context* ctx, const ngr_short_para
             if (!std::isfinite(f_full[k])) fail(NGR_EINVAL, "f_full has a non-finite entry");
         ngr::short_range_tables(*ctx, *sp, phibar, f_full, tables);
     });
+}
+
+NGR_API ngr_status ngr_pm_create(ngr_context* ctx, const ngr_pm_params* pp, const double* G, const double* phibar,
+                                 ngr_pm** out)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!out) fail(NGR_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!pp) fail(NGR_EINVAL, "PM params are NULL");
+        if (pp->N < 16 || pp->N > 1024 || (pp->N & (pp->N - 1))) fail(NGR_EINVAL, "N must be a power of two in 16..1024");
+        if (pp->D < 1 || pp->D > NGR_MAX_SPECIES) fail(NGR_EINVAL, "D must be in 1..6");
+        if (!ngr::finite_pos(pp->box)) fail(NGR_EINVAL, "box must be finite and > 0");
+        if (!ngr::finite_pos(pp->r_s)) fail(NGR_EINVAL, "r_s must be finite and > 0");
+        if (!G || !phibar) fail(NGR_EINVAL, "G and phibar must not be NULL");
+        const uint64_t pairs = (uint64_t)pp->D * pp->D, nq = 3ull * (pp->N / 2) * (pp->N / 2) + 1;
+        for (uint64_t k = 0; k < pairs; ++k)
+            if (!std::isfinite(G[k])) fail(NGR_EINVAL, "G has a non-finite entry");
+        for (uint64_t k = 0; k < pairs * nq; ++k)
+            if (!std::isfinite(phibar[k])) fail(NGR_EINVAL, "phibar has a non-finite entry");
+        ngr_pm* pm = new ngr_pm();
+        try {
+            ngr::pm_create(*ctx, *pp, G, phibar, *pm);
+        } catch (...) {
+            try {
+                ngr::pm_destroy(*ctx, *pm);
+            } catch (...) {
+            }
+            delete pm;
+            throw;
+        }
+        *out = pm;
+    });
+}
+
+NGR_API ngr_status ngr_pm_force(ngr_context* ctx, ngr_pm* pm, const ngr_tree* tree, double* acc, int accumulate,
+                                ngr_pm_stats* st)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        if (!pm || !tree) fail(NGR_EINVAL, "pm and tree must not be NULL");
+        if (tree->nbox != 1) fail(NGR_EINVAL, "the tree must hold one box");
+        if (tree->D != pm->D) fail(NGR_EINVAL, "the tree's D differs from the plan's");
+        if (tree->box != pm->box) fail(NGR_EINVAL, "the tree's box differs from the plan's");
+        if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
+        ngr::PmTimes tm;
+        ngr::pm_force(*ctx, *pm, *tree, acc, accumulate, &tm);
+        if (st) {
+            st->ms_deposit = tm.deposit;
+            st->ms_fft_forward = tm.fft_forward;
+            st->ms_green = tm.green;
+            st->ms_fft_inverse = tm.fft_inverse;
+            st->ms_interp = tm.interp;
+        }
+    });
+}
+
+NGR_API ngr_status ngr_pm_destroy(ngr_context* ctx, ngr_pm* pm)
+{
+    if (!pm) return NGR_OK;
+    ngr_status s = guarded(ctx, [&] { ngr::pm_destroy(*ctx, *pm); });
+    delete pm;
+    return s;
 }
 
 NGR_API ngr_status ngr_server_create(ngr_context* ctx, const ngr_server_params* sp, ngr_server** out)

@@ -214,6 +214,25 @@ struct WalkOut {
     double ms_walk = 0.0, ms_order = 0.0;
 };
 // laws and acc: one per box of the tree; acc[k] is box k's 3 x n_k output.
+// Particle-mesh long-range force (pm.hip).
+struct PmPlan {
+    uint32_t N = 0, D = 0, p = 0, nq = 0;
+    double box = 0.0, r_s = 0.0;
+    uint32_t U = 0;            // unique law tables
+    double* gq = nullptr;      // nq x U: phibar_t exp(-k^2 r_s^2) / (k^2 N^3)
+    double mix_coef[NGR_MAX_SPECIES * NGR_MAX_SPECIES] = {};    // G_ab times the pair's factor
+    uint32_t mix_table[NGR_MAX_SPECIES * NGR_MAX_SPECIES] = {}; // the pair's unique table
+    double* s2 = nullptr;      // N: sinc^2(pi n / N) of each grid index
+    double2* tw = nullptr;     // N / 2 twiddles exp(-2 pi i m / N)
+    double2* mesh = nullptr;   // ceil(D/2) complex meshes of N^3 points
+    ~PmPlan();
+};
+struct PmTimes {
+    float deposit = 0, fft_forward = 0, green = 0, fft_inverse = 0, interp = 0;
+};
+void pm_create(Context& ctx, const ngr_pm_params& pp, const double* G, const double* phibar, PmPlan& pl);
+void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumulate, PmTimes* times);
+void pm_destroy(Context& ctx, PmPlan& pl);
 // Exact short-range tables (short.hip).
 void short_range_grid(double r_s, double r_cut, double range, uint32_t* nk, double* dk);
 void short_range_tables(Context& ctx, const ngr_short_params& sp, const double* phibar, const double* f_full,

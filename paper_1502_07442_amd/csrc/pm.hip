@@ -1,0 +1,484 @@
+// Particle-mesh long-range force of D species (the PM half of TreePM).
+//
+// Paper: Croker, ngravs (CPC). Section 2: PM forces assign particle masses
+// to a density on a regular grid, Fourier transform it, multiply by the
+// k-space Green's function, transform back and interpolate the resulting
+// potential's forces to the particles; in TreePM mode the Green's function
+// carries the Gaussian filter exp(-k^2 r_s^2) (section 2.4.1). Section 2.4:
+// every species is both a passive and an active mass, so the mesh sees D^2
+// species pairs. The assignment, window correction and difference stencil
+// are those of the code the paper extends (GADGET-2): cloud in cell, the
+// window divided out twice, a 4-point centred difference.
+//
+// Design (one GPU, HBM-resident meshes):
+// - The particles come from a built tree: sorted by species, then along the
+//   Morton curve, so each species is one contiguous run and consecutive
+//   threads deposit into neighbouring cells.
+// - Two real species densities share one complex mesh (real and imaginary
+//   parts); ceil(D/2) forward 3-D FFTs replace D. After the transform the two
+//   spectra are separated with Z(k) and conj Z(-k).
+// - The k-space step handles k and -k in one thread, so it can overwrite the
+//   density spectra with the potential spectra in place. Linearity lets it
+//   sum the D source species for each sink species before the inverse
+//   transform: ceil(D/2) inverse FFTs instead of the D^2 mesh passes the
+//   paper's MPI slab decomposition needs. The sink species' real potentials
+//   are paired into complex meshes the same way.
+// - 3-D FFTs are three passes of batched 1-D radix-2 transforms along one
+//   axis each, a tile of lines held in LDS per workgroup (lines adjacent in
+//   memory, so that the strided axes read contiguous runs), three stages at
+//   a time in registers between LDS exchanges, the twiddles staged in LDS
+//   from a float64 table computed on the host.
+// - The Green's function is a table over q = |k|^2 (2 pi / L)^-2 per
+//   distinct law: pairs whose phibar tables agree up to a constant factor
+//   share one table and keep the factor (times G_ab) as a coefficient; the
+//   tables of one q are adjacent, so a mesh point reads one or two cache lines.
+// - Interpolation differentiates the potential on the fly at the eight
+//   cloud-in-cell corners of each particle and writes the acceleration in
+//   input order.
+#include <cmath>
+#include <vector>
+
+#include "ngr_internal.hpp"
+
+namespace ngr {
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr size_t kFftTileBytes = 64 * 1024;   // LDS of one workgroup's lines
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// Lower grid index and fraction along one axis of a lattice coordinate:
+// u = X N 2^-64 exactly (N = 2^p).
+__device__ inline void cic_axis(uint64_t X, uint32_t p, uint32_t& i, double& f)
+{
+    i = (uint32_t)(X >> (64 - p));
+    f = (double)(X & ((1ull << (64 - p)) - 1ull)) * exp2(-(double)(64 - p));
+}
+
+// Densities of species blockIdx.y (sorted run [seg[b], seg[b+1])) into the
+// real (even b) or imaginary (odd b) part of complex mesh b / 2.
+__global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const double* __restrict__ mass,
+                           const uint64_t* __restrict__ seg, uint32_t N, uint32_t p, double inv_h3,
+                           double* __restrict__ mesh)
+{
+    const uint32_t b = blockIdx.y;
+    const uint64_t s0 = seg[b], s1 = seg[b + 1];
+    const uint64_t N3 = (uint64_t)N * N * N;
+    double* m = mesh + 2 * N3 * (b / 2) + (b & 1);
+    const uint32_t mask = N - 1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = s0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s1; i += stride) {
+        uint32_t ix, iy, iz;
+        double fx, fy, fz;
+        cic_axis(X[i], p, ix, fx);
+        cic_axis(X[n + i], p, iy, fy);
+        cic_axis(X[2 * n + i], p, iz, fz);
+        const double w = mass[i] * inv_h3;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t cx = (ix + (c >> 2)) & mask, cy = (iy + ((c >> 1) & 1)) & mask, cz = (iz + (c & 1)) & mask;
+            const double wt = w * ((c >> 2) ? fx : 1.0 - fx) * (((c >> 1) & 1) ? fy : 1.0 - fy) * ((c & 1) ? fz : 1.0 - fz);
+            unsafeAtomicAdd(m + 2 * (((uint64_t)cx * N + cy) * N + cz), wt);
+        }
+    }
+}
+
+// Batched 1-D FFTs of length N = 2^p along one axis of ngrid complex meshes
+// of N^3 points (index (x N + y) N + z). A workgroup transforms T lines:
+// line l of the batch starts at line_base(l) and its elements are `stride`
+// apart. Radix-2 decimation in frequency in place in LDS, natural order in,
+// bit-reversed order read out. sign = -1 forward, +1 inverse (unnormalised).
+// The LDS holds T lines of N points and the N / 2 twiddles.
+// axis 0: lines along z (stride 1), the T lines of a tile N apart;
+// axis 1: along y (stride N), a tile's lines adjacent in z;
+// axis 2: along x (stride N^2), a tile's lines adjacent in z.
+
+__device__ inline uint32_t lds_swizzle(uint32_t i)
+{
+    // XOR the low three bits of a point's LDS slot with its higher bits:
+    // the strided patterns below (lines adjacent in z, sets of stride d,
+    // bit-reversed read-out) then spread over the banks
+    return i ^ (((i >> 3) ^ (i >> 6) ^ (i >> 9)) & 7u);
+}
+
+// F consecutive radix-2 decimation-in-frequency stages s .. s+F-1 of the T
+// lines in LDS. Those stages (halves h, h/2, ...) only mix the 2^F points
+// first + m d of a block of 2h, d = h >> (F-1), so each thread loads such a
+// set into registers, applies the F stages and stores it back.
+template <int F>
+__device__ inline void fft_stages(double2* __restrict__ sm, const double2* __restrict__ tw, uint32_t N, uint32_t p,
+                                  uint32_t T, uint32_t s)
+{
+    constexpr uint32_t M = 1u << F;
+    const uint32_t logh = p - s - 1, logd = logh - (F - 1);
+    const uint32_t h = 1u << logh, d = 1u << logd;
+    const uint32_t logsets = p - F;       // sets per line: N / M
+    for (uint32_t j = threadIdx.x; j < (T << logsets); j += blockDim.x) {
+        const uint32_t l = j >> logsets, js = j & ((1u << logsets) - 1u);
+        // js -> the block of 2h it lies in and the position below d inside it
+        const uint32_t blk = js >> logd, off = js & (d - 1u);
+        const uint32_t first = blk * 2 * h + off;   // within the line
+        double2 v[M];
+#pragma unroll
+        for (uint32_t m = 0; m < M; ++m) v[m] = sm[lds_swizzle(l * N + first + m * d)];
+#pragma unroll
+        for (uint32_t st = 0; st < (uint32_t)F; ++st) {
+            const uint32_t span = M >> (st + 1);          // partner distance in m
+            const uint32_t hh = h >> st;                   // the stage's half
+            const uint32_t twshift = s + st;               // twiddle index = pos * 2^(s+st)
+#pragma unroll
+            for (uint32_t m = 0; m < M; ++m) {
+                if (m & span) continue;
+                const uint32_t pos = (first + m * d) & (hh - 1u);
+                const double2 a = v[m], b = v[m + span];
+                v[m] = cadd(a, b);
+                v[m + span] = cmul(csub(a, b), tw[pos << twshift]);
+            }
+        }
+#pragma unroll
+        for (uint32_t m = 0; m < M; ++m) sm[lds_swizzle(l * N + first + m * d)] = v[m];
+    }
+}
+
+__global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ data, uint32_t N, uint32_t p, uint32_t T,
+                                                         uint32_t logT, int axis, const double2* __restrict__ twiddle,
+                                                         double sign)
+{
+    HIP_DYNAMIC_SHARED(double2, sm);
+    double2* tw = sm + (size_t)T * N;     // N / 2 twiddles, conjugated for the inverse
+    const uint64_t N2 = (uint64_t)N * N, N3 = N2 * N;
+    const uint64_t tiles_per_mesh = N2 >> logT;
+    const uint64_t tile = blockIdx.x % tiles_per_mesh, g = blockIdx.x / tiles_per_mesh;
+    double2* base = data + g * N3;
+    // first element of line 0 of the tile and the distance between the tile's lines
+    uint64_t l0, lstep, stride;
+    if (axis == 0) {
+        l0 = (tile << logT) * N;          // lines (x, y) = tile * T .. + T - 1, each of N elements
+        lstep = N;
+        stride = 1;
+    } else {
+        const uint64_t line0 = tile << logT;   // T consecutive lines in the (other, z) plane, z fastest
+        const uint64_t other = line0 >> p, z = line0 & (N - 1);
+        l0 = axis == 1 ? other * N2 + z : other * N + z;
+        lstep = 1;
+        stride = axis == 1 ? N : N2;
+    }
+    for (uint32_t k = threadIdx.x; k < N / 2; k += blockDim.x) {
+        const double2 w = twiddle[k];
+        tw[k] = make_double2(w.x, sign * w.y);
+    }
+    const uint32_t TN = T * N;
+    for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
+        // consecutive threads take the same element of adjacent lines when
+        // the lines are adjacent in memory, else consecutive elements
+        const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
+        sm[lds_swizzle(l * N + k)] = base[l0 + l * lstep + k * stride];
+    }
+    __syncthreads();
+    // Radix-2 decimation in frequency, up to three stages per pass held in
+    // registers (fft_stages); a barrier between passes.
+    for (uint32_t s = 0; s < p;) {
+        const uint32_t f = min(3u, p - s);
+        if (f == 3) fft_stages<3>(sm, tw, N, p, T, s);
+        else if (f == 2) fft_stages<2>(sm, tw, N, p, T, s);
+        else fft_stages<1>(sm, tw, N, p, T, s);
+        __syncthreads();
+        s += f;
+    }
+    for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
+        const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
+        const uint32_t r = __brev(k) >> (32 - p);
+        base[l0 + l * lstep + k * stride] = sm[lds_swizzle(l * N + r)];
+    }
+}
+
+// Per species pair: its coefficient and which unique table it scales.
+struct PairMix {
+    double coef[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
+    uint32_t table[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
+};
+
+// The k-space step, one thread per pair (k, -k) (the thread of the smaller
+// linear index; self-mirrored points alone). Unpacks the density spectra of
+// every species from the packed meshes, forms every sink species' potential
+// spectrum sum_b coef_ab u_t(ab)(q) / W(k)^2 rho_b(k), and packs the
+// potentials two per mesh, in place. gq[q][t] holds the U unique laws
+// phibar_t(q) exp(-k^2 r_s^2) / (k^2 N^3) (0 at q = 0); s2 holds
+// sinc^2(pi n / N) per grid index.
+template <uint32_t D>
+__global__ void pm_green(double2* __restrict__ mesh, uint32_t N, uint32_t U, const double* __restrict__ gq,
+                         const double* __restrict__ s2, PairMix mix)
+{
+    const uint64_t N3 = (uint64_t)N * N * N;
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N3) return;
+    const uint32_t i = (uint32_t)(c / ((uint64_t)N * N)), j = (uint32_t)((c / N) % N), l = (uint32_t)(c % N);
+    const uint32_t mi = (N - i) & (N - 1), mj = (N - j) & (N - 1), ml = (N - l) & (N - 1);
+    const uint64_t cm = ((uint64_t)mi * N + mj) * N + ml;
+    if (cm < c) return;                   // the mirror's thread does this pair
+    const int ni = i < N / 2 ? (int)i : (int)i - (int)N, nj = j < N / 2 ? (int)j : (int)j - (int)N,
+              nl = l < N / 2 ? (int)l : (int)l - (int)N;
+    const uint32_t q = (uint32_t)(ni * ni + nj * nj + nl * nl);
+    const double W = s2[i] * s2[j] * s2[l];
+    const double iw2 = 1.0 / (W * W);
+    const double* gqq = gq + (uint64_t)q * U;
+    constexpr uint32_t ngrid = (D + 1) / 2;
+    double2 rho[2 * ngrid];
+#pragma unroll
+    for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
+        const double2 z = mesh[g2 * N3 + c], zm = mesh[g2 * N3 + cm];
+        // rho_even(k) = (Z(k) + conj Z(-k)) / 2, rho_odd(k) = (Z(k) - conj Z(-k)) / 2i
+        rho[2 * g2] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+        rho[2 * g2 + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+    }
+#pragma unroll
+    for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
+        double2 ph[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t a = 2 * g2 + h;
+            if (a >= D) break;
+#pragma unroll
+            for (uint32_t b = 0; b < D; ++b) {
+                // the pair's table index is uniform: every lane reads its own q's entry
+                const double f = mix.coef[a * D + b] * gqq[mix.table[a * D + b]] * iw2;
+                ph[h].x = fma(f, rho[b].x, ph[h].x);
+                ph[h].y = fma(f, rho[b].y, ph[h].y);
+            }
+        }
+        // P(k) = Phi_even(k) + i Phi_odd(k); P(-k) = conj Phi_even(k) + i conj Phi_odd(k)
+        mesh[g2 * N3 + c] = make_double2(ph[0].x - ph[1].y, ph[0].y + ph[1].x);
+        if (cm != c) mesh[g2 * N3 + cm] = make_double2(ph[0].x + ph[1].y, -ph[0].y + ph[1].x);
+    }
+}
+
+// Accelerations of species blockIdx.y: -grad Phi by the 4-point difference at
+// the eight cloud-in-cell corners, interpolated with the same weights.
+__global__ void pm_interp(uint64_t n, const uint64_t* __restrict__ X, const uint32_t* __restrict__ perm,
+                          const uint64_t* __restrict__ seg, uint32_t N, uint32_t p, double inv_h,
+                          const double* __restrict__ mesh, double* __restrict__ acc, uint64_t in_off,
+                          int accumulate)
+{
+    const uint32_t a = blockIdx.y;
+    const uint64_t s0 = seg[a], s1 = seg[a + 1];
+    const uint64_t N3 = (uint64_t)N * N * N;
+    const double* m = mesh + 2 * N3 * (a / 2) + (a & 1);
+    const uint32_t mask = N - 1;
+    auto P = [&](uint32_t x, uint32_t y, uint32_t z) {
+        return m[2 * (((uint64_t)(x & mask) * N + (y & mask)) * N + (z & mask))];
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = s0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s1; i += stride) {
+        uint32_t ix, iy, iz;
+        double fx, fy, fz;
+        cic_axis(X[i], p, ix, fx);
+        cic_axis(X[n + i], p, iy, fy);
+        cic_axis(X[2 * n + i], p, iz, fz);
+        double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t cx = ix + (c >> 2), cy = iy + ((c >> 1) & 1), cz = iz + (c & 1);
+            const double wt = ((c >> 2) ? fx : 1.0 - fx) * (((c >> 1) & 1) ? fy : 1.0 - fy) * ((c & 1) ? fz : 1.0 - fz);
+            const double gx = 2.0 / 3.0 * (P(cx + 1, cy, cz) - P(cx - 1, cy, cz)) -
+                              1.0 / 12.0 * (P(cx + 2, cy, cz) - P(cx - 2, cy, cz));
+            const double gy = 2.0 / 3.0 * (P(cx, cy + 1, cz) - P(cx, cy - 1, cz)) -
+                              1.0 / 12.0 * (P(cx, cy + 2, cz) - P(cx, cy - 2, cz));
+            const double gz = 2.0 / 3.0 * (P(cx, cy, cz + 1) - P(cx, cy, cz - 1)) -
+                              1.0 / 12.0 * (P(cx, cy, cz + 2) - P(cx, cy, cz - 2));
+            ax = fma(wt, gx, ax);
+            ay = fma(wt, gy, ay);
+            az = fma(wt, gz, az);
+        }
+        const uint64_t o = perm[i] - in_off;
+        const double vx = -ax * inv_h, vy = -ay * inv_h, vz = -az * inv_h;
+        if (accumulate) {
+            acc[o] += vx;
+            acc[n + o] += vy;
+            acc[2 * n + o] += vz;
+        } else {
+            acc[o] = vx;
+            acc[n + o] = vy;
+            acc[2 * n + o] = vz;
+        }
+    }
+}
+
+// gq[q][t] = u_t[q] exp(-k_q^2 r_s^2) / (k_q^2 N^3), k_q^2 = q (2 pi / L)^2; 0 at q = 0.
+// The U unique tables of one q are adjacent.
+__global__ void pm_green_table(uint32_t U, uint32_t nq, const double* __restrict__ tables, double kunit2,
+                               double r_s2, double invN3, double* __restrict__ gq)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint64_t)U * nq) return;
+    const uint32_t t = (uint32_t)(e / nq), q = (uint32_t)(e % nq);
+    const double k2 = q * kunit2;
+    gq[(uint64_t)q * U + t] = q == 0 ? 0.0 : tables[e] * exp(-k2 * r_s2) / k2 * invN3;
+}
+
+}  // namespace
+
+PmPlan::~PmPlan() = default;
+
+void pm_create(Context& ctx, const ngr_pm_params& pp, const double* G, const double* phibar, PmPlan& pl)
+{
+    const uint32_t N = pp.N, D = pp.D;
+    pl.N = N;
+    pl.D = D;
+    pl.p = 0;
+    while ((1u << pl.p) < N) ++pl.p;
+    pl.box = pp.box;
+    pl.r_s = pp.r_s;
+    pl.nq = 3u * (N / 2) * (N / 2) + 1u;
+    // Laws that are the same table up to a constant factor share one table:
+    // pair ab uses coef_ab u_t(ab)(q) with coef_ab = G_ab c_ab (on the
+    // benchmark's Newtonian laws every pair shares one table).
+    const uint32_t pairs = D * D, nq = pl.nq;
+    std::vector<uint32_t> rep;            // first pair of each unique table
+    for (uint32_t ab = 0; ab < pairs; ++ab) {
+        const double* x = phibar + (size_t)ab * nq;
+        uint32_t kmax = 1;
+        for (uint32_t q = 1; q < nq; ++q)
+            if (std::fabs(x[q]) > std::fabs(x[kmax])) kmax = q;
+        const double xmax = std::fabs(x[kmax]);
+        bool found = false;
+        for (uint32_t t = 0; t < rep.size() && !found; ++t) {
+            const double* u = phibar + (size_t)rep[t] * nq;
+            if (u[kmax] == 0.0 || xmax == 0.0) continue;
+            const double c = x[kmax] / u[kmax];
+            bool same = true;
+            for (uint32_t q = 1; q < nq && same; ++q) same = std::fabs(x[q] - c * u[q]) <= 1e-15 * xmax;
+            if (same) {
+                pl.mix_table[ab] = t;
+                pl.mix_coef[ab] = G[ab] * c;
+                found = true;
+            }
+        }
+        if (!found) {
+            pl.mix_table[ab] = (uint32_t)rep.size();
+            pl.mix_coef[ab] = G[ab];
+            rep.push_back(ab);
+        }
+    }
+    pl.U = (uint32_t)rep.size();
+    const size_t gq_bytes = (size_t)pl.U * nq * sizeof(double);
+    pl.gq = static_cast<double*>(ctx.alloc(gq_bytes));
+    pl.s2 = static_cast<double*>(ctx.alloc(N * sizeof(double)));
+    pl.tw = static_cast<double2*>(ctx.alloc((N / 2) * sizeof(double2)));
+    pl.mesh = static_cast<double2*>(ctx.alloc((size_t)((D + 1) / 2) * N * N * N * sizeof(double2)));
+    // host tables: sinc^2 per grid index (signed frequency), twiddles exp(-2 pi i m / N)
+    std::vector<double> s2(N);
+    for (uint32_t i = 0; i < N; ++i) {
+        const int ni = i < N / 2 ? (int)i : (int)i - (int)N;
+        const double x = M_PI * ni / N;
+        const double sn = ni == 0 ? 1.0 : std::sin(x) / x;
+        s2[i] = sn * sn;
+    }
+    std::vector<double2> tw(N / 2);
+    for (uint32_t m = 0; m < N / 2; ++m) {
+        const double t = -2.0 * M_PI * m / N;
+        tw[m] = make_double2(std::cos(t), std::sin(t));
+    }
+    ctx.to_device(pl.s2, s2.data(), N * sizeof(double));
+    ctx.to_device(pl.tw, tw.data(), (N / 2) * sizeof(double2));
+    double* stage = static_cast<double*>(ctx.alloc(gq_bytes));
+    for (uint32_t t = 0; t < pl.U; ++t)
+        ctx.to_device(stage + (size_t)t * nq, phibar + (size_t)rep[t] * nq, nq * sizeof(double));
+    const double kunit = 2.0 * M_PI / pp.box;
+    const uint64_t ne = (uint64_t)pl.U * nq;
+    hipLaunchKernelGGL(pm_green_table, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, ctx.stream, pl.U, nq, stage,
+                       kunit * kunit, pp.r_s * pp.r_s, 1.0 / ((double)N * N * N), pl.gq);
+    LAUNCH_CHECK("pm_green_table");
+    ctx.sync();
+    ctx.release(stage);
+}
+
+void pm_destroy(Context& ctx, PmPlan& pl)
+{
+    ctx.release(pl.gq);
+    ctx.release(pl.s2);
+    ctx.release(pl.tw);
+    ctx.release(pl.mesh);
+    pl.gq = pl.s2 = nullptr;
+    pl.tw = pl.mesh = nullptr;
+}
+
+static void fft3(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign)
+{
+    const uint32_t N = pl.N;
+    uint32_t T = 1, logT = 0;
+    while (T < 16 && (size_t)(2 * T) * N * sizeof(double2) <= kFftTileBytes && 2 * T <= N * N) {
+        T *= 2;
+        ++logT;
+    }
+    const size_t lds = (size_t)T * N * sizeof(double2) + (N / 2) * sizeof(double2);
+    const uint64_t blocks = (uint64_t)ngrid * ((uint64_t)N * N / T);
+    if (blocks > 0x7fffffffull) fail(NGR_EINVAL, "mesh too large for the FFT grid");
+    for (int axis = 0; axis < 3; ++axis) {
+        hipLaunchKernelGGL(fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), lds, ctx.stream, pl.mesh, N, pl.p, T,
+                           logT, axis, pl.tw, sign);
+        LAUNCH_CHECK("fft_lines");
+    }
+}
+
+void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumulate, PmTimes* times)
+{
+    const uint32_t N = pl.N, D = pl.D, ngrid = (D + 1) / 2;
+    const uint64_t n = t.n, N3 = (uint64_t)N * N * N;
+    const double h = pl.box / N;
+    hipEvent_t ev[6];
+    for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+    HIP_CHECK(hipEventRecord(ev[0], ctx.stream));
+    uint64_t* seg = static_cast<uint64_t*>(ctx.alloc((NGR_MAX_SPECIES + 1) * sizeof(uint64_t)));
+    ctx.to_device(seg, t.seg, (NGR_MAX_SPECIES + 1) * sizeof(uint64_t));
+    HIP_CHECK(hipMemsetAsync(pl.mesh, 0, (size_t)ngrid * N3 * sizeof(double2), ctx.stream));
+    const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096));
+    if (n) {
+        hipLaunchKernelGGL(pm_deposit, dim3(gx, D), dim3(256), 0, ctx.stream, n, t.X, t.mass, seg, N, pl.p,
+                           1.0 / (h * h * h), reinterpret_cast<double*>(pl.mesh));
+        LAUNCH_CHECK("pm_deposit");
+    }
+    HIP_CHECK(hipEventRecord(ev[1], ctx.stream));
+    fft3(ctx, pl, ngrid, -1.0);
+    HIP_CHECK(hipEventRecord(ev[2], ctx.stream));
+    PairMix mix{};
+    for (uint32_t ab = 0; ab < D * D; ++ab) {
+        mix.coef[ab] = pl.mix_coef[ab];
+        mix.table[ab] = pl.mix_table[ab];
+    }
+    const dim3 gg((unsigned)((N3 + 255) / 256));
+    switch (D) {
+    case 1: hipLaunchKernelGGL(pm_green<1>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    case 2: hipLaunchKernelGGL(pm_green<2>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    case 3: hipLaunchKernelGGL(pm_green<3>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    case 4: hipLaunchKernelGGL(pm_green<4>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    case 5: hipLaunchKernelGGL(pm_green<5>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    default: hipLaunchKernelGGL(pm_green<6>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    }
+    LAUNCH_CHECK("pm_green");
+    HIP_CHECK(hipEventRecord(ev[3], ctx.stream));
+    fft3(ctx, pl, ngrid, 1.0);
+    HIP_CHECK(hipEventRecord(ev[4], ctx.stream));
+    if (n) {
+        hipLaunchKernelGGL(pm_interp, dim3(gx, D), dim3(256), 0, ctx.stream, n, t.X, t.perm, seg, N, pl.p, 1.0 / h,
+                           reinterpret_cast<const double*>(pl.mesh), acc, t.boff[0], accumulate);
+        LAUNCH_CHECK("pm_interp");
+    }
+    HIP_CHECK(hipEventRecord(ev[5], ctx.stream));
+    ctx.sync();
+    ctx.release(seg);
+    if (times) {
+        float ms[5];
+        for (int k = 0; k < 5; ++k) HIP_CHECK(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
+        times->deposit = ms[0];
+        times->fft_forward = ms[1];
+        times->green = ms[2];
+        times->fft_inverse = ms[3];
+        times->interp = ms[4];
+    }
+    for (auto& e : ev) HIP_CHECK(hipEventDestroy(e));
+}
+
+}  // namespace ngr
