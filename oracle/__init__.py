@@ -84,28 +84,33 @@ class Law(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32),
                 ("grid", C.c_uint32), ("r_cut", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("kind", C.c_uint32), ("cored", C.c_uint32),
-                ("beta", C.c_double), ("track_counts", C.c_uint32)]
+                ("beta", C.c_double), ("track_counts", C.c_uint32), ("eps_ab", C.c_void_p)]
 
 
-def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=0.0, track_counts=True):
-    """cored: species indices with a core (accumulator laws)."""
+def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=0.0, track_counts=True,
+             eps_ab=None):
+    """cored: species indices with a core (accumulator laws); eps_ab: D x D
+    per-pair softening, or None for eps everywhere."""
     G = np.ascontiguousarray(G, dtype=np.float64)
     tables = np.ascontiguousarray(tables, dtype=np.float64)
+    ea = None if eps_ab is None else np.ascontiguousarray(eps_ab, dtype=np.float64)
     mask = 0
     for b in cored:
         mask |= 1 << int(b)
     law = Law(G.ctypes.data, tables.ctypes.data, tables.shape[-1], GRID[grid],
-              float(r_cut), float(eps), float(theta), int(kind), mask, float(beta), int(bool(track_counts)))
-    law._keep = (G, tables)  # keep the buffers alive with the struct
+              float(r_cut), float(eps), float(theta), int(kind), mask, float(beta), int(bool(track_counts)),
+              None if ea is None else ea.ctypes.data)
+    law._keep = (G, tables, ea)  # keep the buffers alive with the struct
     return law
 
 
 def law_of(p, track_counts=True):
     acc = getattr(p, "accumulator", None)
+    eps_ab = getattr(p, "eps_ab", None)
     if acc is None:
-        return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta)
+        return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, eps_ab=eps_ab)
     return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, kind=LAW_ACCUMULATOR,
-                    cored=acc["cored"], beta=acc["beta"], track_counts=track_counts)
+                    cored=acc["cored"], beta=acc["beta"], track_counts=track_counts, eps_ab=eps_ab)
 
 
 def cored_radial(r: float, s: float) -> float:

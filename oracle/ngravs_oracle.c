@@ -588,6 +588,7 @@ double orc_cored_radial(double r, double s)
 typedef struct {
     const double* G; const double* tab; uint32_t ntab, grid, D;
     double rc, rc2, eps2, band;
+    const double* eps_ab;      /* per-pair softening (section 2: D^2 softenings), or NULL */
     uint32_t kind, cored;
     double inv4pib;
 } pair_ctx;
@@ -610,7 +611,7 @@ static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, doub
     if (s > 0.0) {
         radial = orc_cored_radial(sqrt(r2), s);
     } else {
-        double re2 = r2 + P->eps2;
+        double re2 = r2 + (P->eps_ab ? P->eps_ab[a * P->D + b] * P->eps_ab[a * P->D + b] : P->eps2);
         radial = 1.0 / (re2 * sqrt(re2));
     }
     double k = P->G[a * P->D + b] * mu * f * radial;
@@ -623,6 +624,7 @@ static void make_pair_ctx(pair_ctx* P, const orc_law* law, uint32_t D)
 {
     P->G = law->G; P->tab = law->tables; P->ntab = law->ntab; P->grid = law->grid; P->D = D;
     P->rc = law->r_cut; P->rc2 = law->r_cut * law->r_cut; P->eps2 = law->eps * law->eps;
+    P->eps_ab = law->eps_ab;
     P->band = 1e-6 * P->rc2;
     P->kind = law->kind;
     P->cored = law->cored;

@@ -44,6 +44,8 @@ typedef struct {
     double beta;           /* accumulator: dimensionless scale, > 0             */
     uint32_t track_counts; /* accumulator: 1 = monopole bodies weigh M/N_perp,
                               0 = a monopole counts as one body of mass M        */
+    const double* eps_ab;  /* D x D Plummer softening per species pair (row = sink
+                              species), or NULL: eps for every pair               */
 } orc_law;
 
 enum { ORC_LAW_TABLE = 0, ORC_LAW_ACCUMULATOR = 1 };

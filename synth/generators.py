@@ -67,6 +67,8 @@ class Problem:
     seed: int = 0
     # accumulator laws (section 3.3): {"cored": species indices, "beta": beta}, or None
     accumulator: Optional[dict] = None
+    # per-pair Plummer softening (D, D), row = sink species, or None for eps everywhere
+    eps_ab: Optional[np.ndarray] = None
 
     @property
     def ntab(self) -> int:

@@ -269,13 +269,13 @@ def test_mac_matches_image_enumeration(oracle_lib):
 
 
 # --------------------------------------------------------------- forces ---
-def two_body(oracle_lib, x0, x1, s0, s1, m0, m1, G, tables, grid, r_cut, eps, box=1.0):
+def two_body(oracle_lib, x0, x1, s0, s1, m0, m1, G, tables, grid, r_cut, eps, box=1.0, eps_ab=None):
     pos = np.array([x0, x1], dtype=np.float64).T.copy()
     X = oracle_lib.lattice(pos, box)
     s = np.array([s0, s1], np.uint8)
     m = np.array([m0, m1])
     D = G.shape[0]
-    law = oracle_lib.make_law(G, tables, grid, r_cut, eps, 0.5)
+    law = oracle_lib.make_law(G, tables, grid, r_cut, eps, 0.5, eps_ab=eps_ab)
     T = oracle_lib.Tree(X, s, m, D, box, 1)
     T.monopoles()
     T.groups(64)
@@ -358,6 +358,32 @@ def test_plummer_kernel_with_flat_factor(oracle_lib):
         assert math.isclose(acc[0, 0], 2.0 * dl / (dl * dl + eps * eps) ** 1.5, rel_tol=1e-14)
         assert math.isclose(acc[0, 1], -1.0 * dl / (dl * dl + eps * eps) ** 1.5, rel_tol=1e-14)
         assert acc[1, 0] == 0 and acc[2, 0] == 0
+
+
+def test_per_pair_softening(oracle_lib):
+    """Section 2's D^2 softenings, each a Plummer length: the sink of species
+    a feels m d/(r^2 + eps_ab^2)^(3/2) from a source of species b, with an
+    asymmetric eps matrix (row = sink species); a matrix of equal entries
+    gives exactly the single-eps result."""
+    tables = np.ones((2, 2, 8))
+    G = np.ones((2, 2))
+    eps_ab = np.array([[0.004, 0.011], [0.02, 0.007]])
+    x0 = np.array([0.25, 0.25, 0.25])
+    for r in [0.002, 0.012, 0.04]:
+        x1 = x0 + np.array([r, 0, 0])
+        acc, accd, X = two_body(oracle_lib, x0, x1, 0, 1, 1.0, 2.0, G, tables, "r", 0.1, 0.5, eps_ab=eps_ab)
+        dl = wrap_diff(X[0, 1], X[0, 0]) * 2.0 ** -64
+        assert math.isclose(acc[0, 0], 2.0 * dl / (dl * dl + eps_ab[0, 1] ** 2) ** 1.5, rel_tol=1e-14)
+        assert math.isclose(acc[0, 1], -1.0 * dl / (dl * dl + eps_ab[1, 0] ** 2) ** 1.5, rel_tol=1e-14)
+        assert np.allclose(accd, acc, rtol=1e-15, atol=0)
+    p = synth.clustered_problem(3000, 3, 6, grid="r2", ntab=256)
+    X = oracle_lib.lattice_of(p)
+    T = oracle_lib.Tree(X, p.species, p.mass, p.D, p.box, p.leaf_size)
+    T.monopoles()
+    T.groups(64)
+    one = oracle_lib.make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta)
+    mat = oracle_lib.make_law(p.G, p.tables, p.grid, p.r_cut, 7.0, p.theta, eps_ab=np.full((3, 3), p.eps))
+    assert np.array_equal(T.force(one)[0], T.force(mat)[0])
 
 
 def test_cutoff_and_tie_slack(oracle_lib):
