@@ -147,6 +147,9 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *            bodies) keeps the softened law. f_ab still multiplies.
  *   cored    accumulator: bit b set = species b is cored (< 2^D)
  *   beta     accumulator: the dimensionless scale of Eqs. (13)-(15), > 0
+ *   eps_ab   host, D x D float64 Plummer softening of each species pair (row =
+ *            sink species; section 2's D^2 softenings), each finite and >= 0,
+ *            or NULL for eps everywhere
  */
 typedef struct {
     const double* G;
@@ -161,6 +164,7 @@ typedef struct {
     uint32_t law;
     uint32_t cored;
     double beta;
+    const double* eps_ab;
 } ngr_force_params;
 
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the

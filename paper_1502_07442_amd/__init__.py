@@ -46,7 +46,8 @@ class TreeParams(C.Structure):
 class ForceParams(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32), ("grid", C.c_uint32),
                 ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
-                ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double)]
+                ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double),
+                ("eps_ab", C.c_void_p)]
 
 
 class ForceStats(C.Structure):
@@ -211,9 +212,11 @@ def compute_monopoles(ctx: Context, tree: Tree, track_counts: bool = True):
 LAW_TABLE, LAW_ACCUMULATOR = 0, 1
 
 
-def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None, accumulator=None):
+def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None, accumulator=None,
+                  eps_ab=None):
     """accumulator: None for a table law, else {"cored": species indices,
-    "beta": beta} for the accumulator laws."""
+    "beta": beta} for the accumulator laws; eps_ab: D x D per-pair softening
+    or None."""
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
     if tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
@@ -225,17 +228,22 @@ def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=N
             mask |= 1 << int(b)
     fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS.get(grid, grid),
                      float(r_s), float(r_cut), float(eps), float(theta), int(group_size), law, mask, beta)
-    fp._keep = (G, tables)
+    ea = None
+    if eps_ab is not None:
+        ea = np.ascontiguousarray(eps_ab, dtype=np.float64).reshape(D, D)
+        fp.eps_ab = ea.ctypes.data
+    fp._keep = (G, tables, ea)
     return fp
 
 
 def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
-               group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None):
+               group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None,
+               eps_ab=None):
     """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
     G (D x D) and tables (D x D x ntab, or None) are host arrays;
     accumulator {"cored": [...], "beta": b} selects the accumulator laws.
     Returns the statistics as a dict (and per-group counts when asked)."""
-    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator)
+    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab)
     st = ForceStats()
     if group_counts:
         ng = groups_count(ctx, tree, group_size)
@@ -371,11 +379,11 @@ class BatchBox:
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
                  leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
-                 accumulator=None):
+                 accumulator=None, eps_ab=None):
         self.n = int(species.shape[0])
         self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
         self.tree = TreeParams(leaf_size)
-        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator)
+        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab)
         self.acc = _dev(acc)
         self._keep = (species, mass, pos, lattice, acc)
 

@@ -162,6 +162,10 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     }
     for (uint32_t k = 0; k < D * D; ++k)
         if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, where + "G has a non-finite entry");
+    if (fp->eps_ab)
+        for (uint32_t k = 0; k < D * D; ++k)
+            if (!(std::isfinite(fp->eps_ab[k]) && fp->eps_ab[k] >= 0.0))
+                fail(NGR_EINVAL, where + "eps_ab entries must be finite and >= 0");
     if (fp->tables)
         for (uint64_t k = 0; k < (uint64_t)D * D * fp->ntab; ++k)
             if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, where + "a table entry is not finite");

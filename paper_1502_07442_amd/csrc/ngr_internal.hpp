@@ -193,6 +193,7 @@ struct Law {
     uint32_t cored = 0;
     uint32_t track = 1;
     double beta = 0;
+    std::vector<double> eps_ab;       // D x D Plummer softening per pair (eps everywhere unless given)
 };
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
 

@@ -254,6 +254,8 @@ struct BoxParams {
     uint32_t wrap_limit, D, ntab;
     double inv4pib;            // accumulator laws: 1 / (4 pi beta); 0 for a table law
     uint32_t cored, track;     // cored species mask (0 for a table law); N_perp tracking
+    double eps2_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // per-pair eps^2, row a = sink species
+    float toff_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];    // r^2-grid table offset -eps_ab^2 / h of each pair
 };
 
 // Per-lane-invariant values of the pair term, taken from the box.
@@ -321,12 +323,11 @@ __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfir
 // records rec[0], rec[K], rec[2K], ... (iters of them; the caller offsets rec
 // by the lane's replica).
 template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K>
-__device__ inline void eval_records(const PairParams& A, const double4* __restrict__ rec, uint32_t iters,
-                                    const void* __restrict__ tbv, double ox, double oy, double oz, double& ax,
-                                    double& ay, double& az)
+__device__ inline void eval_records(const PairParams& A, double eps2, float toff, const double4* __restrict__ rec,
+                                    uint32_t iters, const void* __restrict__ tbv, double ox, double oy, double oz,
+                                    double& ax, double& ay, double& az)
 {
-    const double eps2 = A.eps2;
-    const float tscale = A.tscale, toff = A.toff, tmax = A.tmax;
+    const float tscale = A.tscale, tmax = A.tmax;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
     for (uint32_t it = 0; it < iters; ++it) {
         const double4 s = rec[it * K];
@@ -381,11 +382,11 @@ __device__ inline void eval_records(const PairParams& A, const double4* __restri
 // hardware estimates refined by one float64 Newton step each. The records
 // carry G m (not 1.5 G m) and rs[] the source's core scale.
 template <int GRID, int TAB, bool WRAP, uint32_t K>
-__device__ inline void eval_cored(const PairParams& A, const double4* __restrict__ rec, const double* __restrict__ rs,
-                                  uint32_t iters, const void* __restrict__ tbv, const float2* __restrict__ core,
-                                  double s_sink, double ox, double oy, double oz, double& ax, double& ay, double& az)
+__device__ inline void eval_cored(const PairParams& A, double eps2, const double4* __restrict__ rec,
+                                  const double* __restrict__ rs, uint32_t iters, const void* __restrict__ tbv,
+                                  const float2* __restrict__ core, double s_sink, double ox, double oy, double oz,
+                                  double& ax, double& ay, double& az)
 {
-    const double eps2 = A.eps2;
     const float tscale = A.tscale, tmax = A.tmax;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
     for (uint32_t it = 0; it < iters; ++it) {
@@ -558,18 +559,21 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         auto eval = [&](uint32_t b, uint32_t nrec) {
             const unsigned char* tb = tsm + (TAB == kPair ? 8u : 4u) * b * tstride;
             const uint32_t iters = (nrec + K - 1u) >> lk;
+            // the pair's own softening (section 2: D^2 softenings)
+            const double e2 = P.eps2_ab[a * Dk + b];
+            const float to = P.toff_ab[a * Dk + b];
             if (cored_pair(b)) {
                 const double* rrs = recs + replica;
-                if (wrap) eval_cored<GRID, TAB, true, 1>(pp, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else eval_cored<GRID, TAB, false, 4>(pp, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                if (wrap) eval_cored<GRID, TAB, true, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                else eval_cored<GRID, TAB, false, 4>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
                 return;
             }
-            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(pp, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
-            else eval_records<GRID, TAB, EPS0, false, 4>(pp, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az);
+            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            else eval_records<GRID, TAB, EPS0, false, 4>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az);
         };
 
         // Accepted nodes: one record per non-empty species monopole. The next
@@ -987,6 +991,9 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.cored = fp.law == NGR_LAW_ACCUMULATOR ? fp.cored : 0u;
     law.beta = fp.beta;
     law.track = 1;
+    law.eps_ab.assign((size_t)D * D, fp.eps);
+    if (fp.eps_ab)
+        for (uint32_t k = 0; k < D * D; ++k) law.eps_ab[k] = fp.eps_ab[k];
     law.def.clear();
     if (!fp.tables) {
         const uint32_t ntab = fp.ntab;
@@ -1150,7 +1157,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     uint32_t pair_max = 0, value_max = 0;
     for (uint32_t k = 0; k < nbox; ++k) {
         if (laws[k].grid != grid) fail(NGR_EINVAL, "the boxes of one call must share the table grid");
-        eps0 |= laws[k].eps == 0.0;
+        for (uint32_t ab = 0; ab < laws[k].D * laws[k].D; ++ab) eps0 |= laws[k].eps_ab[ab] == 0.0;
         pair_max = std::max(pair_max, table_bytes(kPair, laws[k].D, laws[k].ntab));
         value_max = std::max(value_max, table_bytes(kValue, laws[k].D, laws[k].ntab));
     }
@@ -1197,6 +1204,10 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             P.toff = 0.0f;
         }
         P.tmax = (float)(law.ntab - 1);
+        for (uint32_t ab = 0; ab < law.D * law.D; ++ab) {
+            P.eps2_ab[ab] = law.eps_ab[ab] * law.eps_ab[ab];
+            P.toff_ab[ab] = law.grid == NGR_GRID_R2 ? (float)(-P.eps2_ab[ab] * ((law.ntab - 1) / rc2)) : 0.0f;
+        }
         for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = 1.5 * law.G[j];   // see eval_records
         P.acc = accv[k];
         P.in_off = t.boff[k];

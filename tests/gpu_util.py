@@ -31,7 +31,7 @@ def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None, trac
     gs = p.group_size if group_size is None else group_size
     res = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
                          theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts,
-                         accumulator=getattr(p, "accumulator", None))
+                         accumulator=getattr(p, "accumulator", None), eps_ab=getattr(p, "eps_ab", None))
     st, gc = (res if group_counts else (res, None))
     out = acc.cpu().numpy()
     if not keep_tree:
