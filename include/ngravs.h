@@ -89,9 +89,18 @@ typedef struct {
 } ngr_particles;
 
 /* leaf_size: a node is a leaf once it holds at most this many particles of
- * all species together (1..64; 0 means 16), or at the deepest level (20). */
+ * all species together (1..64; 0 means 16), or at the deepest level (20).
+ * non_periodic: nonzero for a non-periodic box (section 2: non-periodic
+ * runs use the tree alone). Positions (pos, not lattice) must lie in
+ * [0, box)^3 and pairs interact by their plain separation, with no image:
+ * the tree is built on a lattice four times the box, in which the
+ * minimum-image difference of any two particles is their plain one, and
+ * exported lattice coordinates and centres of mass refer to that larger
+ * box. r_cut may then reach 2 box (any r_cut >= sqrt(3) box keeps every
+ * pair). A non-periodic tree takes no PM force. */
 typedef struct {
     uint32_t leaf_size;
+    uint32_t non_periodic;
 } ngr_tree_params;
 
 /*
@@ -103,7 +112,8 @@ typedef struct {
  * Morton60, stable radix sort, gather, breadth-first octree.
  * Errors: NGR_EINVAL for D outside 1..6, box <= 0 or not finite, n >= 2^32,
  * leaf_size > 64, missing pointers, both or neither of pos / lattice, a
- * species id >= D, a mass < 0 or not finite, a position not finite.
+ * species id >= D, a mass < 0 or not finite, a position not finite; for a
+ * non-periodic box also lattice input and a position outside [0, box).
  * On success *out owns device memory until ngr_tree_free.
  */
 ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p,

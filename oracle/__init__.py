@@ -129,10 +129,17 @@ def lattice(x: np.ndarray, box: float) -> np.ndarray:
     return X
 
 
+def box_of(p) -> float:
+    """The lattice's box: the problem's own, or for a non-periodic problem
+    four times it, where every minimum-image difference of two particles in
+    [0, box) is their plain difference (the non-periodic reading)."""
+    return p.box if getattr(p, "periodic", True) else 4.0 * p.box
+
+
 def lattice_of(p) -> np.ndarray:
     if p.lattice is not None:
         return np.ascontiguousarray(p.lattice, dtype=np.uint64)
-    return lattice(p.pos, p.box)
+    return lattice(p.pos, box_of(p))
 
 
 def morton(kx: int, ky: int, kz: int) -> int:
@@ -176,7 +183,7 @@ class Tree:
 
     @classmethod
     def of(cls, p, group_size: Optional[int] = None):
-        t = cls(lattice_of(p), p.species, p.mass, p.D, p.box, p.leaf_size)
+        t = cls(lattice_of(p), p.species, p.mass, p.D, box_of(p), p.leaf_size)
         t.monopoles()
         t.groups(p.group_size if group_size is None else group_size)
         return t
@@ -269,4 +276,4 @@ def direct(X, species, mass, D: int, box: float, law, sinks: Optional[np.ndarray
 
 
 def direct_of(p, sinks=None):
-    return direct(lattice_of(p), p.species, p.mass, p.D, p.box, law_of(p), sinks)
+    return direct(lattice_of(p), p.species, p.mass, p.D, box_of(p), law_of(p), sinks)

@@ -40,7 +40,7 @@ class Particles(C.Structure):
 
 
 class TreeParams(C.Structure):
-    _fields_ = [("leaf_size", C.c_uint32)]
+    _fields_ = [("leaf_size", C.c_uint32), ("non_periodic", C.c_uint32)]
 
 
 class ForceParams(C.Structure):
@@ -194,12 +194,13 @@ class Tree:
 
 
 def tree_build(ctx: Context, *, D: int, box: float, species, mass, pos=None, lattice=None,
-               leaf_size: int = 16) -> Tree:
+               leaf_size: int = 16, periodic: bool = True) -> Tree:
     """ngr_tree_build: device tensors species (uint8, n), mass (float64, n) and
-    either pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n)."""
+    either pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n).
+    periodic=False: a non-periodic box (positions in [0, box)^3 only)."""
     n = int(species.shape[0])
     p = Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
-    tp = TreeParams(leaf_size)
+    tp = TreeParams(leaf_size, 0 if periodic else 1)
     h = C.c_void_p()
     ctx._check(lib().ngr_tree_build(ctx.handle, C.byref(p), C.byref(tp), C.byref(h)), "tree build")
     return Tree(ctx, h)

@@ -199,6 +199,14 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
     b.n = p->n;
     b.D = p->D;
     b.box = p->box;
+    b.region = 0.0;
+    if (tp && tp->non_periodic) {
+        // a non-periodic box sits in the first quarter of a lattice four
+        // times its size: every difference is then below half that lattice
+        if (p->n && !p->pos) fail(NGR_EINVAL, where + "a non-periodic box takes positions, not lattice coordinates");
+        b.region = p->box;
+        b.box = 4.0 * p->box;
+    }
     b.leaf_size = B;
     b.pos = p->pos;
     b.lattice = p->lattice;
@@ -659,6 +667,7 @@ NGR_API ngr_status ngr_pm_force(ngr_context* ctx, ngr_pm* pm, const ngr_tree* tr
         if (!pm || !tree) fail(NGR_EINVAL, "pm and tree must not be NULL");
         if (tree->nbox != 1) fail(NGR_EINVAL, "the tree must hold one box");
         if (tree->D != pm->D) fail(NGR_EINVAL, "the tree's D differs from the plan's");
+        if (tree->region > 0.0) fail(NGR_EINVAL, "a non-periodic tree takes no PM force");
         if (tree->box != pm->box) fail(NGR_EINVAL, "the tree's box differs from the plan's");
         if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
         ngr::PmTimes tm;

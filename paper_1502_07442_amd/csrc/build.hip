@@ -15,7 +15,7 @@
 namespace ngr {
 namespace {
 
-enum : uint32_t { kBadSpecies = 1, kBadMass = 2, kBadPos = 4 };
+enum : uint32_t { kBadSpecies = 1, kBadMass = 2, kBadPos = 4, kBadRegion = 8 };
 
 // One box of a build as the device sees it.
 struct BoxInDev {
@@ -25,6 +25,7 @@ struct BoxInDev {
     const double* mass;
     uint64_t n, off;          // particles and first index in the concatenated arrays
     double box;
+    double region;            // non-periodic: positions must lie in [0, region); 0 for periodic
     uint32_t D, leaf;
 };
 
@@ -75,6 +76,7 @@ __global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64
             for (int a = 0; a < 3; ++a) {
                 const double x = B.pos[a * B.n + i];
                 if (!isfinite(x)) bad |= kBadPos;
+                if (B.region > 0.0 && !(x >= 0.0 && x < B.region)) bad |= kBadRegion;
                 double u = x / B.box;
                 u = u - floor(u);
                 if (!(u < 1.0)) u = 0.0;
@@ -423,7 +425,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
         t.bD[k] = b.D;
         t.bbox[k] = b.box;
         t.bleaf[k] = b.leaf_size;
-        bin[k] = BoxInDev{b.pos, b.lattice, b.species, b.mass, b.n, n, b.box, b.D, b.leaf_size};
+        bin[k] = BoxInDev{b.pos, b.lattice, b.species, b.mass, b.n, n, b.box, b.region, b.D, b.leaf_size};
         n += b.n;
     }
     t.boff[nbox] = n;
@@ -431,6 +433,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
     t.n = n;
     t.D = D;
     t.box = t.bbox[0];
+    t.region = boxes[0].region;
     t.leaf_size = t.bleaf[0];
 
     // ---- input checks, lattice, keys and species counts (one synchronisation)
@@ -480,7 +483,8 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
         ctx.release(boxid);
         if (flags[k] & kBadSpecies) fail(NGR_EINVAL, where + "a species id is >= D");
         if (flags[k] & kBadMass) fail(NGR_EINVAL, where + "a mass is negative or not finite");
-        fail(NGR_EINVAL, where + "a position is not finite");
+        if (flags[k] & kBadPos) fail(NGR_EINVAL, where + "a position is not finite");
+        fail(NGR_EINVAL, where + "a position lies outside the non-periodic box");
     }
     t.bseg.assign((size_t)nbox * (NGR_MAX_SPECIES + 1), 0);
     for (uint32_t k = 0; k < nbox; ++k) {

@@ -84,6 +84,7 @@ struct BoxIn {
     const uint64_t* lattice = nullptr;   // 3 x n, or NULL
     const uint8_t* species = nullptr;
     const double* mass = nullptr;
+    double region = 0.0;                 // non-periodic: the user's box (box is 4 region), else 0
 };
 
 // The tree of one or more independent boxes built together. Particles of all
@@ -104,6 +105,7 @@ struct Tree {
     uint64_t* boff_dev = nullptr;  // device copy of boff
     // one-box conveniences (box 0)
     double box = 0.0;
+    double region = 0.0;           // non-periodic box 0: the user's box (box = 4 region), else 0
     uint32_t leaf_size = 16;
     uint64_t seg[NGR_MAX_SPECIES + 1] = {0};
     // particles in sorted order (box, species, Morton key)

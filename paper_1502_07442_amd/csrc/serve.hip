@@ -151,6 +151,7 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
     Request* r = new Request();
     try {
         check_particles(&rq->particles, &rq->tree, "", r->in);
+        if (r->in.region > 0.0) fail(NGR_EINVAL, "the server steps periodic boxes only");
         uint32_t gs = check_force_params(r->in.D, r->in.box, &rq->force, "");
         r->gs = gs ? gs : chosen_group_size(r->in.n, r->in.D);
         if (!(std::isfinite(rq->dt) && rq->dt > 0.0)) fail(NGR_EINVAL, "dt must be finite and > 0");

@@ -30,7 +30,7 @@ __all__ = [
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
-    "accumulator_problem", "yukawa_law", "exact_split_laws",
+    "accumulator_problem", "yukawa_law", "exact_split_laws", "isolated_problem",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -69,6 +69,8 @@ class Problem:
     accumulator: Optional[dict] = None
     # per-pair Plummer softening (D, D), row = sink species, or None for eps everywhere
     eps_ab: Optional[np.ndarray] = None
+    # False: a non-periodic box (pairs interact by their plain separation, no images)
+    periodic: bool = True
 
     @property
     def ntab(self) -> int:
@@ -366,3 +368,44 @@ def exact_split_laws(D: int, seed: int, lam_range=(0.003, 0.03), box: float = 1.
                 law = yukawa_law(float(rng.uniform(-0.5, 1.0)), lam)
             laws[a][b] = laws[b][a] = law
     return laws
+
+
+def isolated_problem(n: int, D: int, seed: int, *, grid: str = GRID_R2, ntab: int = 2048, theta: float = 0.5,
+                     leaf_size: int = 16, group_size: int = 64, box: float = 1.0) -> Problem:
+    """A non-periodic box standing in for the paper's isolated runs (the
+    galaxy collision of Appendix A): two Plummer spheres of scale 0.05 box,
+    centred a third of the box apart, 90% of the particles, the rest uniform;
+    D equal species; full laws (no short-range split): Newton with
+    probability 1/2, else the Yukawa modulation 1 + alpha (1 + r/lam)
+    exp(-r/lam), random G in [0.5, 2]; r_cut = 1.75 box keeps every pair
+    (sqrt(3) box is the largest separation)."""
+    rng = np.random.default_rng(seed)
+    n_cl = int(round(0.9 * n))
+    half = n_cl // 2
+    centres = np.array([[0.35, 0.4, 0.45], [0.68, 0.6, 0.52]]) * box
+    hid = np.concatenate([np.zeros(half, np.int64), np.ones(n_cl - half, np.int64)])
+    r = _plummer_radii(hid.size, np.full(hid.size, 0.05 * box), rng)
+    d = rng.normal(size=(hid.size, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    p = np.concatenate([centres[hid] + r[:, None] * d, rng.random((n - n_cl, 3)) * box], axis=0)
+    p = np.clip(p, 0.0, np.nextafter(box, 0.0))         # an isolated box has no wrap: keep the few far ones inside
+    p = p[rng.permutation(n)]
+    species = exact_species(n, np.ones(D), rng)
+    r_cut = 1.75 * box
+    eps = box / n ** (1.0 / 3.0) / 40.0
+    G = np.zeros((D, D))
+    tables = np.zeros((D, D, ntab))
+    for a in range(D):
+        for b in range(a, D):
+            G[a, b] = G[b, a] = rng.uniform(0.5, 2.0)
+            if rng.random() < 0.5:
+                t = np.ones(ntab)
+            else:
+                lam = math.exp(rng.uniform(math.log(0.01), math.log(0.3))) * box
+                alpha = rng.uniform(-0.5, 1.0)
+                t = sample_table(lambda x: 1.0 + alpha * (1.0 + x / lam) * np.exp(-x / lam), ntab, r_cut, grid)
+            tables[a, b] = tables[b, a] = t
+    return Problem(name=f"isolated-{n}-D{D}-seed{seed}", n=n, D=D, box=box, species=species,
+                   mass=np.full(n, 1.0 / n), G=G, tables=tables, grid=grid, r_s=0.0, r_cut=r_cut, eps=eps,
+                   theta=theta, leaf_size=leaf_size, group_size=group_size, pos=np.ascontiguousarray(p.T), seed=seed,
+                   periodic=False)
