@@ -58,6 +58,7 @@ def lib():
             "orc_groups": (u64, [P, u32]),
             "orc_groups_export": (None, [P] * 6),
             "orc_mac": (C.c_int, [P, u64, P, P, dbl, dbl]),
+            "orc_mac_relative": (C.c_int, [P, u64, P, P, dbl, dbl, dbl]),
             "orc_group_list": (u64, [P, P, u64, P, u64]),
             "orc_tree_force": (C.c_int, [P, P, P, u64, P, P, P, P]),
             "orc_direct": (C.c_int, [u64, u32, dbl, P, P, P, P, P, u64, P, P]),
@@ -78,19 +79,22 @@ def _p(a: Optional[np.ndarray]):
 
 
 LAW_TABLE, LAW_ACCUMULATOR = 0, 1
+OPEN_GEOMETRIC, OPEN_RELATIVE = 0, 1
 
 
 class Law(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32),
                 ("grid", C.c_uint32), ("r_cut", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("kind", C.c_uint32), ("cored", C.c_uint32),
-                ("beta", C.c_double), ("track_counts", C.c_uint32), ("eps_ab", C.c_void_p)]
+                ("beta", C.c_double), ("track_counts", C.c_uint32), ("eps_ab", C.c_void_p),
+                ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p)]
 
 
 def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=0.0, track_counts=True,
-             eps_ab=None):
+             eps_ab=None, alpha=None, old_acc=None):
     """cored: species indices with a core (accumulator laws); eps_ab: D x D
-    per-pair softening, or None for eps everywhere."""
+    per-pair softening, or None for eps everywhere; alpha and old_acc (n
+    previous |a| in input order) select the relative opening test."""
     G = np.ascontiguousarray(G, dtype=np.float64)
     tables = np.ascontiguousarray(tables, dtype=np.float64)
     ea = None if eps_ab is None else np.ascontiguousarray(eps_ab, dtype=np.float64)
@@ -100,17 +104,25 @@ def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=
     law = Law(G.ctypes.data, tables.ctypes.data, tables.shape[-1], GRID[grid],
               float(r_cut), float(eps), float(theta), int(kind), mask, float(beta), int(bool(track_counts)),
               None if ea is None else ea.ctypes.data)
-    law._keep = (G, tables, ea)  # keep the buffers alive with the struct
+    oa = None
+    if alpha is not None:
+        oa = np.ascontiguousarray(old_acc, dtype=np.float64)
+        law.opening, law.alpha, law.old_acc = OPEN_RELATIVE, float(alpha), oa.ctypes.data
+    law._keep = (G, tables, ea, oa)  # keep the buffers alive with the struct
     return law
 
 
 def law_of(p, track_counts=True):
     acc = getattr(p, "accumulator", None)
     eps_ab = getattr(p, "eps_ab", None)
+    rel = getattr(p, "relative", None)
+    extra = dict(eps_ab=eps_ab)
+    if rel is not None:
+        extra.update(alpha=rel["alpha"], old_acc=rel["old_acc"])
     if acc is None:
-        return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, eps_ab=eps_ab)
+        return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, **extra)
     return make_law(p.G, p.tables, p.grid, p.r_cut, p.eps, p.theta, kind=LAW_ACCUMULATOR,
-                    cored=acc["cored"], beta=acc["beta"], track_counts=track_counts, eps_ab=eps_ab)
+                    cored=acc["cored"], beta=acc["beta"], track_counts=track_counts, **extra)
 
 
 def cored_radial(r: float, s: float) -> float:
@@ -235,6 +247,11 @@ class Tree:
         lo = np.ascontiguousarray(lo, np.uint32)
         hi = np.ascontiguousarray(hi, np.uint32)
         return int(lib().orc_mac(self._t, node, _p(lo), _p(hi), R2, theta2))
+
+    def mac_relative(self, node: int, lo, hi, R2: float, rel_k: float, a_min: float) -> int:
+        lo = np.ascontiguousarray(lo, np.uint32)
+        hi = np.ascontiguousarray(hi, np.uint32)
+        return int(lib().orc_mac_relative(self._t, node, _p(lo), _p(hi), R2, rel_k, a_min))
 
     def group_list(self, law, g: int) -> np.ndarray:
         n = int(lib().orc_group_list(self._t, C.byref(law), g, None, 0))

@@ -466,6 +466,54 @@ int orc_mac(const orc_tree* t, uint64_t node, const uint32_t lo[3],
     return ORC_OPEN;
 }
 
+/*
+ * The relative opening test (section 2.2: the walk keeps the stock code's
+ * criterion, which compares the previously computed acceleration with a
+ * Newtonian estimate of the node's contribution). Reading, per group: with
+ * M the node's mass over all species, l its side and d_min as above, the
+ * node is accepted when M l^2 / d_min^4 <= alpha a_min, a_min the smallest
+ * previous |a| of the group's sinks, and when d_max < r_cut (the short-range
+ * clause above); it is opened when the group's box reaches into the node's
+ * cube grown to 1.2 times its side (the stock code's guard against accepting
+ * a node that holds the sink), and pruned when d_min >= r_cut. In half key
+ * units l = 2 S and lengths scale by u = box / 2^21, so the test is
+ * M (4 S^2) <= (alpha u^2 a_min) D2^2, evaluated in float64 in that order;
+ * rel_k = alpha u^2.
+ */
+int orc_mac_relative(const orc_tree* t, uint64_t node, const uint32_t lo[3],
+                     const uint32_t hi[3], double R2, double rel_k, double a_min)
+{
+    uint32_t c[3], S;
+    node_cell(t, node, c, &S);
+    const int64_t half = 1ll << ORC_LEVELS;
+    int64_t D2 = 0, D2max = 0;
+    int inside = 1;
+    for (unsigned a = 0; a < 3; ++a) {
+        int64_t w = (int64_t)hi[a] - (int64_t)lo[a];
+        int64_t d = (2 * (int64_t)c[a] + (int64_t)S) - ((int64_t)lo[a] + (int64_t)hi[a]);
+        d = ((d + half) % (2 * half) + 2 * half) % (2 * half) - half;
+        int64_t ad = d < 0 ? -d : d;
+        int64_t g = 0;
+        if ((int64_t)S + w < half) {
+            g = ad - ((int64_t)S + w);
+            if (g < 0) g = 0;
+        }
+        int64_t gmax = ad + (int64_t)S + w;
+        D2 += g * g;
+        D2max += gmax * gmax;
+        /* group box within the grown cube on this axis: |d| < 1.2 S + w */
+        if (!(5 * ad < 6 * (int64_t)S + 5 * w)) inside = 0;
+    }
+    if ((double)D2 >= R2) return ORC_PRUNE;
+    if (inside) return ORC_OPEN;
+    double M = 0.0;
+    for (uint32_t b = 0; b < t->D; ++b) M += t->M[b][node];
+    const double lhs = M * (double)(4 * (int64_t)S * (int64_t)S);
+    const double rhs = (rel_k * a_min) * ((double)D2 * (double)D2);
+    if (lhs <= rhs && (double)D2max < R2) return ORC_ACCEPT;
+    return ORC_OPEN;
+}
+
 static void mac_constants(const orc_tree* t, const orc_law* law, double* R2, double* theta2)
 {
     double q = law->r_cut / t->box * 2097152.0;   /* r_cut in half key units */
@@ -485,25 +533,39 @@ static void list_push(list_t* L, uint64_t v)
     L->e[L->n++] = v;
 }
 
+/* rel: 0 for the geometric test, else the relative one with rel_k, a_min */
+typedef struct { int rel; double R2, theta2, rel_k, a_min; } mac_args;
+
 static void walk(const orc_tree* t, uint64_t i, const uint32_t lo[3], const uint32_t hi[3],
-                 double R2, double theta2, list_t* L)
+                 const mac_args* m, list_t* L)
 {
-    int d = orc_mac(t, i, lo, hi, R2, theta2);
+    int d = m->rel ? orc_mac_relative(t, i, lo, hi, m->R2, m->rel_k, m->a_min)
+                   : orc_mac(t, i, lo, hi, m->R2, m->theta2);
     if (d == ORC_PRUNE) return;
     if (d == ORC_ACCEPT) { list_push(L, i | (1ull << 32)); return; }
     if (t->n_child[i] == 0) { list_push(L, i | (2ull << 32)); return; }
     for (uint64_t c = (uint64_t)t->first_child[i]; c < (uint64_t)t->first_child[i] + t->n_child[i]; ++c)
-        walk(t, c, lo, hi, R2, theta2, L);
+        walk(t, c, lo, hi, m, L);
 }
 
 static void group_list(const orc_tree* t, const orc_law* law, uint64_t g, list_t* L)
 {
-    double R2, theta2;
-    mac_constants(t, law, &R2, &theta2);
+    mac_args m = {0, 0.0, 0.0, 0.0, 0.0};
+    mac_constants(t, law, &m.R2, &m.theta2);
+    if (law->opening == ORC_OPEN_RELATIVE) {
+        const double u = t->box / 2097152.0;    /* one half key unit */
+        m.rel = 1;
+        m.rel_k = law->alpha * (u * u);
+        m.a_min = INFINITY;
+        for (uint64_t i = t->gstart[g]; i < t->gstart[g] + t->gcount[g]; ++i) {
+            double a = law->old_acc[t->perm[i]];
+            if (a < m.a_min) m.a_min = a;
+        }
+    }
     uint32_t lo[3], hi[3];
     for (unsigned a = 0; a < 3; ++a) { lo[a] = t->glo[a][g]; hi[a] = t->ghi[a][g]; }
     L->n = 0;
-    walk(t, 0, lo, hi, R2, theta2, L);
+    walk(t, 0, lo, hi, &m, L);
 }
 
 uint64_t orc_group_list(const orc_tree* t, const orc_law* law, uint64_t g,

@@ -46,9 +46,13 @@ typedef struct {
                               0 = a monopole counts as one body of mass M        */
     const double* eps_ab;  /* D x D Plummer softening per species pair (row = sink
                               species), or NULL: eps for every pair               */
+    uint32_t opening;      /* ORC_OPEN_GEOMETRIC or ORC_OPEN_RELATIVE             */
+    double alpha;          /* relative: the force-error tolerance, > 0            */
+    const double* old_acc; /* relative: n previous |a| in input order             */
 } orc_law;
 
 enum { ORC_LAW_TABLE = 0, ORC_LAW_ACCUMULATOR = 1 };
+enum { ORC_OPEN_GEOMETRIC = 0, ORC_OPEN_RELATIVE = 1 };
 
 int      orc_num_threads(void);
 
@@ -78,6 +82,8 @@ void     orc_groups_export(const orc_tree* t, uint8_t* species, uint32_t* start,
                            uint32_t* count, uint32_t* lo, uint32_t* hi);
 
 /* interaction list of one group: entries are node | kind << 32 */
+int      orc_mac_relative(const orc_tree* t, uint64_t node, const uint32_t lo[3],
+                          const uint32_t hi[3], double R2, double rel_k, double a_min);
 int      orc_mac(const orc_tree* t, uint64_t node, const uint32_t lo[3],
                  const uint32_t hi[3], double R2, double theta2);
 uint64_t orc_group_list(const orc_tree* t, const orc_law* law, uint64_t g,

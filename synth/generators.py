@@ -71,6 +71,8 @@ class Problem:
     eps_ab: Optional[np.ndarray] = None
     # False: a non-periodic box (pairs interact by their plain separation, no images)
     periodic: bool = True
+    # relative opening test: {"alpha": tolerance, "old_acc": (n,) previous |a|}, or None (geometric)
+    relative: Optional[dict] = None
 
     @property
     def ntab(self) -> int:
