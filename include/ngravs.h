@@ -54,6 +54,8 @@ typedef int32_t ngr_status;
 #define NGR_GRID_R2     1      /* table samples uniform in r^2 on [0, r_cut^2]          */
 #define NGR_LAW_TABLE        0   /* f_ab(r) times the softened Newtonian force            */
 #define NGR_LAW_ACCUMULATOR  1   /* section 3.3: cored species, Eqs. (13)-(17)            */
+#define NGR_OPEN_GEOMETRIC   0   /* opening test: side < theta d_min                      */
+#define NGR_OPEN_RELATIVE    1   /* opening test: M l^2 <= alpha a_old d_min^4 (section 2.2) */
 #define NGR_MAX_TABLE   12288  /* D * ntab must not exceed this (one sink species' D
                                   tables are held on chip during the walk)              */
 
@@ -160,6 +162,20 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   eps_ab   host, D x D float64 Plummer softening of each species pair (row =
  *            sink species; section 2's D^2 softenings), each finite and >= 0,
  *            or NULL for eps everywhere
+ *   opening  NGR_OPEN_GEOMETRIC (0), the test described at ngr_tree_force, or
+ *            NGR_OPEN_RELATIVE: section 2.2 keeps the stock code's relative
+ *            criterion, the previous acceleration against a Newtonian
+ *            estimate of the node's contribution. Per group: a node is
+ *            accepted when M l^2 <= alpha a_min d_min^4 (M its mass over all
+ *            species, l its side, a_min the smallest previous |a| of the
+ *            group's sinks) and d_max < r_cut; opened when the group's box
+ *            reaches into the node's cube grown to 1.2 sides; pruned when
+ *            d_min >= r_cut. theta is not used. Evaluated in float64 as
+ *            M (4 S^2) <= (alpha u^2 a_min) D2^2 in half key units
+ *            (u = box / 2^21).
+ *   alpha    relative: the tolerance, finite and > 0
+ *   old_acc  relative: device, n float64, the previous |a| of each particle
+ *            in input order (read during the call)
  */
 typedef struct {
     const double* G;
@@ -175,6 +191,9 @@ typedef struct {
     uint32_t cored;
     double beta;
     const double* eps_ab;
+    uint32_t opening;
+    double alpha;
+    const double* old_acc;
 } ngr_force_params;
 
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the

@@ -47,7 +47,7 @@ class ForceParams(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32), ("grid", C.c_uint32),
                 ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
                 ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double),
-                ("eps_ab", C.c_void_p)]
+                ("eps_ab", C.c_void_p), ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p)]
 
 
 class ForceStats(C.Structure):
@@ -214,10 +214,11 @@ LAW_TABLE, LAW_ACCUMULATOR = 0, 1
 
 
 def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None, accumulator=None,
-                  eps_ab=None):
+                  eps_ab=None, relative=None):
     """accumulator: None for a table law, else {"cored": species indices,
     "beta": beta} for the accumulator laws; eps_ab: D x D per-pair softening
-    or None."""
+    or None; relative: None for the geometric opening test, else {"alpha":
+    alpha, "old_acc": device tensor of the previous |a| (n, float64)}."""
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
     if tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
@@ -233,18 +234,23 @@ def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=N
     if eps_ab is not None:
         ea = np.ascontiguousarray(eps_ab, dtype=np.float64).reshape(D, D)
         fp.eps_ab = ea.ctypes.data
-    fp._keep = (G, tables, ea)
+    oa = None
+    if relative is not None:
+        oa = relative["old_acc"]
+        fp.opening, fp.alpha, fp.old_acc = 1, float(relative["alpha"]), _dev(oa)
+    fp._keep = (G, tables, ea, oa)
     return fp
 
 
 def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
                group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None,
-               eps_ab=None):
+               eps_ab=None, relative=None):
     """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
     G (D x D) and tables (D x D x ntab, or None) are host arrays;
     accumulator {"cored": [...], "beta": b} selects the accumulator laws.
     Returns the statistics as a dict (and per-group counts when asked)."""
-    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab)
+    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
+                       relative)
     st = ForceStats()
     if group_counts:
         ng = groups_count(ctx, tree, group_size)
@@ -380,11 +386,12 @@ class BatchBox:
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
                  leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
-                 accumulator=None, eps_ab=None):
+                 accumulator=None, eps_ab=None, relative=None):
         self.n = int(species.shape[0])
         self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
         self.tree = TreeParams(leaf_size)
-        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab)
+        self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
+                                   relative)
         self.acc = _dev(acc)
         self._keep = (species, mass, pos, lattice, acc)
 

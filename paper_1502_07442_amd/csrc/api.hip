@@ -162,6 +162,12 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     }
     for (uint32_t k = 0; k < D * D; ++k)
         if (!std::isfinite(fp->G[k])) fail(NGR_EINVAL, where + "G has a non-finite entry");
+    if (fp->opening != NGR_OPEN_GEOMETRIC && fp->opening != NGR_OPEN_RELATIVE)
+        fail(NGR_EINVAL, where + "opening must be NGR_OPEN_GEOMETRIC or NGR_OPEN_RELATIVE");
+    if (fp->opening == NGR_OPEN_RELATIVE) {
+        if (!ngr::finite_pos(fp->alpha)) fail(NGR_EINVAL, where + "alpha must be finite and > 0");
+        if (!fp->old_acc) fail(NGR_EINVAL, where + "old_acc is NULL");
+    }
     if (fp->eps_ab)
         for (uint32_t k = 0; k < D * D; ++k)
             if (!(std::isfinite(fp->eps_ab[k]) && fp->eps_ab[k] >= 0.0))

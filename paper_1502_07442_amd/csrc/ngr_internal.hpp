@@ -196,6 +196,9 @@ struct Law {
     uint32_t track = 1;
     double beta = 0;
     std::vector<double> eps_ab;       // D x D Plummer softening per pair (eps everywhere unless given)
+    uint32_t opening = NGR_OPEN_GEOMETRIC;
+    double alpha = 0;
+    const double* old_acc = nullptr;  // device, previous |a| of the box's particles (relative test)
 };
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
 

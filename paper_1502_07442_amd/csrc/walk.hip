@@ -254,6 +254,9 @@ struct BoxParams {
     uint32_t wrap_limit, D, ntab;
     double inv4pib;            // accumulator laws: 1 / (4 pi beta); 0 for a table law
     uint32_t cored, track;     // cored species mask (0 for a table law); N_perp tracking
+    const double* old_acc;     // relative opening test: previous |a| of the box's particles (input order)
+    double rel_k;              // relative opening test: alpha (box / 2^21)^2
+    uint32_t relative;         // 1: the relative opening test, 0: the geometric one
     double eps2_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // per-pair eps^2, row a = sink species
     float toff_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];    // r^2-grid table offset -eps_ab^2 / h of each pair
 };
@@ -550,6 +553,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         }
         double ax = 0.0, ay = 0.0, az = 0.0;
         unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
+        // relative opening test: the smallest previous |a| of the group's sinks
+        const bool rel = P.relative != 0u;
+        double a_min = 0.0;
+        if (rel) {
+            double am = __builtin_inf();
+            if (sink < ns) am = P.old_acc[A.perm[s0 + sink] - in_off];
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) am = fmin(am, __shfl_xor(am, d, 64));
+            a_min = am;
+        }
         // the sink's own core scale (accumulator laws, cored sink species)
         double s_sink = 0.0;
         if (ACC && core_a && sink < ns) s_sink = A.mass[s0 + sink] * inv4pib;
@@ -732,6 +745,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 const int32_t S = 1 << (kLevels - (int)cl.w);
                 const uint32_t cc[3] = {cl.x, cl.y, cl.z};
                 double D2 = 0.0, D2m = 0.0;
+                bool inside = true;       // the group's box reaches into the node's cube grown to 1.2 sides
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int32_t w = (int32_t)(hi[k] - lo[k]);
@@ -743,9 +757,23 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     const int32_t gm = ad + S + w;
                     D2 += (double)gp * (double)gp;
                     D2m += (double)gm * (double)gm;
+                    inside = inside && 5 * ad < 6 * S + 5 * w;
+                }
+                bool accept;
+                if (rel) {
+                    // M l^2 <= alpha a_min d^4 with M the node's mass over all
+                    // species, l = 2 S and d^2 = D2 in half key units
+                    double M = 0.0;
+                    if (!inside && D2 < R2)
+                        for (uint32_t b = 0; b < D; ++b) M += A.mono[(uint64_t)b * A.nn + node].w;
+                    const double lhs = M * (double)(4ll * S * S);
+                    const double rhs = (P.rel_k * a_min) * (D2 * D2);
+                    accept = !inside && lhs <= rhs && D2m < R2;
+                } else {
+                    accept = (double)(4ll * S * S) < theta2 * D2 && D2m < R2;
                 }
                 if (D2 >= R2) dec = kPrune;
-                else if ((double)(4ll * S * S) < theta2 * D2 && D2m < R2) dec = kAccept;
+                else if (accept) dec = kAccept;
                 else {
                     dec = kOpen;
                     nc = A.n_child[node];
@@ -991,6 +1019,9 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.cored = fp.law == NGR_LAW_ACCUMULATOR ? fp.cored : 0u;
     law.beta = fp.beta;
     law.track = 1;
+    law.opening = fp.opening;
+    law.alpha = fp.alpha;
+    law.old_acc = fp.old_acc;
     law.eps_ab.assign((size_t)D * D, fp.eps);
     if (fp.eps_ab)
         for (uint32_t k = 0; k < D * D; ++k) law.eps_ab[k] = fp.eps_ab[k];
@@ -1221,6 +1252,12 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             P.inv4pib = 1.0 / (4.0 * M_PI * law.beta);
         }
         P.track = law.track;
+        if (law.opening == NGR_OPEN_RELATIVE) {
+            const double u = box / 2097152.0;   // one half key unit
+            P.relative = 1;
+            P.rel_k = law.alpha * (u * u);
+            P.old_acc = law.old_acc;
+        }
     }
     BoxParams* boxes = static_cast<BoxParams*>(ctx.alloc(nbox * sizeof(BoxParams)));
     ctx.to_device(boxes, bp.data(), nbox * sizeof(BoxParams));

@@ -29,9 +29,13 @@ def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None, trac
     ngr.compute_monopoles(ctx, tree, track_counts=track_counts)
     acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
     gs = p.group_size if group_size is None else group_size
+    rel = getattr(p, "relative", None)
+    if rel is not None:
+        rel = {"alpha": rel["alpha"], "old_acc": torch.from_numpy(np.ascontiguousarray(rel["old_acc"])).cuda()}
     res = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
                          theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts,
-                         accumulator=getattr(p, "accumulator", None), eps_ab=getattr(p, "eps_ab", None))
+                         accumulator=getattr(p, "accumulator", None), eps_ab=getattr(p, "eps_ab", None),
+                         relative=rel)
     st, gc = (res if group_counts else (res, None))
     out = acc.cpu().numpy()
     if not keep_tree:
