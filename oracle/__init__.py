@@ -87,14 +87,16 @@ class Law(C.Structure):
                 ("grid", C.c_uint32), ("r_cut", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("kind", C.c_uint32), ("cored", C.c_uint32),
                 ("beta", C.c_double), ("track_counts", C.c_uint32), ("eps_ab", C.c_void_p),
-                ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p)]
+                ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p),
+                ("corr", C.c_void_p), ("corr_n", C.c_uint32)]
 
 
 def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=0.0, track_counts=True,
-             eps_ab=None, alpha=None, old_acc=None):
+             eps_ab=None, alpha=None, old_acc=None, corr=None):
     """cored: species indices with a core (accumulator laws); eps_ab: D x D
     per-pair softening, or None for eps everywhere; alpha and old_acc (n
-    previous |a| in input order) select the relative opening test."""
+    previous |a| in input order) select the relative opening test; corr
+    (D, D, n+1, n+1, n+1, 3) lattice correction tables (no cut-off then)."""
     G = np.ascontiguousarray(G, dtype=np.float64)
     tables = np.ascontiguousarray(tables, dtype=np.float64)
     ea = None if eps_ab is None else np.ascontiguousarray(eps_ab, dtype=np.float64)
@@ -108,7 +110,11 @@ def make_law(G, tables, grid, r_cut, eps, theta, kind=LAW_TABLE, cored=(), beta=
     if alpha is not None:
         oa = np.ascontiguousarray(old_acc, dtype=np.float64)
         law.opening, law.alpha, law.old_acc = OPEN_RELATIVE, float(alpha), oa.ctypes.data
-    law._keep = (G, tables, ea, oa)  # keep the buffers alive with the struct
+    co = None
+    if corr is not None:
+        co = np.ascontiguousarray(corr, dtype=np.float64)
+        law.corr, law.corr_n = co.ctypes.data, co.shape[2] - 1
+    law._keep = (G, tables, ea, oa, co)  # keep the buffers alive with the struct
     return law
 
 
@@ -116,7 +122,7 @@ def law_of(p, track_counts=True):
     acc = getattr(p, "accumulator", None)
     eps_ab = getattr(p, "eps_ab", None)
     rel = getattr(p, "relative", None)
-    extra = dict(eps_ab=eps_ab)
+    extra = dict(eps_ab=eps_ab, corr=getattr(p, "lattice_corr", None))
     if rel is not None:
         extra.update(alpha=rel["alpha"], old_acc=rel["old_acc"])
     if acc is None:

@@ -517,7 +517,7 @@ int orc_mac_relative(const orc_tree* t, uint64_t node, const uint32_t lo[3],
 static void mac_constants(const orc_tree* t, const orc_law* law, double* R2, double* theta2)
 {
     double q = law->r_cut / t->box * 2097152.0;   /* r_cut in half key units */
-    *R2 = q * q;
+    *R2 = law->corr ? INFINITY : q * q;    /* with lattice corrections every pair interacts */
     *theta2 = law->theta * law->theta;
 }
 
@@ -653,7 +653,42 @@ typedef struct {
     const double* eps_ab;      /* per-pair softening (section 2: D^2 softenings), or NULL */
     uint32_t kind, cored;
     double inv4pib;
+    const double* corr;        /* lattice correction tables, or NULL */
+    uint32_t corr_n;
+    double corr_scale;         /* corr_n / (box / 2) */
 } pair_ctx;
+
+/*
+ * Lattice correction (section 2.3: tabulated corrections from the infinite
+ * image lattice, interpolated to the particle offsets as the stock code
+ * does). A table T holds, on the grid d in [0, box/2]^3 of n intervals per
+ * axis, the extra acceleration of a sink from all images of a unit source at
+ * offset d other than the nearest; it is odd in each component's own axis
+ * and even in the others, so the value at d is the trilinear interpolation
+ * at |d| with each component's sign set by its axis.
+ */
+static void lattice_correction(const double* T, uint32_t n, double scale, const double d[3], double out[3])
+{
+    uint32_t i[3];
+    double f[3];
+    for (unsigned x = 0; x < 3; ++x) {
+        double u = fabs(d[x]) * scale;
+        uint32_t k = (uint32_t)u;
+        if (k > n - 1) k = n - 1;
+        i[x] = k;
+        f[x] = u - (double)k;
+        out[x] = 0.0;
+    }
+    const uint64_t m = n + 1;
+    for (unsigned c = 0; c < 8; ++c) {
+        unsigned cx = c >> 2, cy = (c >> 1) & 1, cz = c & 1;
+        double w = (cx ? f[0] : 1.0 - f[0]) * (cy ? f[1] : 1.0 - f[1]) * (cz ? f[2] : 1.0 - f[2]);
+        const double* e = T + (((uint64_t)(i[0] + cx) * m + (i[1] + cy)) * m + (i[2] + cz)) * 3;
+        for (unsigned x = 0; x < 3; ++x) out[x] += w * e[x];
+    }
+    for (unsigned x = 0; x < 3; ++x)
+        if (d[x] < 0.0) out[x] = -out[x];
+}
 
 static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, double mu_body,
                       double m_sink, const double d[3], double acc[3], double* slack)
@@ -679,11 +714,21 @@ static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, doub
     double k = P->G[a * P->D + b] * mu * f * radial;
     if (inside)
         for (unsigned x = 0; x < 3; ++x) acc[x] += k * d[x];
+    if (inside && P->corr) {
+        const uint64_t m = P->corr_n + 1;
+        double cr[3];
+        lattice_correction(P->corr + ((uint64_t)a * P->D + b) * m * m * m * 3, P->corr_n, P->corr_scale, d, cr);
+        const double gm = P->G[a * P->D + b] * mu;
+        for (unsigned x = 0; x < 3; ++x) acc[x] += gm * cr[x];
+    }
     if (tie) *slack += fabs(k) * sqrt(r2);
 }
 
-static void make_pair_ctx(pair_ctx* P, const orc_law* law, uint32_t D)
+static void make_pair_ctx(pair_ctx* P, const orc_law* law, uint32_t D, double box)
 {
+    P->corr = law->corr;
+    P->corr_n = law->corr_n;
+    P->corr_scale = law->corr ? (double)law->corr_n / (0.5 * box) : 0.0;
     P->G = law->G; P->tab = law->tables; P->ntab = law->ntab; P->grid = law->grid; P->D = D;
     P->rc = law->r_cut; P->rc2 = law->r_cut * law->r_cut; P->eps2 = law->eps * law->eps;
     P->eps_ab = law->eps_ab;
@@ -717,7 +762,7 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
     if (!t->M[0] && t->D) return -1;
     uint64_t ng = groups ? n_sub : t->ng;
     pair_ctx P;
-    make_pair_ctx(&P, law, t->D);
+    make_pair_ctx(&P, law, t->D, t->box);
     const double scale = t->box * TWO_M64;
     const uint64_t n = t->n;
     uint64_t pp = 0, pn = 0;
@@ -805,7 +850,7 @@ int orc_direct(uint64_t n, uint32_t D, double box, const uint64_t* X,
                const uint32_t* sinks, uint64_t n_sinks, double* acc, double* slack)
 {
     pair_ctx P;
-    make_pair_ctx(&P, law, D);
+    make_pair_ctx(&P, law, D, box);
     const double scale = box * TWO_M64;
     int64_t nc = (int64_t)floor(box / (law->r_cut * (1.0 + 1e-9)));
     if (nc > 1024) nc = 1024;

@@ -49,6 +49,10 @@ typedef struct {
     uint32_t opening;      /* ORC_OPEN_GEOMETRIC or ORC_OPEN_RELATIVE             */
     double alpha;          /* relative: the force-error tolerance, > 0            */
     const double* old_acc; /* relative: n previous |a| in input order             */
+    const double* corr;    /* lattice corrections (section 2.3), or NULL: D x D
+                              tables of (corr_n + 1)^3 x 3 on [0, box/2]^3; with
+                              them every pair interacts (no cut-off)              */
+    uint32_t corr_n;       /* intervals per axis of the correction tables        */
 } orc_law;
 
 enum { ORC_LAW_TABLE = 0, ORC_LAW_ACCUMULATOR = 1 };

@@ -31,6 +31,7 @@ __all__ = [
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
     "accumulator_problem", "yukawa_law", "exact_split_laws", "isolated_problem",
+    "newtonian_lattice_correction", "periodic_tree_problem",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -73,6 +74,8 @@ class Problem:
     periodic: bool = True
     # relative opening test: {"alpha": tolerance, "old_acc": (n,) previous |a|}, or None (geometric)
     relative: Optional[dict] = None
+    # pure-tree periodic mode: (D, D, n+1, n+1, n+1, 3) lattice correction tables, or None
+    lattice_corr: Optional[np.ndarray] = None
 
     @property
     def ntab(self) -> int:
@@ -411,3 +414,67 @@ def isolated_problem(n: int, D: int, seed: int, *, grid: str = GRID_R2, ntab: in
                    mass=np.full(n, 1.0 / n), G=G, tables=tables, grid=grid, r_s=0.0, r_cut=r_cut, eps=eps,
                    theta=theta, leaf_size=leaf_size, group_size=group_size, pos=np.ascontiguousarray(p.T), seed=seed,
                    periodic=False)
+
+
+def newtonian_lattice_correction(EN: int, box: float = 1.0, alpha: float = 2.0, nreal: int = 4,
+                                 kmax: int = 6) -> np.ndarray:
+    """The lattice correction of Newton's law in a periodic box (section 2.3:
+    the tables that correct the nearest-image force for every other image),
+    on (EN + 1)^3 points d in [0, box/2]^3, shape (EN + 1, EN + 1, EN + 1, 3):
+    the acceleration of a sink whose unit-mass source sits at offset d from
+    it (source - sink), summed over all periodic images with a neutralising
+    background by Ewald summation (splitting parameter alpha / box, real-space
+    images |n_i| <= nreal, wave vectors |m_i| <= kmax), minus the nearest
+    image's d / |d|^3. Zero at d = 0."""
+    L = float(box)
+    a = alpha / L
+    g = np.linspace(0.0, L / 2, EN + 1)
+    D = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1)       # (EN+1)^3 x 3
+    x = -D                                                             # sink - source
+    F = np.zeros_like(D)
+    rng_ = range(-nreal, nreal + 1)
+    for i in rng_:
+        for j in rng_:
+            for k in rng_:
+                r = x - L * np.array([i, j, k])
+                rr = np.linalg.norm(r, axis=-1)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    fac = (erfc(a * rr) + 2 * a * rr / math.sqrt(math.pi) * np.exp(-a * a * rr * rr)) / rr ** 3
+                fac = np.where(rr > 0, fac, 0.0)
+                F -= fac[..., None] * r
+    mr = range(-kmax, kmax + 1)
+    for i in mr:
+        for j in mr:
+            for k in mr:
+                if i == 0 and j == 0 and k == 0:
+                    continue
+                kv = 2 * math.pi / L * np.array([i, j, k], dtype=np.float64)
+                k2 = float(kv @ kv)
+                amp = 4 * math.pi / L ** 3 * math.exp(-k2 / (4 * a * a)) / k2
+                F -= amp * np.sin(x @ kv)[..., None] * kv
+    rr = np.linalg.norm(D, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        near = np.where(rr[..., None] > 0, D / rr[..., None] ** 3, 0.0)
+    out = F - near
+    out[0, 0, 0] = 0.0
+    return out
+
+
+def periodic_tree_problem(n: int, D: int, seed: int, *, EN: int = 32, ntab: int = 2048, theta: float = 0.5,
+                          leaf_size: int = 16, group_size: int = 64, box: float = 1.0) -> Problem:
+    """Pure-tree periodic mode with lattice corrections (section 2.3): a
+    clustered box, D species in equal shares, Newton for every pair with
+    random G in [0.5, 2] (the same correction table for every pair), tables
+    of ones on the r^2 grid out to r_cut = 0.9 box (past the farthest
+    nearest image, sqrt(3)/2 box), eps of 1/40 the mean spacing."""
+    rng = np.random.default_rng(seed)
+    pos = clustered_positions(n, box, rng, f_cl=0.6, halos=max(1, n // 400))
+    species = exact_species(n, np.ones(D), rng)
+    G = rng.uniform(0.5, 2.0, (D, D))
+    G = 0.5 * (G + G.T)
+    T = newtonian_lattice_correction(EN, box)
+    corr = np.broadcast_to(T, (D, D) + T.shape).copy()
+    return Problem(name=f"periodic-tree-{n}-D{D}-seed{seed}", n=n, D=D, box=box, species=species,
+                   mass=np.full(n, 1.0 / n), G=G, tables=np.ones((D, D, ntab)), grid=GRID_R2, r_s=0.0,
+                   r_cut=0.9 * box, eps=box / n ** (1.0 / 3.0) / 40.0, theta=theta, leaf_size=leaf_size,
+                   group_size=group_size, pos=pos, seed=seed, lattice_corr=corr)
