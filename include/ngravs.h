@@ -140,7 +140,7 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   grid     NGR_GRID_R or NGR_GRID_R2; f between samples is the straight
  *            line through the two neighbours, f = 0 for r >= r_cut
  *   r_s      split scale, used only when tables == NULL (> 0 then)
- *   r_cut    cut-off radius, 0 < r_cut < box / 2
+ *   r_cut    cut-off radius, 0 < r_cut < box / 2 (see lattice_corr)
  *   eps      Plummer softening, >= 0
  *   theta    opening angle, > 0
  *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice, 32)
@@ -176,6 +176,19 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   alpha    relative: the tolerance, finite and > 0
  *   old_acc  relative: device, n float64, the previous |a| of each particle
  *            in input order (read during the call)
+ *   lattice_corr  host, or NULL: pure-tree periodic mode (section 2.3). D x D
+ *            tables of (corr_n + 1)^3 x 3 float64, index ((ab (n+1) + i) (n+1)
+ *            + j) (n+1) + k, component last: on the grid d = (i, j, k) box /
+ *            (2 corr_n) in [0, box/2]^3, the acceleration a sink receives from
+ *            every image of a unit source at offset d (source - sink) other
+ *            than the nearest, per unit G_ab; odd in each component's own
+ *            axis, so it is read trilinearly at |d| with each component
+ *            signed by its axis. Every pair then interacts by its nearest
+ *            image (no cut-off: r_cut is the tables' range and must reach
+ *            sqrt(3)/2 box, the farthest nearest image) and adds G_ab mu
+ *            times the interpolated correction. Table laws only; periodic
+ *            trees only.
+ *   corr_n   intervals per axis of the correction tables, 1..512
  */
 typedef struct {
     const double* G;
@@ -194,6 +207,8 @@ typedef struct {
     uint32_t opening;
     double alpha;
     const double* old_acc;
+    const double* lattice_corr;
+    uint32_t corr_n;
 } ngr_force_params;
 
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the

@@ -47,7 +47,8 @@ class ForceParams(C.Structure):
     _fields_ = [("G", C.c_void_p), ("tables", C.c_void_p), ("ntab", C.c_uint32), ("grid", C.c_uint32),
                 ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
                 ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double),
-                ("eps_ab", C.c_void_p), ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p)]
+                ("eps_ab", C.c_void_p), ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p),
+                ("lattice_corr", C.c_void_p), ("corr_n", C.c_uint32)]
 
 
 class ForceStats(C.Structure):
@@ -214,11 +215,12 @@ LAW_TABLE, LAW_ACCUMULATOR = 0, 1
 
 
 def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=None, accumulator=None,
-                  eps_ab=None, relative=None):
+                  eps_ab=None, relative=None, lattice_corr=None):
     """accumulator: None for a table law, else {"cored": species indices,
     "beta": beta} for the accumulator laws; eps_ab: D x D per-pair softening
     or None; relative: None for the geometric opening test, else {"alpha":
-    alpha, "old_acc": device tensor of the previous |a| (n, float64)}."""
+    alpha, "old_acc": device tensor of the previous |a| (n, float64)};
+    lattice_corr: host (D, D, n+1, n+1, n+1, 3) correction tables or None."""
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
     if tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
@@ -238,19 +240,23 @@ def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=N
     if relative is not None:
         oa = relative["old_acc"]
         fp.opening, fp.alpha, fp.old_acc = 1, float(relative["alpha"]), _dev(oa)
-    fp._keep = (G, tables, ea, oa)
+    lc = None
+    if lattice_corr is not None:
+        lc = np.ascontiguousarray(lattice_corr, dtype=np.float64)
+        fp.lattice_corr, fp.corr_n = lc.ctypes.data, lc.shape[2] - 1
+    fp._keep = (G, tables, ea, oa, lc)
     return fp
 
 
 def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
                group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None,
-               eps_ab=None, relative=None):
+               eps_ab=None, relative=None, lattice_corr=None):
     """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
     G (D x D) and tables (D x D x ntab, or None) are host arrays;
     accumulator {"cored": [...], "beta": b} selects the accumulator laws.
     Returns the statistics as a dict (and per-group counts when asked)."""
     fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
-                       relative)
+                       relative, lattice_corr)
     st = ForceStats()
     if group_counts:
         ng = groups_count(ctx, tree, group_size)
@@ -386,12 +392,12 @@ class BatchBox:
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
                  leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
-                 accumulator=None, eps_ab=None, relative=None):
+                 accumulator=None, eps_ab=None, relative=None, lattice_corr=None):
         self.n = int(species.shape[0])
         self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
         self.tree = TreeParams(leaf_size)
         self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
-                                   relative)
+                                   relative, lattice_corr)
         self.acc = _dev(acc)
         self._keep = (species, mass, pos, lattice, acc)
 

@@ -148,7 +148,16 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     if ((uint64_t)D * fp->ntab > NGR_MAX_TABLE) fail(NGR_EINVAL, where + "D * ntab exceeds NGR_MAX_TABLE");
     if (fp->grid != NGR_GRID_R && fp->grid != NGR_GRID_R2) fail(NGR_EINVAL, where + "grid must be NGR_GRID_R or NGR_GRID_R2");
     if (!ngr::finite_pos(fp->r_cut)) fail(NGR_EINVAL, where + "r_cut must be finite and > 0");
-    if (!(fp->r_cut < 0.5 * box)) fail(NGR_EINVAL, where + "r_cut must be < box / 2");
+    if (fp->lattice_corr) {
+        if (!(fp->r_cut >= 0.8660254037844387 * box)) fail(NGR_EINVAL, where + "with lattice corrections r_cut must reach sqrt(3)/2 box");
+        if (fp->corr_n < 1 || fp->corr_n > 512) fail(NGR_EINVAL, where + "corr_n must be in 1..512");
+        if (fp->law != NGR_LAW_TABLE) fail(NGR_EINVAL, where + "lattice corrections take the table laws only");
+        const uint64_t m = fp->corr_n + 1ull, cnt = (uint64_t)D * D * m * m * m * 3ull;
+        for (uint64_t k = 0; k < cnt; ++k)
+            if (!std::isfinite(fp->lattice_corr[k])) fail(NGR_EINVAL, where + "a lattice correction is not finite");
+    } else if (!(fp->r_cut < 0.5 * box)) {
+        fail(NGR_EINVAL, where + "r_cut must be < box / 2");
+    }
     if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, where + "eps must be finite and >= 0");
     if (!ngr::finite_pos(fp->theta)) fail(NGR_EINVAL, where + "theta must be finite and > 0");
     if (!fp->tables && !ngr::finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
@@ -253,6 +262,7 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         using ngr::fail;
         if (!tree) fail(NGR_EINVAL, "tree is NULL");
         if (!tree->has_monopoles) fail(NGR_ESTATE, "ngr_compute_monopoles must precede ngr_tree_force");
+        if (fp && fp->lattice_corr && tree->region > 0.0) fail(NGR_EINVAL, "lattice corrections need a periodic tree");
         uint32_t gs = ngr::check_force_params(tree->D, tree->box, fp, "");
         if (!gs) gs = ngr::chosen_group_size(tree->n, tree->D);
         if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
@@ -521,6 +531,8 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
         for (uint32_t k = 0; k < nbox; ++k) {
             const std::string where = "box " + std::to_string(k) + ": ";
             ngr::check_particles(&boxes[k].particles, &boxes[k].tree, where, in[k]);
+            if (boxes[k].force.lattice_corr && in[k].region > 0.0)
+                ngr::fail(NGR_EINVAL, where + "lattice corrections need a periodic box");
             gs[k] = ngr::check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
             if (!gs[k]) gs[k] = ngr::chosen_group_size(in[k].n, in[k].D);
             if (!boxes[k].acc && in[k].n) fail(NGR_EINVAL, where + "acc is NULL");

@@ -199,6 +199,8 @@ struct Law {
     uint32_t opening = NGR_OPEN_GEOMETRIC;
     double alpha = 0;
     const double* old_acc = nullptr;  // device, previous |a| of the box's particles (relative test)
+    const double* corr = nullptr;     // host, lattice correction tables (pure-tree periodic mode), or NULL
+    uint32_t corr_n = 0;
 };
 void make_law(const ngr_force_params& fp, uint32_t D, Law& law);
 

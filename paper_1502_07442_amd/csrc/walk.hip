@@ -257,6 +257,9 @@ struct BoxParams {
     const double* old_acc;     // relative opening test: previous |a| of the box's particles (input order)
     double rel_k;              // relative opening test: alpha (box / 2^21)^2
     uint32_t relative;         // 1: the relative opening test, 0: the geometric one
+    const double* corr;        // lattice corrections (pure-tree periodic mode): D x D tables, or NULL
+    uint32_t corr_n;           // their intervals per axis
+    double corr_scale;         // corr_n / (box / 2)
     double eps2_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // per-pair eps^2, row a = sink species
     float toff_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];    // r^2-grid table offset -eps_ab^2 / h of each pair
 };
@@ -325,10 +328,44 @@ __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfir
 // Pair terms of this lane's sink with LDS records of one source species:
 // records rec[0], rec[K], rec[2K], ... (iters of them; the caller offsets rec
 // by the lane's replica).
-template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K>
+// Lattice correction of one pair (pure-tree periodic mode, section 2.3):
+// the table T holds, on n intervals per axis of [0, box/2]^3, the extra
+// acceleration from every image of a unit source but the nearest; odd in
+// each component's own axis, even in the others, so it is read trilinearly
+// at |d| and each component takes the sign of its axis.
+__device__ inline void lattice_correction(const double* __restrict__ T, uint32_t n, double scale, double dx,
+                                          double dy, double dz, double& cx, double& cy, double& cz)
+{
+    const double u0 = fabs(dx) * scale, u1 = fabs(dy) * scale, u2 = fabs(dz) * scale;
+    const uint32_t i0 = min((uint32_t)u0, n - 1u), i1 = min((uint32_t)u1, n - 1u), i2 = min((uint32_t)u2, n - 1u);
+    const double f0 = u0 - i0, f1 = u1 - i1, f2 = u2 - i2;
+    const uint64_t m = n + 1u;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t a = c >> 2, b = (c >> 1) & 1, d = c & 1;
+        const double w = (a ? f0 : 1.0 - f0) * (b ? f1 : 1.0 - f1) * (d ? f2 : 1.0 - f2);
+        const double* e = T + (((uint64_t)(i0 + a) * m + (i1 + b)) * m + (i2 + d)) * 3;
+        sx = fma(w, e[0], sx);
+        sy = fma(w, e[1], sy);
+        sz = fma(w, e[2], sz);
+    }
+    cx = dx < 0.0 ? -sx : sx;
+    cy = dy < 0.0 ? -sy : sy;
+    cz = dz < 0.0 ? -sz : sz;
+}
+
+// Lattice corrections for the pair term (EW): table, intervals and scale.
+struct LatticeCorr {
+    const double* T;
+    uint32_t n;
+    double scale;
+};
+
+template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K, bool EW = false>
 __device__ inline void eval_records(const PairParams& A, double eps2, float toff, const double4* __restrict__ rec,
                                     uint32_t iters, const void* __restrict__ tbv, double ox, double oy, double oz,
-                                    double& ax, double& ay, double& az)
+                                    double& ax, double& ay, double& az, LatticeCorr lc = LatticeCorr{nullptr, 0u, 0.0})
 {
     const float tscale = A.tscale, tmax = A.tmax;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
@@ -371,6 +408,15 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
         az = fma(coef, dz, az);
+        if (EW) {
+            // the records carry 1.5 G m
+            double cx, cy, cz;
+            lattice_correction(lc.T, lc.n, lc.scale, dx, dy, dz, cx, cy, cz);
+            const double gm = s.w * (2.0 / 3.0);
+            ax = fma(gm, cx, ax);
+            ay = fma(gm, cy, ay);
+            az = fma(gm, cz, az);
+        }
     }
 }
 
@@ -447,7 +493,7 @@ __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t n
     return (raw + 255u) & ~255u;
 }
 
-template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC>
+template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC, bool EW = false>
 __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
     HIP_DYNAMIC_SHARED(unsigned char, smem);
@@ -529,6 +575,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             hi[k] = A.ghi[k * A.ng + g];
             wrap |= (hi[k] - lo[k]) > wrap_limit;
         }
+        wrap = wrap || EW;                // every pair needs its nearest image there
         // group centre: lattice units and box fraction
         const uint64_t C0 = (uint64_t)(lo[0] + hi[0]) << 43, C1 = (uint64_t)(lo[1] + hi[1]) << 43,
                        C2 = (uint64_t)(lo[2] + hi[2]) << 43;
@@ -581,6 +628,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
                 else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
                 else eval_cored<GRID, TAB, false, 4>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                return;
+            }
+            if (EW && P.corr) {
+                const uint64_t m = P.corr_n + 1u;
+                const LatticeCorr lc{P.corr + (uint64_t)(a * Dk + b) * m * m * m * 3u, P.corr_n, P.corr_scale};
+                eval_records<GRID, TAB, EPS0, true, 1, true>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, lc);
                 return;
             }
             if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az);
@@ -1019,6 +1072,8 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.cored = fp.law == NGR_LAW_ACCUMULATOR ? fp.cored : 0u;
     law.beta = fp.beta;
     law.track = 1;
+    law.corr = fp.lattice_corr;
+    law.corr_n = fp.corr_n;
     law.opening = fp.opening;
     law.alpha = fp.alpha;
     law.old_acc = fp.old_acc;
@@ -1182,9 +1237,33 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     out.box_pn.assign(nbox, 0);
     if (t.n == 0 || g.ng == 0) return;
     const uint32_t grid = laws[0].grid;
-    bool eps0 = false, acc_law = false;
-    for (uint32_t k = 0; k < nbox; ++k) acc_law |= laws[k].kind == NGR_LAW_ACCUMULATOR;
+    bool eps0 = false, acc_law = false, ew = false;
+    for (uint32_t k = 0; k < nbox; ++k) {
+        acc_law |= laws[k].kind == NGR_LAW_ACCUMULATOR;
+        ew |= laws[k].corr != nullptr;
+    }
+    if (acc_law && ew) fail(NGR_EINVAL, "lattice corrections take the table laws only");
     if (acc_law) upload_core_table(ctx);
+    // lattice correction tables of every box that has them, one block
+    std::vector<uint64_t> corr_off(nbox, 0);
+    double* corr_dev = nullptr;
+    if (ew) {
+        uint64_t total = 0;
+        for (uint32_t k = 0; k < nbox; ++k) {
+            corr_off[k] = total;
+            if (laws[k].corr) {
+                const uint64_t m = laws[k].corr_n + 1ull;
+                total += (uint64_t)laws[k].D * laws[k].D * m * m * m * 3ull;
+            }
+        }
+        corr_dev = static_cast<double*>(ctx.alloc(total * sizeof(double)));
+        for (uint32_t k = 0; k < nbox; ++k)
+            if (laws[k].corr) {
+                const uint64_t m = laws[k].corr_n + 1ull;
+                ctx.to_device(corr_dev + corr_off[k], laws[k].corr,
+                              (uint64_t)laws[k].D * laws[k].D * m * m * m * 3ull * sizeof(double));
+            }
+    }
     uint32_t pair_max = 0, value_max = 0;
     for (uint32_t k = 0; k < nbox; ++k) {
         if (laws[k].grid != grid) fail(NGR_EINVAL, "the boxes of one call must share the table grid");
@@ -1222,7 +1301,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         P.inv_box = 1.0 / box;
         P.eps2 = law.eps * law.eps;
         const double q = law.r_cut / box * 2097152.0;   // r_cut in half key units
-        P.R2 = q * q;
+        P.R2 = law.corr ? __builtin_inf() : q * q;      // with lattice corrections every pair interacts
         P.theta2 = law.theta * law.theta;
         const double wl = std::floor(1048576.0 * (1.0 - 2.0 * law.r_cut / box)) - 1.0;
         P.wrap_limit = wl < 0.0 ? 0u : (uint32_t)wl;
@@ -1252,6 +1331,11 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             P.inv4pib = 1.0 / (4.0 * M_PI * law.beta);
         }
         P.track = law.track;
+        if (law.corr) {
+            P.corr = corr_dev + corr_off[k];
+            P.corr_n = law.corr_n;
+            P.corr_scale = (double)law.corr_n / (0.5 * box);
+        }
         if (law.opening == NGR_OPEN_RELATIVE) {
             const double u = box / 2097152.0;   // one half key unit
             P.relative = 1;
@@ -1341,9 +1425,17 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     };
     // a one-box call reads its box's parameters from the kernel arguments;
     // the accumulator laws read them from the table in device memory
-    const int sel = (acc_law ? 16 : nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) + (mode == kValue ? 2 : 0) +
-                    (eps0 ? 1 : 0);
+    const int sel = (ew ? 24 : acc_law ? 16 : nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) +
+                    (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
     switch (sel) {
+    case 24: launch(walk_kernel<NGR_GRID_R, kPair, false, false, false, true>); break;
+    case 25: launch(walk_kernel<NGR_GRID_R, kPair, true, false, false, true>); break;
+    case 26: launch(walk_kernel<NGR_GRID_R, kValue, false, false, false, true>); break;
+    case 27: launch(walk_kernel<NGR_GRID_R, kValue, true, false, false, true>); break;
+    case 28: launch(walk_kernel<NGR_GRID_R2, kPair, false, false, false, true>); break;
+    case 29: launch(walk_kernel<NGR_GRID_R2, kPair, true, false, false, true>); break;
+    case 30: launch(walk_kernel<NGR_GRID_R2, kValue, false, false, false, true>); break;
+    case 31: launch(walk_kernel<NGR_GRID_R2, kValue, true, false, false, true>); break;
     case 0: launch(walk_kernel<NGR_GRID_R, kPair, false, false, false>); break;
     case 1: launch(walk_kernel<NGR_GRID_R, kPair, true, false, false>); break;
     case 2: launch(walk_kernel<NGR_GRID_R, kValue, false, false, false>); break;
@@ -1378,6 +1470,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     ctx.release(order);
     ctx.release(ctl);
     ctx.release(boxes);
+    if (corr_dev) ctx.release(corr_dev);
     float ms_order = 0.0f, ms = 0.0f;
     HIP_CHECK(hipEventElapsedTime(&ms_order, e0, e1));
     HIP_CHECK(hipEventElapsedTime(&ms, e1, e2));

@@ -35,7 +35,7 @@ def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None, trac
     res = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
                          theta=p.theta, r_s=p.r_s, group_size=gs, acc=acc, group_counts=group_counts,
                          accumulator=getattr(p, "accumulator", None), eps_ab=getattr(p, "eps_ab", None),
-                         relative=rel)
+                         relative=rel, lattice_corr=getattr(p, "lattice_corr", None))
     st, gc = (res if group_counts else (res, None))
     out = acc.cpu().numpy()
     if not keep_tree:
