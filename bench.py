@@ -53,7 +53,9 @@ def batched(ngr, synth, nbox=256, reps=3):
     """The many-box workload: nbox independent boxes in one
     ngr_batch_build_force call (group size chosen by the library), against
     the same boxes looped box by box through the single-box calls on the same
-    stream. Inputs are resident before timing; each call includes the build."""
+    stream; then the autotuner on the same boxes and the batch at the sizes
+    it chose. Inputs are resident before timing; each call includes the
+    build."""
     import numpy as np
     import torch
     probs = [synth.batch_box(k) for k in range(nbox)]
@@ -91,13 +93,46 @@ def batched(ngr, synth, nbox=256, reps=3):
     loop()
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
+    # the autotuner on the same boxes, then the batch at its sizes
+    tune = ngr.autotune(ctx, boxes)
+    ngr.batch_build_force(ctx, boxes)               # warm-up
+    ttimes = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stt, pbt = ngr.batch_build_force(ctx, boxes, per_box=True)
+        torch.cuda.synchronize()
+        ttimes.append(time.perf_counter() - t0)
+    t_tuned = float(np.median(ttimes))
+    sizes = {g: sum(1 for b in pbt if b["group_size"] == g) for g in (16, 32, 64)}
+    # the default size again, after the tuned runs (same context)
+    for b in boxes:
+        b.force.group_size = 32
+    dtimes = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        std = ngr.batch_build_force(ctx, boxes)
+        torch.cuda.synchronize()
+        dtimes.append(time.perf_counter() - t0)
+    for b in boxes:
+        b.force.group_size = 0
+    t_default_after = float(np.median(dtimes))
     ctx.close()
     return {"workload": f"{nbox} clustered boxes: n log-uniform in [2^12, 2^18], D in 1..4, clustered fraction "
                         f"in [0, 0.8], laws of their own", "n_boxes": nbox, "n_particles": st["n_particles"],
             "interactions": inter, "ms_per_batch": t_batch * 1e3, "boxes_per_s": nbox / t_batch,
             "interactions_per_s": inter / t_batch, "walk_ms": st["ms_walk"], "build_ms": st["ms_build"],
             "loop_ms": t_loop * 1e3, "loop_boxes_per_s": nbox / t_loop, "speedup_vs_loop": t_loop / t_batch,
-            "group_size": "library choice (32)"}
+            "group_size": "library default (32)",
+            "tuned": {"tune_ms": tune["ms"], "classes": tune["classes"], "ms_per_batch": t_tuned * 1e3,
+                      "boxes_per_s": nbox / t_tuned, "walk_ms": stt["ms_walk"],
+                      "interactions": stt["interactions_pp"] + stt["interactions_pn"],
+                      "boxes_by_group_size": sizes, "speedup_vs_loop": t_loop / t_tuned,
+                      "build_ms": stt["ms_build"], "groups_ms": stt["ms_groups"],
+                      "default_again_ms_per_batch": t_default_after * 1e3, "default_again_groups_ms": std["ms_groups"],
+                      "default_again_walk_ms": std["ms_walk"]},
+            "groups_ms": st["ms_groups"]}
 
 
 def served(ngr, synth, nreq=200, warm=25, steps=8, dt=1e-3, loads=(0.5, 0.9)):

@@ -143,7 +143,8 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *   r_cut    cut-off radius, 0 < r_cut < box / 2 (see lattice_corr)
  *   eps      Plummer softening, >= 0
  *   theta    opening angle, > 0
- *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice, 32)
+ *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice: 32, or
+ *            what ngr_autotune chose for the box's class on this context)
  *   law      NGR_LAW_TABLE (0), or NGR_LAW_ACCUMULATOR: the accumulator
  *            laws of section 3.3. A pair in which neither species is cored
  *            keeps the law above. Otherwise the Newtonian factor
@@ -448,6 +449,32 @@ typedef struct {
  */
 ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes,
                                  ngr_batch_stats* st, ngr_force_stats* per_box);
+
+/*
+ * Group-size autotuner. Boxes are sorted into classes by D and floor(log2 n).
+ * For each class present, up to two boxes of that class, repeated until they
+ * hold 2^21 particles (enough groups to fill the device, so that a class's
+ * throughput is measured and not one group's latency), are built together
+ * once. Their groups and walk are timed (wall clock, the better of two runs)
+ * at group sizes 16, 32 and 64. The context keeps the fastest size per
+ * class; afterwards group_size = 0 in any call on this context
+ * (ngr_tree_force, ngr_batch_build_force, the server) resolves to it.
+ * Classes never tuned keep the default, 32. Results of later calls depend on
+ * the sizes chosen (the group size shapes the interaction lists), each
+ * within the force tolerance; per-box statistics report the size used.
+ * Inputs as for ngr_batch_build_force (acc is not written). st may be NULL.
+ */
+typedef struct {
+    uint32_t classes;       /* classes tuned by this call                     */
+    uint32_t launches;      /* walk launches timed                            */
+    double ms;              /* wall time of the call                          */
+} ngr_tune_stats;
+
+ngr_status ngr_autotune(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes, ngr_tune_stats* st);
+
+/* The group size that group_size = 0 resolves to for a box of n particles
+ * and D species on this context. */
+ngr_status ngr_tuned_group_size(const ngr_context* ctx, uint64_t n, uint32_t D, uint32_t* group_size);
 
 /* ---- served requests ---- */
 

@@ -25,7 +25,8 @@ EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_
             "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
             "ngr_batch_build_force", "ngr_server_create", "ngr_server_submit", "ngr_server_tick",
             "ngr_server_status", "ngr_server_take", "ngr_server_destroy", "ngr_short_range_grid",
-            "ngr_short_range_tables", "ngr_pm_create", "ngr_pm_force", "ngr_pm_destroy"]
+            "ngr_short_range_tables", "ngr_pm_create", "ngr_pm_force", "ngr_pm_destroy", "ngr_autotune",
+            "ngr_tuned_group_size"]
 
 
 class NgravsError(RuntimeError):
@@ -67,6 +68,32 @@ class Box(C.Structure):
 class RequestDesc(C.Structure):
     _fields_ = [("particles", Particles), ("vel", C.c_void_p), ("tree", TreeParams), ("force", ForceParams),
                 ("dt", C.c_double), ("steps", C.c_uint32)]
+
+
+class TuneStats(C.Structure):
+    _fields_ = [("classes", C.c_uint32), ("launches", C.c_uint32), ("ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def autotune(ctx: Context, boxes) -> dict:
+    """ngr_autotune over a list of BatchBox: afterwards group_size = 0
+    resolves to the fastest measured size of each box's class."""
+    arr = (Box * len(boxes))()
+    for k, b in enumerate(boxes):
+        arr[k] = Box(b.particles, b.tree, b.force, b.acc)
+    st = TuneStats()
+    ctx._check(lib().ngr_autotune(ctx.handle, len(boxes), arr, C.byref(st)), "autotune")
+    return st.as_dict()
+
+
+def tuned_group_size(ctx: Context, n: int, D: int) -> int:
+    gs = C.c_uint32()
+    rc = lib().ngr_tuned_group_size(ctx.handle, int(n), int(D), C.byref(gs))
+    if rc != 0:
+        raise NgravsError(rc, "tuned_group_size: bad arguments")
+    return gs.value
 
 
 class ServerParams(C.Structure):
@@ -127,6 +154,8 @@ def lib():
             "ngr_pm_create": (i32, [P, P, P, P, P]),
             "ngr_pm_force": (i32, [P, P, P, P, C.c_int, P]),
             "ngr_pm_destroy": (i32, [P, P]),
+            "ngr_autotune": (i32, [P, u32, P, P]),
+            "ngr_tuned_group_size": (i32, [P, u64, u32, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

@@ -187,15 +187,24 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     return gs;
 }
 
-// Group size of a box when the caller leaves it to the library (0). With
-// groups of at most 32 (16) sinks evaluating 2 (4) records per lane slot,
-// 32 gave the shortest walk on the many-box workload (256 clustered boxes of
-// 2^12..2^18 particles, D 1..4: walk 41 ms at 32 against 45 ms at 16 and 64).
-uint32_t chosen_group_size(uint64_t n, uint32_t D)
+// The autotuner's class of a box: its D and floor(log2 n).
+uint64_t size_class(uint64_t n, uint32_t D)
 {
-    (void)n;
-    (void)D;
-    return 32;
+    uint32_t l = 0;
+    while (l < 63 && (2ull << l) <= n) ++l;
+    return ((uint64_t)D << 8) | l;
+}
+
+// Group size of a box when the caller leaves it to the library (0): what
+// ngr_autotune measured fastest for the box's class on this context, else
+// 32. With groups of at most 32 (16) sinks evaluating 2 (4) records per lane
+// slot, 32 gave the shortest walk on the many-box workload (256 clustered
+// boxes of 2^12..2^18 particles, D 1..4: walk 41 ms at 32 against 45 ms at
+// 16 and 64).
+uint32_t chosen_group_size(const Context& ctx, uint64_t n, uint32_t D)
+{
+    auto it = ctx.tuned.find(size_class(n, D));
+    return it == ctx.tuned.end() ? 32u : it->second;
 }
 
 void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const std::string& where, ngr::BoxIn& b)
@@ -264,7 +273,7 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
         if (!tree->has_monopoles) fail(NGR_ESTATE, "ngr_compute_monopoles must precede ngr_tree_force");
         if (fp && fp->lattice_corr && tree->region > 0.0) fail(NGR_EINVAL, "lattice corrections need a periodic tree");
         uint32_t gs = ngr::check_force_params(tree->D, tree->box, fp, "");
-        if (!gs) gs = ngr::chosen_group_size(tree->n, tree->D);
+        if (!gs) gs = ngr::chosen_group_size(*ctx, tree->n, tree->D);
         if (!acc && tree->n) fail(NGR_EINVAL, "acc is NULL");
         ngr::Context& c = *ctx;
         ngr::Groups g;
@@ -493,7 +502,7 @@ NGR_API ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree, uin
 {
     return guarded(ctx, [&] {
         if (!tree || !n_groups) ngr::fail(NGR_EINVAL, "tree or n_groups is NULL");
-        uint32_t gs = group_size ? group_size : ngr::chosen_group_size(tree->n, tree->D);
+        uint32_t gs = group_size ? group_size : ngr::chosen_group_size(*ctx, tree->n, tree->D);
         if (gs != 16 && gs != 32 && gs != 64) ngr::fail(NGR_EINVAL, "group_size must be 16, 32 or 64 (or 0)");
         ngr::Groups g;
         try {
@@ -534,7 +543,7 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
             if (boxes[k].force.lattice_corr && in[k].region > 0.0)
                 ngr::fail(NGR_EINVAL, where + "lattice corrections need a periodic box");
             gs[k] = ngr::check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
-            if (!gs[k]) gs[k] = ngr::chosen_group_size(in[k].n, in[k].D);
+            if (!gs[k]) gs[k] = ngr::chosen_group_size(*ctx, in[k].n, in[k].D);
             if (!boxes[k].acc && in[k].n) fail(NGR_EINVAL, where + "acc is NULL");
             if (boxes[k].force.grid != boxes[0].force.grid) fail(NGR_EINVAL, where + "the boxes must share the table grid");
             acc[k] = boxes[k].acc;
@@ -642,6 +651,110 @@ NGR_API ngr_status ngr_short_range_tables(ngr_context* ctx, const ngr_short_para
             if (!std::isfinite(f_full[k])) fail(NGR_EINVAL, "f_full has a non-finite entry");
         ngr::short_range_tables(*ctx, *sp, phibar, f_full, tables);
     });
+}
+
+NGR_API ngr_status ngr_autotune(ngr_context* ctx, uint32_t nbox, const ngr_box* boxes, ngr_tune_stats* st)
+{
+    return guarded(ctx, [&] {
+        using ngr::fail;
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!boxes) fail(NGR_EINVAL, "boxes is NULL");
+        if (nbox == 0 || nbox > 65535) fail(NGR_EINVAL, "nbox must be in 1..65535");
+        std::vector<ngr::BoxIn> in(nbox);
+        for (uint32_t k = 0; k < nbox; ++k) {
+            const std::string where = "box " + std::to_string(k) + ": ";
+            ngr::check_particles(&boxes[k].particles, &boxes[k].tree, where, in[k]);
+            if (boxes[k].force.lattice_corr && in[k].region > 0.0)
+                fail(NGR_EINVAL, where + "lattice corrections need a periodic box");
+            (void)ngr::check_force_params(in[k].D, in[k].box, &boxes[k].force, where);
+            if (boxes[k].force.grid != boxes[0].force.grid) fail(NGR_EINVAL, where + "the boxes must share the table grid");
+        }
+        // up to two boxes of each class (D, floor(log2 n)), in input order
+        std::map<uint64_t, std::vector<uint32_t>> cls;
+        for (uint32_t k = 0; k < nbox; ++k) {
+            if (in[k].n == 0) continue;
+            auto& v = cls[ngr::size_class(in[k].n, in[k].D)];
+            if (v.size() < 2) v.push_back(k);
+        }
+        ngr::Context& c = *ctx;
+        uint32_t launches = 0;
+        const uint32_t cand[3] = {16, 32, 64};
+        for (auto& kv : cls) {
+            // the class's samples, repeated until they hold 2^21 particles:
+            // enough groups to fill the device, so that the time measured is
+            // the class's throughput in a batch and not one group's latency
+            std::vector<ngr::BoxIn> sub;
+            std::vector<ngr::Law> laws;
+            std::vector<double*> accs;
+            std::vector<double*> scratch;
+            uint64_t held = 0;
+            for (uint32_t rep = 0; held < (1ull << 21) && sub.size() < 4096; ++rep)
+                for (uint32_t k : kv.second) {
+                    sub.push_back(in[k]);
+                    laws.emplace_back();
+                    ngr::make_law(boxes[k].force, in[k].D, laws.back());
+                    double* a = static_cast<double*>(c.alloc(3 * in[k].n * sizeof(double)));
+                    scratch.push_back(a);
+                    accs.push_back(a);
+                    held += in[k].n;
+                }
+            ngr::Tree t;
+            std::vector<ngr::LawTables> tabs;
+            void* tab_block = nullptr;
+            double best = 0.0;
+            uint32_t best_gs = 32;
+            try {
+                ngr::build_forest(c, sub, t);
+                ngr::compute_monopoles(c, t);
+                tab_block = ngr::upload_tables(c, laws, tabs);
+                for (uint32_t gi = 0; gi < 3; ++gi) {
+                    // the groups and the walk (both grow with the group count), the better of two runs
+                    double ms = 0.0;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        c.sync();
+                        const auto w0 = std::chrono::steady_clock::now();
+                        ngr::Groups g;
+                        ngr::WalkOut wo;
+                        ngr::make_groups(c, t, std::vector<uint32_t>(sub.size(), cand[gi]), g);
+                        ngr::walk_force(c, t, g, laws, tabs, accs, nullptr, wo);
+                        c.sync();
+                        const double e = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+                        g.free(c);
+                        ms = rep == 0 ? e : std::min(ms, e);
+                        ++launches;
+                    }
+                    if (gi == 0 || ms < best) {
+                        best = ms;
+                        best_gs = cand[gi];
+                    }
+                }
+            } catch (...) {
+                try {
+                    ngr::free_tree(c, t);
+                    c.release(tab_block);
+                    for (double* a : scratch) c.release(a);
+                } catch (...) {
+                }
+                throw;
+            }
+            ngr::free_tree(c, t);
+            c.release(tab_block);
+            for (double* a : scratch) c.release(a);
+            c.tuned[kv.first] = best_gs;
+        }
+        if (st) {
+            st->classes = (uint32_t)cls.size();
+            st->launches = launches;
+            st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    });
+}
+
+NGR_API ngr_status ngr_tuned_group_size(const ngr_context* ctx, uint64_t n, uint32_t D, uint32_t* group_size)
+{
+    if (!ctx || !group_size || D < 1 || D > NGR_MAX_SPECIES) return NGR_EINVAL;
+    *group_size = ngr::chosen_group_size(*ctx, n, D);
+    return NGR_OK;
 }
 
 NGR_API ngr_status ngr_pm_create(ngr_context* ctx, const ngr_pm_params* pp, const double* G, const double* phibar,

@@ -56,6 +56,7 @@ struct Context {
     DevMem stacks;          // per-wave traversal stacks of the walk
     DevMem counters;        // small device counters (queues, statistics, flags)
     DevMem core;            // core-factor table of the accumulator laws (built on first use)
+    std::map<uint64_t, uint32_t> tuned;           // group size per class (D << 8 | floor(log2 n))
     uint64_t* pinned = nullptr;                   // pinned host staging, kPinnedWords
     static constexpr size_t kPinnedWords = 64;
 
@@ -141,7 +142,8 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
 // Check one box's force parameters; returns group_size (0: caller's choice).
 uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, const std::string& where);
 // The group size used when the caller passes 0.
-uint32_t chosen_group_size(uint64_t n, uint32_t D);
+uint32_t chosen_group_size(const Context& ctx, uint64_t n, uint32_t D);
+uint64_t size_class(uint64_t n, uint32_t D);
 
 // ---- device scan (scan.hip) ----
 // Exclusive prefix sum of n uint32 values; out may alias in. If total is

@@ -90,7 +90,8 @@ __global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const dou
 // of N^3 points (index (x N + y) N + z). A workgroup transforms T lines:
 // line l of the batch starts at line_base(l) and its elements are `stride`
 // apart. Radix-2 decimation in frequency in place in LDS, natural order in,
-// bit-reversed order read out. sign = -1 forward, +1 inverse (unnormalised).
+// bit-reversed order read out. sign = +1: exp(-2 pi i k n / N) (forward),
+// -1: exp(+2 pi i k n / N) (inverse, unnormalised).
 // The LDS holds T lines of N points and the N / 2 twiddles.
 // axis 0: lines along z (stride 1), the T lines of a tile N apart;
 // axis 1: along y (stride N), a tile's lines adjacent in z;
@@ -108,11 +109,19 @@ __device__ inline uint32_t lds_swizzle(uint32_t i)
 // lines in LDS. Those stages (halves h, h/2, ...) only mix the 2^F points
 // first + m d of a block of 2h, d = h >> (F-1), so each thread loads such a
 // set into registers, applies the F stages and stores it back.
+// Twiddles: the pair (m, m + span) of stage st takes W^((off + j d) 2^(s+st))
+// with j = m mod span, off the set's position below d and W the twiddle of
+// one index; since d 2^(s+st) = N 2^st / 2^F, that is w0^(2^st) times the
+// 2^F-th root of unity of order j 2^st, with w0 = W^(off 2^s): one table
+// read per set, two squarings, and roots of unity that are constants.
 template <int F>
-__device__ inline void fft_stages(double2* __restrict__ sm, const double2* __restrict__ tw, uint32_t N, uint32_t p,
-                                  uint32_t T, uint32_t s)
+__device__ inline void fft_stages(double2* __restrict__ sm, const double2* __restrict__ tw, double sign, uint32_t N,
+                                  uint32_t p, uint32_t T, uint32_t s)
 {
     constexpr uint32_t M = 1u << F;
+    // cos and sin of 2 pi q / 8, q = 0 .. 3
+    constexpr double kC[4] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440};
+    constexpr double kS[4] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440};
     const uint32_t logh = p - s - 1, logd = logh - (F - 1);
     const uint32_t h = 1u << logh, d = 1u << logd;
     const uint32_t logsets = p - F;       // sets per line: N / M
@@ -124,18 +133,22 @@ __device__ inline void fft_stages(double2* __restrict__ sm, const double2* __res
         double2 v[M];
 #pragma unroll
         for (uint32_t m = 0; m < M; ++m) v[m] = sm[lds_swizzle(l * N + first + m * d)];
+        double2 w[F];                               // w0^(2^st)
+        w[0] = tw[off << s];
+#pragma unroll
+        for (int st = 1; st < F; ++st) w[st] = cmul(w[st - 1], w[st - 1]);
 #pragma unroll
         for (uint32_t st = 0; st < (uint32_t)F; ++st) {
             const uint32_t span = M >> (st + 1);          // partner distance in m
-            const uint32_t hh = h >> st;                   // the stage's half
-            const uint32_t twshift = s + st;               // twiddle index = pos * 2^(s+st)
 #pragma unroll
             for (uint32_t m = 0; m < M; ++m) {
                 if (m & span) continue;
-                const uint32_t pos = (first + m * d) & (hh - 1u);
+                const uint32_t q = ((m & (span - 1u)) << st) * (8u / M);   // root angle in 2 pi / 8
+                double2 t = w[st];
+                if (q) t = cmul(t, make_double2(kC[q], -sign * kS[q]));
                 const double2 a = v[m], b = v[m + span];
                 v[m] = cadd(a, b);
-                v[m + span] = cmul(csub(a, b), tw[pos << twshift]);
+                v[m + span] = cmul(csub(a, b), t);
             }
         }
 #pragma unroll
@@ -148,7 +161,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ d
                                                          double sign)
 {
     HIP_DYNAMIC_SHARED(double2, sm);
-    double2* tw = sm + (size_t)T * N;     // N / 2 twiddles, conjugated for the inverse
+    double2* tw = sm + (size_t)T * N;     // N / 2 twiddles, conjugated for the inverse (sign -1)
     const uint64_t N2 = (uint64_t)N * N, N3 = N2 * N;
     const uint64_t tiles_per_mesh = N2 >> logT;
     const uint64_t tile = blockIdx.x % tiles_per_mesh, g = blockIdx.x / tiles_per_mesh;
@@ -182,9 +195,9 @@ __global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ d
     // registers (fft_stages); a barrier between passes.
     for (uint32_t s = 0; s < p;) {
         const uint32_t f = min(3u, p - s);
-        if (f == 3) fft_stages<3>(sm, tw, N, p, T, s);
-        else if (f == 2) fft_stages<2>(sm, tw, N, p, T, s);
-        else fft_stages<1>(sm, tw, N, p, T, s);
+        if (f == 3) fft_stages<3>(sm, tw, sign, N, p, T, s);
+        else if (f == 2) fft_stages<2>(sm, tw, sign, N, p, T, s);
+        else fft_stages<1>(sm, tw, sign, N, p, T, s);
         __syncthreads();
         s += f;
     }
@@ -446,7 +459,7 @@ void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumula
         LAUNCH_CHECK("pm_deposit");
     }
     HIP_CHECK(hipEventRecord(ev[1], ctx.stream));
-    fft3(ctx, pl, ngrid, -1.0);
+    fft3(ctx, pl, ngrid, 1.0);
     HIP_CHECK(hipEventRecord(ev[2], ctx.stream));
     PairMix mix{};
     for (uint32_t ab = 0; ab < D * D; ++ab) {
@@ -464,7 +477,7 @@ void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumula
     }
     LAUNCH_CHECK("pm_green");
     HIP_CHECK(hipEventRecord(ev[3], ctx.stream));
-    fft3(ctx, pl, ngrid, 1.0);
+    fft3(ctx, pl, ngrid, -1.0);
     HIP_CHECK(hipEventRecord(ev[4], ctx.stream));
     if (n) {
         hipLaunchKernelGGL(pm_interp, dim3(gx, D), dim3(256), 0, ctx.stream, n, t.X, t.perm, seg, N, pl.p, 1.0 / h,

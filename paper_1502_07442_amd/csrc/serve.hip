@@ -155,7 +155,7 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
         uint32_t gs = check_force_params(r->in.D, r->in.box, &rq->force, "");
         if (rq->force.lattice_corr || rq->force.opening != NGR_OPEN_GEOMETRIC)
             fail(NGR_EINVAL, "the server takes the geometric opening test without lattice corrections");
-        r->gs = gs ? gs : chosen_group_size(r->in.n, r->in.D);
+        r->gs = gs ? gs : chosen_group_size(ctx, r->in.n, r->in.D);
         if (!(std::isfinite(rq->dt) && rq->dt > 0.0)) fail(NGR_EINVAL, "dt must be finite and > 0");
         if (rq->steps > (1u << 20)) fail(NGR_EINVAL, "steps must be at most 2^20");
         r->dt = rq->dt;
