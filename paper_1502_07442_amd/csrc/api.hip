@@ -688,7 +688,7 @@ NGR_API ngr_status ngr_autotune(ngr_context* ctx, uint32_t nbox, const ngr_box* 
             std::vector<double*> accs;
             std::vector<double*> scratch;
             uint64_t held = 0;
-            for (uint32_t rep = 0; held < (1ull << 21) && sub.size() < 4096; ++rep)
+            while (held < (1ull << 21) && sub.size() < 4096)
                 for (uint32_t k : kv.second) {
                     sub.push_back(in[k]);
                     laws.emplace_back();

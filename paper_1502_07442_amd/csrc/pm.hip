@@ -158,53 +158,58 @@ __device__ inline void fft_stages(double2* __restrict__ sm, const double2* __res
 
 __global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ data, uint32_t N, uint32_t p, uint32_t T,
                                                          uint32_t logT, int axis, const double2* __restrict__ twiddle,
-                                                         double sign)
+                                                         double sign, uint64_t ntiles)
 {
     HIP_DYNAMIC_SHARED(double2, sm);
     double2* tw = sm + (size_t)T * N;     // N / 2 twiddles, conjugated for the inverse (sign -1)
     const uint64_t N2 = (uint64_t)N * N, N3 = N2 * N;
     const uint64_t tiles_per_mesh = N2 >> logT;
-    const uint64_t tile = blockIdx.x % tiles_per_mesh, g = blockIdx.x / tiles_per_mesh;
-    double2* base = data + g * N3;
-    // first element of line 0 of the tile and the distance between the tile's lines
-    uint64_t l0, lstep, stride;
-    if (axis == 0) {
-        l0 = (tile << logT) * N;          // lines (x, y) = tile * T .. + T - 1, each of N elements
-        lstep = N;
-        stride = 1;
-    } else {
-        const uint64_t line0 = tile << logT;   // T consecutive lines in the (other, z) plane, z fastest
-        const uint64_t other = line0 >> p, z = line0 & (N - 1);
-        l0 = axis == 1 ? other * N2 + z : other * N + z;
-        lstep = 1;
-        stride = axis == 1 ? N : N2;
-    }
     for (uint32_t k = threadIdx.x; k < N / 2; k += blockDim.x) {
         const double2 w = twiddle[k];
         tw[k] = make_double2(w.x, sign * w.y);
     }
     const uint32_t TN = T * N;
-    for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
-        // consecutive threads take the same element of adjacent lines when
-        // the lines are adjacent in memory, else consecutive elements
-        const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
-        sm[lds_swizzle(l * N + k)] = base[l0 + l * lstep + k * stride];
-    }
-    __syncthreads();
-    // Radix-2 decimation in frequency, up to three stages per pass held in
-    // registers (fft_stages); a barrier between passes.
-    for (uint32_t s = 0; s < p;) {
-        const uint32_t f = min(3u, p - s);
-        if (f == 3) fft_stages<3>(sm, tw, sign, N, p, T, s);
-        else if (f == 2) fft_stages<2>(sm, tw, sign, N, p, T, s);
-        else fft_stages<1>(sm, tw, sign, N, p, T, s);
+    // a bounded grid of workgroups, each taking tiles in turn (the twiddles
+    // are staged once per workgroup); the trip count is uniform per workgroup
+    for (uint64_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const uint64_t tile = it % tiles_per_mesh, g = it / tiles_per_mesh;
+        double2* base = data + g * N3;
+        // first element of line 0 of the tile and the distance between the tile's lines
+        uint64_t l0, lstep, stride;
+        if (axis == 0) {
+            l0 = (tile << logT) * N;          // lines (x, y) = tile * T .. + T - 1, each of N elements
+            lstep = N;
+            stride = 1;
+        } else {
+            const uint64_t line0 = tile << logT;   // T consecutive lines in the (other, z) plane, z fastest
+            const uint64_t other = line0 >> p, z = line0 & (N - 1);
+            l0 = axis == 1 ? other * N2 + z : other * N + z;
+            lstep = 1;
+            stride = axis == 1 ? N : N2;
+        }
+        __syncthreads();                  // the previous tile's read-out is done (and the twiddles are in)
+        for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
+            // consecutive threads take the same element of adjacent lines when
+            // the lines are adjacent in memory, else consecutive elements
+            const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
+            sm[lds_swizzle(l * N + k)] = base[l0 + l * lstep + k * stride];
+        }
         __syncthreads();
-        s += f;
-    }
-    for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
-        const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
-        const uint32_t r = __brev(k) >> (32 - p);
-        base[l0 + l * lstep + k * stride] = sm[lds_swizzle(l * N + r)];
+        // Radix-2 decimation in frequency, up to three stages per pass held in
+        // registers (fft_stages); a barrier between passes.
+        for (uint32_t s = 0; s < p;) {
+            const uint32_t f = min(3u, p - s);
+            if (f == 3) fft_stages<3>(sm, tw, sign, N, p, T, s);
+            else if (f == 2) fft_stages<2>(sm, tw, sign, N, p, T, s);
+            else fft_stages<1>(sm, tw, sign, N, p, T, s);
+            __syncthreads();
+            s += f;
+        }
+        for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
+            const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
+            const uint32_t r = __brev(k) >> (32 - p);
+            base[l0 + l * lstep + k * stride] = sm[lds_swizzle(l * N + r)];
+        }
     }
 }
 
@@ -214,8 +219,9 @@ struct PairMix {
     uint32_t table[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
 };
 
-// The k-space step, one thread per pair (k, -k) (the thread of the smaller
-// linear index; self-mirrored points alone). Unpacks the density spectra of
+// The k-space step, one thread per pair (k, -k) (the member with x index at
+// most N/2, the smaller linear index within the planes x = 0 and x = N/2;
+// self-mirrored points alone). Unpacks the density spectra of
 // every species from the packed meshes, forms every sink species' potential
 // spectrum sum_b coef_ab u_t(ab)(q) / W(k)^2 rho_b(k), and packs the
 // potentials two per mesh, in place. gq[q][t] holds the U unique laws
@@ -226,12 +232,15 @@ __global__ void pm_green(double2* __restrict__ mesh, uint32_t N, uint32_t U, con
                          const double* __restrict__ s2, PairMix mix)
 {
     const uint64_t N3 = (uint64_t)N * N * N;
-    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N3) return;
+    // points with x index <= N/2 hold one member of every pair (k, -k); a
+    // bounded grid strides over them
+    const uint64_t half = (uint64_t)(N / 2 + 1) * N * N;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < half; c += stride) {
     const uint32_t i = (uint32_t)(c / ((uint64_t)N * N)), j = (uint32_t)((c / N) % N), l = (uint32_t)(c % N);
     const uint32_t mi = (N - i) & (N - 1), mj = (N - j) & (N - 1), ml = (N - l) & (N - 1);
     const uint64_t cm = ((uint64_t)mi * N + mj) * N + ml;
-    if (cm < c) return;                   // the mirror's thread does this pair
+    if (cm < c) continue;                 // the pair's other member (x index 0 or N/2) does it
     const int ni = i < N / 2 ? (int)i : (int)i - (int)N, nj = j < N / 2 ? (int)j : (int)j - (int)N,
               nl = l < N / 2 ? (int)l : (int)l - (int)N;
     const uint32_t q = (uint32_t)(ni * ni + nj * nj + nl * nl);
@@ -265,6 +274,7 @@ __global__ void pm_green(double2* __restrict__ mesh, uint32_t N, uint32_t U, con
         // P(k) = Phi_even(k) + i Phi_odd(k); P(-k) = conj Phi_even(k) + i conj Phi_odd(k)
         mesh[g2 * N3 + c] = make_double2(ph[0].x - ph[1].y, ph[0].y + ph[1].x);
         if (cm != c) mesh[g2 * N3 + cm] = make_double2(ph[0].x + ph[1].y, -ph[0].y + ph[1].x);
+    }
     }
 }
 
@@ -433,10 +443,12 @@ static void fft3(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign)
         uint32_t logT = 0;
         while ((1u << logT) < T) ++logT;
         const size_t lds = (size_t)T * N * sizeof(double2) + (N / 2) * sizeof(double2);
-        const uint64_t blocks = (uint64_t)ngrid * ((uint64_t)N * N / T);
-        if (blocks > 0x7fffffffull) fail(NGR_EINVAL, "mesh too large for the FFT grid");
+        const uint64_t ntiles = (uint64_t)ngrid * ((uint64_t)N * N / T);
+        // as many workgroups as fit on the device at once (LDS-bound), each looping over tiles
+        const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, ctx.lds_per_block / lds));
+        const uint64_t blocks = std::min<uint64_t>(ntiles, per_cu * (uint64_t)ctx.num_cu);
         hipLaunchKernelGGL(fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), lds, ctx.stream, pl.mesh, N, pl.p, T,
-                           logT, axis, pl.tw, sign);
+                           logT, axis, pl.tw, sign, ntiles);
         LAUNCH_CHECK("fft_lines");
     }
 }
@@ -466,7 +478,8 @@ void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumula
         mix.coef[ab] = pl.mix_coef[ab];
         mix.table[ab] = pl.mix_table[ab];
     }
-    const dim3 gg((unsigned)((N3 + 255) / 256));
+    const uint64_t half = (uint64_t)(N / 2 + 1) * N * N;
+    const dim3 gg((unsigned)std::min<uint64_t>((half + 255) / 256, 64ull * ctx.num_cu));
     switch (D) {
     case 1: hipLaunchKernelGGL(pm_green<1>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
     case 2: hipLaunchKernelGGL(pm_green<2>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
