@@ -43,8 +43,7 @@
 namespace ngr {
 namespace {
 
-constexpr int kFftThreads = 256;
-constexpr size_t kFftTileBytes = 64 * 1024;   // LDS of one workgroup's lines
+constexpr size_t kFftTileBytes = 128 * 1024;   // most LDS for one workgroup's lines
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -156,45 +155,94 @@ __device__ inline void fft_stages(double2* __restrict__ sm, const double2* __res
     }
 }
 
-__global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ data, uint32_t N, uint32_t p, uint32_t T,
-                                                         uint32_t logT, int axis, const double2* __restrict__ twiddle,
-                                                         double sign, uint64_t ntiles)
+// One tile's element e (0 .. T N - 1) of a thread: its line l and point k.
+// Consecutive threads take the same point of adjacent lines when the lines
+// are adjacent in memory (axes 1, 2), else consecutive points (axis 0).
+template <int AXIS>
+__device__ __forceinline__ void tile_element(uint32_t e, uint32_t p, uint32_t T, uint32_t logT, uint32_t& l,
+                                             uint32_t& k)
+{
+    l = AXIS == 0 ? e >> p : e & (T - 1);
+    k = AXIS == 0 ? e & ((1u << p) - 1u) : e >> logT;
+}
+
+// First element of line 0 of tile it (tiles counted over all meshes; N^2 / T
+// tiles per mesh).
+template <int AXIS>
+__device__ __forceinline__ uint64_t tile_origin(uint64_t it, uint32_t p, uint32_t logT)
+{
+    const uint32_t lt = 2 * p - logT;     // log2 of the tiles per mesh
+    const uint64_t tile = it & ((1ull << lt) - 1ull), g = it >> lt;
+    const uint64_t N = 1ull << p;
+    uint64_t l0;
+    if (AXIS == 0) {
+        l0 = (tile << logT) << p;         // lines (x, y) = tile * T .. + T - 1, each of N elements
+    } else if (AXIS == 1) {
+        const uint64_t line0 = tile << logT;   // T consecutive lines in the (x, z) plane, z fastest
+        const uint64_t x = line0 >> p, z = line0 & (N - 1);
+        l0 = (x << (2 * p)) + z;
+    } else {
+        // T lines adjacent in z at one y; consecutive tiles step y first, so
+        // the workgroups running at once read rows of many different y (16
+        // KiB apart at N = 1024) in every x plane rather than the same few
+        const uint64_t y = tile & (N - 1), z = (tile >> p) << logT;
+        l0 = (y << p) + z;
+    }
+    return (g << (3 * p)) + l0;
+}
+
+// The real and imaginary parts go to separate register arrays: an array of
+// double2 held across the tile loop is kept in scratch memory by the compiler.
+template <uint32_t EPT, uint32_t NT, int AXIS>
+__device__ __forceinline__ void load_tile(double (&rx)[EPT], double (&ry)[EPT], const double2* __restrict__ src,
+                                          uint32_t p, uint32_t T, uint32_t logT, uint64_t lstep, uint64_t stride)
+{
+#pragma unroll
+    for (uint32_t i = 0; i < EPT; ++i) {
+        uint32_t l, k;
+        tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+        const double2 v = src[l * lstep + k * stride];
+        rx[i] = v.x;
+        ry[i] = v.y;
+    }
+}
+
+// EPT = T N / NT elements per thread (NT threads), fixed at compile time so that
+// a tile's loads are all issued before the first is waited for. The axis is a
+// template parameter too: with it a runtime argument, the gfx950 backend
+// (ROCm 7.2) left the register holding log2 T unset on the x-axis path into
+// the tile loop, so the x transform read and wrote wrong tiles. A bounded
+// grid of workgroups takes tiles in turn; the next tile's loads are issued
+// into registers before the current tile's stages, so they are in flight
+// while the stages run.
+template <uint32_t EPT, uint32_t NT, int AXIS>
+__global__ __launch_bounds__(NT) void fft_lines(double2* __restrict__ data, uint32_t N, uint32_t p, uint32_t T,
+                                                uint32_t logT, const double2* __restrict__ twiddle, double sign,
+                                                uint64_t ntiles)
 {
     HIP_DYNAMIC_SHARED(double2, sm);
     double2* tw = sm + (size_t)T * N;     // N / 2 twiddles, conjugated for the inverse (sign -1)
-    const uint64_t N2 = (uint64_t)N * N, N3 = N2 * N;
-    const uint64_t tiles_per_mesh = N2 >> logT;
     for (uint32_t k = threadIdx.x; k < N / 2; k += blockDim.x) {
         const double2 w = twiddle[k];
         tw[k] = make_double2(w.x, sign * w.y);
     }
-    const uint32_t TN = T * N;
-    // a bounded grid of workgroups, each taking tiles in turn (the twiddles
-    // are staged once per workgroup); the trip count is uniform per workgroup
-    for (uint64_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
-        const uint64_t tile = it % tiles_per_mesh, g = it / tiles_per_mesh;
-        double2* base = data + g * N3;
-        // first element of line 0 of the tile and the distance between the tile's lines
-        uint64_t l0, lstep, stride;
-        if (axis == 0) {
-            l0 = (tile << logT) * N;          // lines (x, y) = tile * T .. + T - 1, each of N elements
-            lstep = N;
-            stride = 1;
-        } else {
-            const uint64_t line0 = tile << logT;   // T consecutive lines in the (other, z) plane, z fastest
-            const uint64_t other = line0 >> p, z = line0 & (N - 1);
-            l0 = axis == 1 ? other * N2 + z : other * N + z;
-            lstep = 1;
-            stride = axis == 1 ? N : N2;
-        }
+    // distance between a tile's lines and between a line's points
+    const uint64_t lstep = AXIS == 0 ? N : 1, stride = AXIS == 0 ? 1 : (AXIS == 1 ? N : (uint64_t)N * N);
+    double rx[EPT], ry[EPT];
+    uint64_t it = blockIdx.x;
+    if (it < ntiles) load_tile<EPT, NT, AXIS>(rx, ry, data + tile_origin<AXIS>(it, p, logT), p, T, logT, lstep, stride);
+    // the trip count is uniform per workgroup
+    for (; it < ntiles; it += gridDim.x) {
         __syncthreads();                  // the previous tile's read-out is done (and the twiddles are in)
-        for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
-            // consecutive threads take the same element of adjacent lines when
-            // the lines are adjacent in memory, else consecutive elements
-            const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
-            sm[lds_swizzle(l * N + k)] = base[l0 + l * lstep + k * stride];
+#pragma unroll
+        for (uint32_t i = 0; i < EPT; ++i) {
+            uint32_t l, k;
+            tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+            sm[lds_swizzle(l * N + k)] = make_double2(rx[i], ry[i]);
         }
         __syncthreads();
+        const uint64_t nx = it + gridDim.x;
+        if (nx < ntiles) load_tile<EPT, NT, AXIS>(rx, ry, data + tile_origin<AXIS>(nx, p, logT), p, T, logT, lstep, stride);
         // Radix-2 decimation in frequency, up to three stages per pass held in
         // registers (fft_stages); a barrier between passes.
         for (uint32_t s = 0; s < p;) {
@@ -205,10 +253,13 @@ __global__ __launch_bounds__(kFftThreads) void fft_lines(double2* __restrict__ d
             __syncthreads();
             s += f;
         }
-        for (uint32_t e = threadIdx.x; e < TN; e += blockDim.x) {
-            const uint32_t l = axis == 0 ? e >> p : e & (T - 1), k = axis == 0 ? e & (N - 1) : e >> logT;
-            const uint32_t r = __brev(k) >> (32 - p);
-            base[l0 + l * lstep + k * stride] = sm[lds_swizzle(l * N + r)];
+        double2* dst = data + tile_origin<AXIS>(it, p, logT);
+#pragma unroll
+        for (uint32_t i = 0; i < EPT; ++i) {
+            uint32_t l, k;
+            tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+            const uint32_t rk = __brev(k) >> (32 - p);
+            dst[l * lstep + k * stride] = sm[lds_swizzle(l * N + rk)];
         }
     }
 }
@@ -228,18 +279,19 @@ struct PairMix {
 // phibar_t(q) exp(-k^2 r_s^2) / (k^2 N^3) (0 at q = 0); s2 holds
 // sinc^2(pi n / N) per grid index.
 template <uint32_t D>
-__global__ void pm_green(double2* __restrict__ mesh, uint32_t N, uint32_t U, const double* __restrict__ gq,
+__global__ void pm_green(double2* __restrict__ mesh, uint32_t p, uint32_t U, const double* __restrict__ gq,
                          const double* __restrict__ s2, PairMix mix)
 {
-    const uint64_t N3 = (uint64_t)N * N * N;
+    const uint32_t N = 1u << p, m = N - 1;
+    const uint64_t N3 = 1ull << (3 * p);
     // points with x index <= N/2 hold one member of every pair (k, -k); a
     // bounded grid strides over them
-    const uint64_t half = (uint64_t)(N / 2 + 1) * N * N;
+    const uint64_t half = (uint64_t)(N / 2 + 1) << (2 * p);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < half; c += stride) {
-    const uint32_t i = (uint32_t)(c / ((uint64_t)N * N)), j = (uint32_t)((c / N) % N), l = (uint32_t)(c % N);
-    const uint32_t mi = (N - i) & (N - 1), mj = (N - j) & (N - 1), ml = (N - l) & (N - 1);
-    const uint64_t cm = ((uint64_t)mi * N + mj) * N + ml;
+    const uint32_t i = (uint32_t)(c >> (2 * p)), j = (uint32_t)(c >> p) & m, l = (uint32_t)c & m;
+    const uint32_t mi = (N - i) & m, mj = (N - j) & m, ml = (N - l) & m;
+    const uint64_t cm = ((((uint64_t)mi << p) | mj) << p) | ml;
     if (cm < c) continue;                 // the pair's other member (x index 0 or N/2) does it
     const int ni = i < N / 2 ? (int)i : (int)i - (int)N, nj = j < N / 2 ? (int)j : (int)j - (int)N,
               nl = l < N / 2 ? (int)l : (int)l - (int)N;
@@ -256,24 +308,31 @@ __global__ void pm_green(double2* __restrict__ mesh, uint32_t N, uint32_t U, con
         rho[2 * g2] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
         rho[2 * g2 + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
     }
+    double2 ph[2 * ngrid];
 #pragma unroll
-    for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
-        double2 ph[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    for (uint32_t a = 0; a < 2 * ngrid; ++a) ph[a] = make_double2(0.0, 0.0);
+    // Each unique table is read once per point (a lane's q is its own, so a
+    // read touches one cache line per lane); the pairs that scale it are
+    // selected by the uniform table index.
+    for (uint32_t t = 0; t < U; ++t) {
+        const double g = gqq[t] * iw2;
 #pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
-            const uint32_t a = 2 * g2 + h;
-            if (a >= D) break;
+        for (uint32_t a = 0; a < D; ++a) {
 #pragma unroll
             for (uint32_t b = 0; b < D; ++b) {
-                // the pair's table index is uniform: every lane reads its own q's entry
-                const double f = mix.coef[a * D + b] * gqq[mix.table[a * D + b]] * iw2;
-                ph[h].x = fma(f, rho[b].x, ph[h].x);
-                ph[h].y = fma(f, rho[b].y, ph[h].y);
+                if (mix.table[a * D + b] != t) continue;
+                const double f = mix.coef[a * D + b] * g;
+                ph[a].x = fma(f, rho[b].x, ph[a].x);
+                ph[a].y = fma(f, rho[b].y, ph[a].y);
             }
         }
+    }
+#pragma unroll
+    for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
         // P(k) = Phi_even(k) + i Phi_odd(k); P(-k) = conj Phi_even(k) + i conj Phi_odd(k)
-        mesh[g2 * N3 + c] = make_double2(ph[0].x - ph[1].y, ph[0].y + ph[1].x);
-        if (cm != c) mesh[g2 * N3 + cm] = make_double2(ph[0].x + ph[1].y, -ph[0].y + ph[1].x);
+        const double2 pe = ph[2 * g2], po = ph[2 * g2 + 1];
+        mesh[g2 * N3 + c] = make_double2(pe.x - po.y, pe.y + po.x);
+        if (cm != c) mesh[g2 * N3 + cm] = make_double2(pe.x + po.y, -pe.y + po.x);
     }
     }
 }
@@ -432,11 +491,12 @@ static void fft3(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign)
 {
     const uint32_t N = pl.N;
     // lines per workgroup: along z (contiguous lines) at least 1024 points; along
-    // y and x (lines adjacent in z) as many as fit 64 KiB, for longer
-    // contiguous runs (measured at N = 1024: 38 ms per mesh and forward
-    // transform with 1 and 4 lines, 42 ms with 4 and 4, 50 ms with 1 and 8)
+    // y and x (lines adjacent in z) as many as fit kFftTileBytes, for longer
+    // contiguous runs: 8 lines at N = 1024 read whole 128-byte lines of memory
+    // (4 lines read half lines)
+    const size_t tile_max = std::min(kFftTileBytes, ctx.lds_per_block - (N / 2) * sizeof(double2));
     uint32_t T12 = 1;
-    while (T12 < 16 && (size_t)(2 * T12) * N * sizeof(double2) <= kFftTileBytes && 2 * T12 <= N * N) T12 *= 2;
+    while (T12 < 16 && (size_t)(2 * T12) * N * sizeof(double2) <= tile_max && 2 * T12 <= N * N) T12 *= 2;
     const uint32_t T0 = std::min<uint32_t>(16, std::max<uint32_t>(1, 1024 / N));
     for (int axis = 0; axis < 3; ++axis) {
         const uint32_t T = axis == 0 ? T0 : T12;
@@ -444,11 +504,37 @@ static void fft3(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign)
         while ((1u << logT) < T) ++logT;
         const size_t lds = (size_t)T * N * sizeof(double2) + (N / 2) * sizeof(double2);
         const uint64_t ntiles = (uint64_t)ngrid * ((uint64_t)N * N / T);
+        // 256 threads, 512 for tiles over 64 KiB (at most 16 elements a thread)
+        const uint32_t NT = (size_t)T * N * sizeof(double2) > 64 * 1024 ? 512 : 256;
+        const uint32_t ept = (T * N) / NT;
+        if ((T * N) % NT != 0 || ept < 1 || ept > 16 || (ept & (ept - 1)) != 0 || lds > ctx.lds_per_block)
+            fail(NGR_EINVAL, "pm: an FFT tile of " + std::to_string(T) + " lines of " + std::to_string(N) +
+                                 " points does not fit one workgroup");
         // as many workgroups as fit on the device at once (LDS-bound), each looping over tiles
         const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, ctx.lds_per_block / lds));
         const uint64_t blocks = std::min<uint64_t>(ntiles, per_cu * (uint64_t)ctx.num_cu);
-        hipLaunchKernelGGL(fft_lines, dim3((unsigned)blocks), dim3(kFftThreads), lds, ctx.stream, pl.mesh, N, pl.p, T,
-                           logT, axis, pl.tw, sign, ntiles);
+        const dim3 grid((unsigned)blocks);
+#define NGR_FFT_LAUNCH(E, W)                                                                                        \
+    switch (axis) {                                                                                                  \
+    case 0: hipLaunchKernelGGL((fft_lines<E, W, 0>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,    \
+                               pl.tw, sign, ntiles); break;                                                          \
+    case 1: hipLaunchKernelGGL((fft_lines<E, W, 1>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,    \
+                               pl.tw, sign, ntiles); break;                                                          \
+    default: hipLaunchKernelGGL((fft_lines<E, W, 2>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,   \
+                                pl.tw, sign, ntiles); break;                                                         \
+    }
+        if (NT == 512) {
+            NGR_FFT_LAUNCH(16, 512);
+        } else {
+            switch (ept) {
+            case 1: NGR_FFT_LAUNCH(1, 256); break;
+            case 2: NGR_FFT_LAUNCH(2, 256); break;
+            case 4: NGR_FFT_LAUNCH(4, 256); break;
+            case 8: NGR_FFT_LAUNCH(8, 256); break;
+            default: NGR_FFT_LAUNCH(16, 256); break;
+            }
+        }
+#undef NGR_FFT_LAUNCH
         LAUNCH_CHECK("fft_lines");
     }
 }
@@ -481,12 +567,12 @@ void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumula
     const uint64_t half = (uint64_t)(N / 2 + 1) * N * N;
     const dim3 gg((unsigned)std::min<uint64_t>((half + 255) / 256, 64ull * ctx.num_cu));
     switch (D) {
-    case 1: hipLaunchKernelGGL(pm_green<1>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
-    case 2: hipLaunchKernelGGL(pm_green<2>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
-    case 3: hipLaunchKernelGGL(pm_green<3>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
-    case 4: hipLaunchKernelGGL(pm_green<4>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
-    case 5: hipLaunchKernelGGL(pm_green<5>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
-    default: hipLaunchKernelGGL(pm_green<6>, gg, dim3(256), 0, ctx.stream, pl.mesh, N, pl.U, pl.gq, pl.s2, mix); break;
+    case 1: hipLaunchKernelGGL(pm_green<1>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
+    case 2: hipLaunchKernelGGL(pm_green<2>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
+    case 3: hipLaunchKernelGGL(pm_green<3>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
+    case 4: hipLaunchKernelGGL(pm_green<4>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
+    case 5: hipLaunchKernelGGL(pm_green<5>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
+    default: hipLaunchKernelGGL(pm_green<6>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
     }
     LAUNCH_CHECK("pm_green");
     HIP_CHECK(hipEventRecord(ev[3], ctx.stream));

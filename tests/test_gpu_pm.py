@@ -2,7 +2,7 @@
 path against the oracle's numpy PM, element by element (the same scheme in
 float64; FFT and atomic-sum orders differ, so 1e-10 rms|a|): one to six
 species, random asymmetric G and mixed Newton/Yukawa laws, meshes of 16 to
-128 points, positions given as floats or lattice coordinates, accumulation,
+512 points, positions given as floats or lattice coordinates, accumulation,
 empty species, and the error paths."""
 import math
 
@@ -63,6 +63,23 @@ def run(ctx, p, N, G, phib, r_s, accumulate_onto=None):
                                         (20000, 4, 128, 5), (3000, 5, 64, 6)])
 def test_parity(ctx, n, D, N, seed):
     p = synth.clustered_problem(n, D, seed, ntab=64)
+    G, phib = laws(D, N, p.box, seed)
+    r_s = 1.25 * p.box / N
+    acc, st = run(ctx, p, N, G, phib, r_s)
+    ref = pm.pm_accel(oracle.lattice_of(p), p.species, p.mass, D, p.box, G, phib, N, r_s)
+    rms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
+    err = np.max(np.linalg.norm(acc - ref, axis=0)) / rms
+    print(f"  max|da|/rms={err:.3g} ms={st}", flush=True)
+    assert err < 1e-10
+
+
+def test_parity_mesh_512(ctx):
+    """At N = 512 the y and x transforms hold 16 lines of 512 points per
+    workgroup (128 KiB of LDS, 512 threads), the layout of the large meshes;
+    the smaller meshes above use 256-thread tiles of at most 64 KiB. One
+    species keeps the oracle's transforms to two (about 30 s)."""
+    D, N, seed = 1, 512, 8
+    p = synth.clustered_problem(4000, D, seed, ntab=64)
     G, phib = laws(D, N, p.box, seed)
     r_s = 1.25 * p.box / N
     acc, st = run(ctx, p, N, G, phib, r_s)
