@@ -320,7 +320,11 @@ typedef struct {
 
 typedef struct ngr_pm ngr_pm;
 
-/* Device time of the last ngr_pm_force, per step (ms). */
+/* Device time of the last ngr_pm_force, per step (ms): the deposit (with the
+ * clearing of the meshes); the forward transforms along x and y; one pass
+ * holding the forward z transform, the k-space step and the inverse z
+ * transform (ms_green); the inverse transforms along y and x; the
+ * interpolation. */
 typedef struct {
     double ms_deposit;
     double ms_fft_forward;

@@ -23,11 +23,15 @@
 //   transform: ceil(D/2) inverse FFTs instead of the D^2 mesh passes the
 //   paper's MPI slab decomposition needs. The sink species' real potentials
 //   are paired into complex meshes the same way.
-// - 3-D FFTs are three passes of batched 1-D radix-2 transforms along one
-//   axis each, a tile of lines held in LDS per workgroup (lines adjacent in
-//   memory, so that the strided axes read contiguous runs), three stages at
-//   a time in registers between LDS exchanges, the twiddles staged in LDS
-//   from a float64 table computed on the host.
+// - 3-D FFTs are passes of batched 1-D radix-2 transforms along one axis
+//   each, a tile of lines held in LDS per workgroup, three stages at a time
+//   in registers between LDS exchanges, the twiddles staged in LDS from a
+//   float64 table computed on the host. The x and y passes take tiles of
+//   lines adjacent in z, so that the strided axes read contiguous runs. The
+//   z transforms of both directions and the k-space step are one pass: a
+//   workgroup holds a z line and its mirror line (-x, -y) of every mesh, so
+//   both points of every pair (k, -k) are in its LDS. A force is then five
+//   sweeps over the meshes (x, y, z with the k-space step, y, x), not seven.
 // - The Green's function is a table over q = |k|^2 (2 pi / L)^-2 per
 //   distinct law: pairs whose phibar tables agree up to a constant factor
 //   share one table and keep the factor (times G_ab) as a coefficient; the
@@ -92,9 +96,10 @@ __global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const dou
 // bit-reversed order read out. sign = +1: exp(-2 pi i k n / N) (forward),
 // -1: exp(+2 pi i k n / N) (inverse, unnormalised).
 // The LDS holds T lines of N points and the N / 2 twiddles.
-// axis 0: lines along z (stride 1), the T lines of a tile N apart;
 // axis 1: along y (stride N), a tile's lines adjacent in z;
 // axis 2: along x (stride N^2), a tile's lines adjacent in z.
+// The z transforms (contiguous lines) run inside the k-space pass
+// (pm_green_z).
 
 __device__ inline uint32_t lds_swizzle(uint32_t i)
 {
@@ -156,14 +161,12 @@ __device__ inline void fft_stages(double2* __restrict__ sm, const double2* __res
 }
 
 // One tile's element e (0 .. T N - 1) of a thread: its line l and point k.
-// Consecutive threads take the same point of adjacent lines when the lines
-// are adjacent in memory (axes 1, 2), else consecutive points (axis 0).
-template <int AXIS>
-__device__ __forceinline__ void tile_element(uint32_t e, uint32_t p, uint32_t T, uint32_t logT, uint32_t& l,
-                                             uint32_t& k)
+// Consecutive threads take the same point of adjacent lines (adjacent in
+// memory), so a wave reads runs of T elements.
+__device__ __forceinline__ void tile_element(uint32_t e, uint32_t T, uint32_t logT, uint32_t& l, uint32_t& k)
 {
-    l = AXIS == 0 ? e >> p : e & (T - 1);
-    k = AXIS == 0 ? e & ((1u << p) - 1u) : e >> logT;
+    l = e & (T - 1);
+    k = e >> logT;
 }
 
 // First element of line 0 of tile it (tiles counted over all meshes; N^2 / T
@@ -175,9 +178,7 @@ __device__ __forceinline__ uint64_t tile_origin(uint64_t it, uint32_t p, uint32_
     const uint64_t tile = it & ((1ull << lt) - 1ull), g = it >> lt;
     const uint64_t N = 1ull << p;
     uint64_t l0;
-    if (AXIS == 0) {
-        l0 = (tile << logT) << p;         // lines (x, y) = tile * T .. + T - 1, each of N elements
-    } else if (AXIS == 1) {
+    if (AXIS == 1) {
         const uint64_t line0 = tile << logT;   // T consecutive lines in the (x, z) plane, z fastest
         const uint64_t x = line0 >> p, z = line0 & (N - 1);
         l0 = (x << (2 * p)) + z;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void load_tile(double (&rx)[EPT], double (&ry)[EPT], 
 #pragma unroll
     for (uint32_t i = 0; i < EPT; ++i) {
         uint32_t l, k;
-        tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+        tile_element(threadIdx.x + i * NT, T, logT, l, k);
         const double2 v = src[l * lstep + k * stride];
         rx[i] = v.x;
         ry[i] = v.y;
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(NT) void fft_lines(double2* __restrict__ data, uint
         tw[k] = make_double2(w.x, sign * w.y);
     }
     // distance between a tile's lines and between a line's points
-    const uint64_t lstep = AXIS == 0 ? N : 1, stride = AXIS == 0 ? 1 : (AXIS == 1 ? N : (uint64_t)N * N);
+    const uint64_t lstep = 1, stride = AXIS == 1 ? N : (uint64_t)N * N;
     double rx[EPT], ry[EPT];
     uint64_t it = blockIdx.x;
     if (it < ntiles) load_tile<EPT, NT, AXIS>(rx, ry, data + tile_origin<AXIS>(it, p, logT), p, T, logT, lstep, stride);
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(NT) void fft_lines(double2* __restrict__ data, uint
 #pragma unroll
         for (uint32_t i = 0; i < EPT; ++i) {
             uint32_t l, k;
-            tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+            tile_element(threadIdx.x + i * NT, T, logT, l, k);
             sm[lds_swizzle(l * N + k)] = make_double2(rx[i], ry[i]);
         }
         __syncthreads();
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(NT) void fft_lines(double2* __restrict__ data, uint
 #pragma unroll
         for (uint32_t i = 0; i < EPT; ++i) {
             uint32_t l, k;
-            tile_element<AXIS>(threadIdx.x + i * NT, p, T, logT, l, k);
+            tile_element(threadIdx.x + i * NT, T, logT, l, k);
             const uint32_t rk = __brev(k) >> (32 - p);
             dst[l * lstep + k * stride] = sm[lds_swizzle(l * N + rk)];
         }
@@ -270,40 +271,22 @@ struct PairMix {
     uint32_t table[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
 };
 
-// The k-space step, one thread per pair (k, -k) (the member with x index at
-// most N/2, the smaller linear index within the planes x = 0 and x = N/2;
-// self-mirrored points alone). Unpacks the density spectra of
-// every species from the packed meshes, forms every sink species' potential
-// spectrum sum_b coef_ab u_t(ab)(q) / W(k)^2 rho_b(k), and packs the
-// potentials two per mesh, in place. gq[q][t] holds the U unique laws
-// phibar_t(q) exp(-k^2 r_s^2) / (k^2 N^3) (0 at q = 0); s2 holds
-// sinc^2(pi n / N) per grid index.
+// The k-space step at one pair of points (k, -k): Z[g] = Z_g(k) and Zm[g] =
+// Z_g(-k) of the packed meshes in; the packed potential spectra P_g(k) and
+// P_g(-k) out. Unpacks the density spectra of every species, forms every sink
+// species' potential spectrum sum_b coef_ab u_t(ab)(q) / W(k)^2 rho_b(k), and
+// packs the potentials two per mesh. gq[q][t] holds the U unique laws
+// phibar_t(q) exp(-k^2 r_s^2) / (k^2 N^3) (0 at q = 0); iw2 = 1 / W(k)^2.
 template <uint32_t D>
-__global__ void pm_green(double2* __restrict__ mesh, uint32_t p, uint32_t U, const double* __restrict__ gq,
-                         const double* __restrict__ s2, PairMix mix)
+__device__ __forceinline__ void green_point(double2 (&Z)[(D + 1) / 2], double2 (&Zm)[(D + 1) / 2],
+                                            const double* __restrict__ gqq, uint32_t U, double iw2,
+                                            const PairMix& mix)
 {
-    const uint32_t N = 1u << p, m = N - 1;
-    const uint64_t N3 = 1ull << (3 * p);
-    // points with x index <= N/2 hold one member of every pair (k, -k); a
-    // bounded grid strides over them
-    const uint64_t half = (uint64_t)(N / 2 + 1) << (2 * p);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < half; c += stride) {
-    const uint32_t i = (uint32_t)(c >> (2 * p)), j = (uint32_t)(c >> p) & m, l = (uint32_t)c & m;
-    const uint32_t mi = (N - i) & m, mj = (N - j) & m, ml = (N - l) & m;
-    const uint64_t cm = ((((uint64_t)mi << p) | mj) << p) | ml;
-    if (cm < c) continue;                 // the pair's other member (x index 0 or N/2) does it
-    const int ni = i < N / 2 ? (int)i : (int)i - (int)N, nj = j < N / 2 ? (int)j : (int)j - (int)N,
-              nl = l < N / 2 ? (int)l : (int)l - (int)N;
-    const uint32_t q = (uint32_t)(ni * ni + nj * nj + nl * nl);
-    const double W = s2[i] * s2[j] * s2[l];
-    const double iw2 = 1.0 / (W * W);
-    const double* gqq = gq + (uint64_t)q * U;
     constexpr uint32_t ngrid = (D + 1) / 2;
     double2 rho[2 * ngrid];
 #pragma unroll
     for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
-        const double2 z = mesh[g2 * N3 + c], zm = mesh[g2 * N3 + cm];
+        const double2 z = Z[g2], zm = Zm[g2];
         // rho_even(k) = (Z(k) + conj Z(-k)) / 2, rho_odd(k) = (Z(k) - conj Z(-k)) / 2i
         rho[2 * g2] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
         rho[2 * g2 + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
@@ -331,9 +314,181 @@ __global__ void pm_green(double2* __restrict__ mesh, uint32_t p, uint32_t U, con
     for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
         // P(k) = Phi_even(k) + i Phi_odd(k); P(-k) = conj Phi_even(k) + i conj Phi_odd(k)
         const double2 pe = ph[2 * g2], po = ph[2 * g2 + 1];
-        mesh[g2 * N3 + c] = make_double2(pe.x - po.y, pe.y + po.x);
-        if (cm != c) mesh[g2 * N3 + cm] = make_double2(pe.x + po.y, -pe.y + po.x);
+        Z[g2] = make_double2(pe.x - po.y, pe.y + po.x);
+        Zm[g2] = make_double2(pe.x + po.y, -pe.y + po.x);
     }
+}
+
+// Lines along z come in mirror pairs: line (x, y) holds the points (x, y, k),
+// line (-x, -y) the points -(x, y, k) up to the sign of k. Pair P (of N^2 / 2
+// + 2) is the line with the smaller index: x in 1 .. N/2 - 1 with any y, then
+// x = 0 and x = N/2 with y in 0 .. N/2 (four lines are their own mirror).
+__device__ __forceinline__ void mirror_pair(uint64_t P, uint32_t p, uint32_t& x, uint32_t& y)
+{
+    const uint32_t N = 1u << p;
+    const uint64_t inner = (uint64_t)(N / 2 - 1) << p;
+    if (P < inner) {
+        x = 1u + (uint32_t)(P >> p);
+        y = (uint32_t)P & (N - 1u);
+    } else {
+        const uint32_t r = (uint32_t)(P - inner);
+        x = r < N / 2 + 1 ? 0u : N / 2;
+        y = r < N / 2 + 1 ? r : r - (N / 2 + 1);
+    }
+}
+
+constexpr uint32_t kFusedThreads = 512;
+
+// The z transforms and the k-space step in one pass. A workgroup takes a
+// mirror pair of z lines in every packed mesh (2 ceil(D/2) lines in LDS: slot
+// 2g the line (x, y) of mesh g, slot 2g + 1 the mirror line): forward
+// transform along z, the k-space step at (k, -k) with both points in LDS,
+// inverse transform, write back. The x and y transforms of both directions
+// run before and after it, so each mesh is read and written once here where
+// separate passes would take three sweeps. The forward output is in
+// bit-reversed order; the k-space step reads it there and writes the inverse
+// transform's input in natural order (results held in registers across a
+// barrier). The next pair's loads are in flight while a pair is transformed.
+template <uint32_t D>
+__global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict__ mesh, uint32_t p, uint32_t U,
+                                                            const double* __restrict__ gq,
+                                                            const double* __restrict__ s2,
+                                                            const double2* __restrict__ twiddle, PairMix mix,
+                                                            uint64_t npairs)
+{
+    constexpr uint32_t ngrid = (D + 1) / 2, L = 2 * ngrid, NT = kFusedThreads;
+    constexpr uint32_t EMAX = (L * 1024 + NT - 1) / NT;   // elements per thread at N = 1024
+    constexpr uint32_t KMAX = (1024 + NT - 1) / NT;       // points per thread in the k-space step
+    const uint32_t N = 1u << p, m = N - 1u, LN = L * N;
+    const uint64_t N3 = 1ull << (3 * p);
+    HIP_DYNAMIC_SHARED(double2, sm);
+    double2* twf = sm + (size_t)LN;       // forward twiddles
+    double2* twi = twf + N / 2;           // conjugated, for the inverse
+    for (uint32_t k = threadIdx.x; k < N / 2; k += NT) {
+        const double2 w = twiddle[k];
+        twf[k] = w;
+        twi[k] = make_double2(w.x, -w.y);
+    }
+    // the trip count is uniform per workgroup; every workgroup has a first pair
+    // (the grid is at most npairs)
+    uint64_t P = blockIdx.x;
+    uint32_t x, y;
+    mirror_pair(P, p, x, y);
+    double rx[EMAX], ry[EMAX];
+    {
+        const uint64_t la = (((uint64_t)x << p) | y) << p, lb = ((((uint64_t)((N - x) & m)) << p) | ((N - y) & m)) << p;
+#pragma unroll
+        for (uint32_t i = 0; i < EMAX; ++i) {
+            const uint32_t e = threadIdx.x + i * NT;
+            if (e < LN) {
+                const uint32_t l = e >> p, k = e & m;
+                const double2 v = mesh[(l >> 1) * N3 + ((l & 1) ? lb : la) + k];
+                rx[i] = v.x;
+                ry[i] = v.y;
+            }
+        }
+    }
+    for (;;) {
+        const uint32_t mx = (N - x) & m, my = (N - y) & m;
+        const bool self = mx == x && my == y;
+        const uint64_t la = (((uint64_t)x << p) | y) << p, lb = (((uint64_t)mx << p) | my) << p;
+        __syncthreads();                  // the previous pair's read-out is done (and the twiddles are in)
+#pragma unroll
+        for (uint32_t i = 0; i < EMAX; ++i) {
+            const uint32_t e = threadIdx.x + i * NT;
+            if (e < LN) sm[lds_swizzle(e)] = make_double2(rx[i], ry[i]);
+        }
+        __syncthreads();
+        const uint64_t nP = P + gridDim.x;
+        const bool more = nP < npairs;
+        uint32_t nx, ny;
+        mirror_pair(more ? nP : P, p, nx, ny);
+        if (more) {
+            const uint64_t na = (((uint64_t)nx << p) | ny) << p,
+                           nb = ((((uint64_t)((N - nx) & m)) << p) | ((N - ny) & m)) << p;
+#pragma unroll
+            for (uint32_t i = 0; i < EMAX; ++i) {
+                const uint32_t e = threadIdx.x + i * NT;
+                if (e < LN) {
+                    const uint32_t l = e >> p, k = e & m;
+                    const double2 v = mesh[(l >> 1) * N3 + ((l & 1) ? nb : na) + k];
+                    rx[i] = v.x;
+                    ry[i] = v.y;
+                }
+            }
+        }
+        for (uint32_t s = 0; s < p;) {
+            const uint32_t f = min(3u, p - s);
+            if (f == 3) fft_stages<3>(sm, twf, 1.0, N, p, L, s);
+            else if (f == 2) fft_stages<2>(sm, twf, 1.0, N, p, L, s);
+            else fft_stages<1>(sm, twf, 1.0, N, p, L, s);
+            __syncthreads();
+            s += f;
+        }
+        // k-space step: point k of line (x, y) pairs with point -k of the mirror line
+        const int nxs = x < N / 2 ? (int)x : (int)x - (int)N, nys = y < N / 2 ? (int)y : (int)y - (int)N;
+        const double wxy = s2[x] * s2[y];
+        double2 outA[KMAX][ngrid], outB[KMAX][ngrid];
+#pragma unroll
+        for (uint32_t j = 0; j < KMAX; ++j) {
+            const uint32_t k = threadIdx.x + j * NT;
+            if (k < N) {
+                const uint32_t mk = (N - k) & m;
+                const uint32_t kr = __brev(k) >> (32 - p), mkr = __brev(mk) >> (32 - p);
+                const int nz = k < N / 2 ? (int)k : (int)k - (int)N;
+                const uint32_t q = (uint32_t)(nxs * nxs + nys * nys + nz * nz);
+                const double W = wxy * s2[k];
+                double2 Z[ngrid], Zm[ngrid];
+#pragma unroll
+                for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
+                    Z[g2] = sm[lds_swizzle((2 * g2) * N + kr)];
+                    Zm[g2] = sm[lds_swizzle((2 * g2 + 1) * N + mkr)];
+                }
+                green_point<D>(Z, Zm, gq + (uint64_t)q * U, U, 1.0 / (W * W), mix);
+#pragma unroll
+                for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
+                    outA[j][g2] = Z[g2];
+                    outB[j][g2] = Zm[g2];
+                }
+            }
+        }
+        __syncthreads();                  // every bit-reversed read is done
+#pragma unroll
+        for (uint32_t j = 0; j < KMAX; ++j) {
+            const uint32_t k = threadIdx.x + j * NT;
+            if (k < N) {
+                const uint32_t mk = (N - k) & m;
+#pragma unroll
+                for (uint32_t g2 = 0; g2 < ngrid; ++g2) {
+                    sm[lds_swizzle((2 * g2) * N + k)] = outA[j][g2];
+                    sm[lds_swizzle((2 * g2 + 1) * N + mk)] = outB[j][g2];
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t s = 0; s < p;) {
+            const uint32_t f = min(3u, p - s);
+            if (f == 3) fft_stages<3>(sm, twi, -1.0, N, p, L, s);
+            else if (f == 2) fft_stages<2>(sm, twi, -1.0, N, p, L, s);
+            else fft_stages<1>(sm, twi, -1.0, N, p, L, s);
+            __syncthreads();
+            s += f;
+        }
+        // read-out in natural order; a line that is its own mirror is written once
+#pragma unroll
+        for (uint32_t i = 0; i < EMAX; ++i) {
+            const uint32_t e = threadIdx.x + i * NT;
+            if (e < LN) {
+                const uint32_t l = e >> p, k = e & m;
+                if (self && (l & 1)) continue;
+                const uint32_t r = __brev(k) >> (32 - p);
+                mesh[(l >> 1) * N3 + ((l & 1) ? lb : la) + k] = sm[lds_swizzle(l * N + r)];
+            }
+        }
+        if (!more) break;
+        P = nP;
+        x = nx;
+        y = ny;
     }
 }
 
@@ -487,56 +642,81 @@ void pm_destroy(Context& ctx, PmPlan& pl)
     pl.tw = pl.mesh = nullptr;
 }
 
-static void fft3(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign)
+// One pass of 1-D transforms along y (axis 1) or x (axis 2) over every mesh.
+static void fft_axis(Context& ctx, PmPlan& pl, uint32_t ngrid, double sign, int axis)
 {
     const uint32_t N = pl.N;
-    // lines per workgroup: along z (contiguous lines) at least 1024 points; along
-    // y and x (lines adjacent in z) as many as fit kFftTileBytes, for longer
-    // contiguous runs: 8 lines at N = 1024 read whole 128-byte lines of memory
-    // (4 lines read half lines)
+    // lines per workgroup (adjacent in z): as many as fit kFftTileBytes, for
+    // longer contiguous runs: 8 lines at N = 1024 read whole 128-byte lines of
+    // memory (4 lines read half lines)
     const size_t tile_max = std::min(kFftTileBytes, ctx.lds_per_block - (N / 2) * sizeof(double2));
-    uint32_t T12 = 1;
-    while (T12 < 16 && (size_t)(2 * T12) * N * sizeof(double2) <= tile_max && 2 * T12 <= N * N) T12 *= 2;
-    const uint32_t T0 = std::min<uint32_t>(16, std::max<uint32_t>(1, 1024 / N));
-    for (int axis = 0; axis < 3; ++axis) {
-        const uint32_t T = axis == 0 ? T0 : T12;
-        uint32_t logT = 0;
-        while ((1u << logT) < T) ++logT;
-        const size_t lds = (size_t)T * N * sizeof(double2) + (N / 2) * sizeof(double2);
-        const uint64_t ntiles = (uint64_t)ngrid * ((uint64_t)N * N / T);
-        // 256 threads, 512 for tiles over 64 KiB (at most 16 elements a thread)
-        const uint32_t NT = (size_t)T * N * sizeof(double2) > 64 * 1024 ? 512 : 256;
-        const uint32_t ept = (T * N) / NT;
-        if ((T * N) % NT != 0 || ept < 1 || ept > 16 || (ept & (ept - 1)) != 0 || lds > ctx.lds_per_block)
-            fail(NGR_EINVAL, "pm: an FFT tile of " + std::to_string(T) + " lines of " + std::to_string(N) +
-                                 " points does not fit one workgroup");
-        // as many workgroups as fit on the device at once (LDS-bound), each looping over tiles
-        const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, ctx.lds_per_block / lds));
-        const uint64_t blocks = std::min<uint64_t>(ntiles, per_cu * (uint64_t)ctx.num_cu);
-        const dim3 grid((unsigned)blocks);
+    uint32_t T = 1;
+    while (T < 16 && (size_t)(2 * T) * N * sizeof(double2) <= tile_max && 2 * T <= N) T *= 2;
+    uint32_t logT = 0;
+    while ((1u << logT) < T) ++logT;
+    const size_t lds = (size_t)T * N * sizeof(double2) + (N / 2) * sizeof(double2);
+    const uint64_t ntiles = (uint64_t)ngrid * ((uint64_t)N * N / T);
+    // 256 threads, 512 for tiles over 64 KiB (at most 16 elements a thread)
+    const uint32_t NT = (size_t)T * N * sizeof(double2) > 64 * 1024 ? 512 : 256;
+    const uint32_t ept = (T * N) / NT;
+    if ((T * N) % NT != 0 || ept < 1 || ept > 16 || (ept & (ept - 1)) != 0 || (NT == 512 && ept != 16) ||
+        lds > ctx.lds_per_block)
+        fail(NGR_EINVAL, "pm: an FFT tile of " + std::to_string(T) + " lines of " + std::to_string(N) +
+                             " points does not fit one workgroup");
+    // as many workgroups as fit on the device at once (LDS-bound), each looping over tiles
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, ctx.lds_per_block / lds));
+    const uint64_t blocks = std::min<uint64_t>(ntiles, per_cu * (uint64_t)ctx.num_cu);
+    const dim3 grid((unsigned)blocks);
 #define NGR_FFT_LAUNCH(E, W)                                                                                        \
-    switch (axis) {                                                                                                  \
-    case 0: hipLaunchKernelGGL((fft_lines<E, W, 0>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,    \
-                               pl.tw, sign, ntiles); break;                                                          \
-    case 1: hipLaunchKernelGGL((fft_lines<E, W, 1>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,    \
-                               pl.tw, sign, ntiles); break;                                                          \
-    default: hipLaunchKernelGGL((fft_lines<E, W, 2>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT,   \
-                                pl.tw, sign, ntiles); break;                                                         \
-    }
-        if (NT == 512) {
-            NGR_FFT_LAUNCH(16, 512);
-        } else {
-            switch (ept) {
-            case 1: NGR_FFT_LAUNCH(1, 256); break;
-            case 2: NGR_FFT_LAUNCH(2, 256); break;
-            case 4: NGR_FFT_LAUNCH(4, 256); break;
-            case 8: NGR_FFT_LAUNCH(8, 256); break;
-            default: NGR_FFT_LAUNCH(16, 256); break;
-            }
+    if (axis == 1)                                                                                                   \
+        hipLaunchKernelGGL((fft_lines<E, W, 1>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT, pl.tw,  \
+                           sign, ntiles);                                                                            \
+    else                                                                                                             \
+        hipLaunchKernelGGL((fft_lines<E, W, 2>), grid, dim3(W), lds, ctx.stream, pl.mesh, N, pl.p, T, logT, pl.tw,  \
+                           sign, ntiles)
+    if (NT == 512) {
+        NGR_FFT_LAUNCH(16, 512);
+    } else {
+        switch (ept) {
+        case 1: NGR_FFT_LAUNCH(1, 256); break;
+        case 2: NGR_FFT_LAUNCH(2, 256); break;
+        case 4: NGR_FFT_LAUNCH(4, 256); break;
+        case 8: NGR_FFT_LAUNCH(8, 256); break;
+        default: NGR_FFT_LAUNCH(16, 256); break;
         }
-#undef NGR_FFT_LAUNCH
-        LAUNCH_CHECK("fft_lines");
     }
+#undef NGR_FFT_LAUNCH
+    LAUNCH_CHECK("fft_lines");
+}
+
+// The z transforms of both directions and the k-space step (pm_green_z).
+static void green_z(Context& ctx, PmPlan& pl, uint32_t ngrid)
+{
+    const uint32_t N = pl.N, D = pl.D;
+    const size_t lds = (size_t)(2 * ngrid * N + N) * sizeof(double2);
+    if (lds > ctx.lds_per_block)
+        fail(NGR_EINVAL, "pm: the k-space pass needs " + std::to_string(lds) + " bytes of LDS per workgroup");
+    PairMix mix{};
+    for (uint32_t ab = 0; ab < D * D; ++ab) {
+        mix.coef[ab] = pl.mix_coef[ab];
+        mix.table[ab] = pl.mix_table[ab];
+    }
+    const uint64_t npairs = (uint64_t)N * N / 2 + 2;
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(4, ctx.lds_per_block / lds));
+    const dim3 grid((unsigned)std::min<uint64_t>(npairs, per_cu * (uint64_t)ctx.num_cu)), block(kFusedThreads);
+#define NGR_GZ_LAUNCH(DD)                                                                                            \
+    hipLaunchKernelGGL(pm_green_z<DD>, grid, block, lds, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, pl.tw, mix, \
+                       npairs)
+    switch (D) {
+    case 1: NGR_GZ_LAUNCH(1); break;
+    case 2: NGR_GZ_LAUNCH(2); break;
+    case 3: NGR_GZ_LAUNCH(3); break;
+    case 4: NGR_GZ_LAUNCH(4); break;
+    case 5: NGR_GZ_LAUNCH(5); break;
+    default: NGR_GZ_LAUNCH(6); break;
+    }
+#undef NGR_GZ_LAUNCH
+    LAUNCH_CHECK("pm_green_z");
 }
 
 void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumulate, PmTimes* times)
@@ -557,26 +737,13 @@ void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumula
         LAUNCH_CHECK("pm_deposit");
     }
     HIP_CHECK(hipEventRecord(ev[1], ctx.stream));
-    fft3(ctx, pl, ngrid, 1.0);
+    fft_axis(ctx, pl, ngrid, 1.0, 2);
+    fft_axis(ctx, pl, ngrid, 1.0, 1);
     HIP_CHECK(hipEventRecord(ev[2], ctx.stream));
-    PairMix mix{};
-    for (uint32_t ab = 0; ab < D * D; ++ab) {
-        mix.coef[ab] = pl.mix_coef[ab];
-        mix.table[ab] = pl.mix_table[ab];
-    }
-    const uint64_t half = (uint64_t)(N / 2 + 1) * N * N;
-    const dim3 gg((unsigned)std::min<uint64_t>((half + 255) / 256, 64ull * ctx.num_cu));
-    switch (D) {
-    case 1: hipLaunchKernelGGL(pm_green<1>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    case 2: hipLaunchKernelGGL(pm_green<2>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    case 3: hipLaunchKernelGGL(pm_green<3>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    case 4: hipLaunchKernelGGL(pm_green<4>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    case 5: hipLaunchKernelGGL(pm_green<5>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    default: hipLaunchKernelGGL(pm_green<6>, gg, dim3(256), 0, ctx.stream, pl.mesh, pl.p, pl.U, pl.gq, pl.s2, mix); break;
-    }
-    LAUNCH_CHECK("pm_green");
+    green_z(ctx, pl, ngrid);
     HIP_CHECK(hipEventRecord(ev[3], ctx.stream));
-    fft3(ctx, pl, ngrid, -1.0);
+    fft_axis(ctx, pl, ngrid, -1.0, 1);
+    fft_axis(ctx, pl, ngrid, -1.0, 2);
     HIP_CHECK(hipEventRecord(ev[4], ctx.stream));
     if (n) {
         hipLaunchKernelGGL(pm_interp, dim3(gx, D), dim3(256), 0, ctx.stream, n, t.X, t.perm, seg, N, pl.p, 1.0 / h,
