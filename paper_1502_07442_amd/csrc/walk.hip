@@ -245,7 +245,7 @@ enum TableMode { kPair = 0, kValue = 1 };
 // Force-law and walk parameters of one box.
 struct BoxParams {
     double box, inv_box, eps2, R2, theta2;
-    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // 1.5 G_ab, row a = sink species, D x D
+    double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // G_ab, row a = sink species, D x D
     double* acc;               // 3 x n output, input order
     uint64_t in_off, n;        // first input index (over all boxes) and particles of the box
     const float2* pair;        // the box's tables, PAIR layout
@@ -379,14 +379,11 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
         }
         const double re2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));   // r^2 + eps^2
         const float sf = (float)re2;
+        // (r^2+eps^2)^(-3/2) in float32 from the hardware rsqrt: a relative
+        // error of a few 1e-7, the precision of the float32 table factor it
+        // multiplies (finite for r^2+eps^2 above ~2e-26)
         const float z = __builtin_amdgcn_rsqf(sf);
-        const double zd = (double)z;
-        const double z2 = zd * zd;
-        // with e = 1 - re2 z^2 (minus twice the relative error of z),
-        // (r^2+eps^2)^(-3/2) = z^3 (1 + 1.5 e) to ~1e-13; the records carry
-        // 1.5 G m, so the factor used is 5/3 - re2 z^2 = (1 + 1.5 e) / 1.5
-        const double e = fma(-re2, z2, 5.0 / 3.0);
-        const double z3 = z2 * zd;
+        const float z3 = z * z * z;
         float t;
         if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);                 // r^2 / h, from r^2 + eps^2
         else t = __builtin_sqrtf((float)(re2 - eps2)) * tscale;             // r / h
@@ -402,17 +399,15 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
             const float t0 = tv[k], t1 = tv[k + 1];
             f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
         }
-        const double p = (double)f * s.w * z3;
-        double coef = p * e;
+        double coef = (double)(f * z3) * s.w;                              // records carry G m
         if (EPS0) coef = re2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
         az = fma(coef, dz, az);
         if (EW) {
-            // the records carry 1.5 G m
             double cx, cy, cz;
             lattice_correction(lc.T, lc.n, lc.scale, dx, dy, dz, cx, cy, cz);
-            const double gm = s.w * (2.0 / 3.0);
+            const double gm = s.w;
             ax = fma(gm, cx, ax);
             ay = fma(gm, cy, ay);
             az = fma(gm, cz, az);
@@ -429,7 +424,7 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
 // Newtonian factor, so a pair without a core (s = 0) takes the softened law
 // from r -> sqrt(r^2 + eps^2). r and 1 / (s + r) come from the float32
 // hardware estimates refined by one float64 Newton step each. The records
-// carry G m (not 1.5 G m) and rs[] the source's core scale.
+// carry G m and rs[] the source's core scale.
 template <int GRID, int TAB, bool WRAP, uint32_t K>
 __device__ inline void eval_cored(const PairParams& A, double eps2, const double4* __restrict__ rec,
                                   const double* __restrict__ rs, uint32_t iters, const void* __restrict__ tbv,
@@ -659,7 +654,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     d1 -= rint(d1);
                     d2 -= rint(d2);
                     const uint32_t slot = (uint32_t)__popcll(m & lt);
-                    rec[slot] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w * (cp ? 2.0 / 3.0 : 1.0));
+                    rec[slot] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w);
                     if (cp) {
                         // a monopole of N_perp bodies: each of mass M / N_perp when tracked
                         double body = r.w;
@@ -748,7 +743,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 const bool cp = cored_pair(b);
                 if (sv) {
                     rec[lane] = make_double4((double)(int64_t)(sx - C0) * scale, (double)(int64_t)(sy - C1) * scale,
-                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm * (cp ? 2.0 / 3.0 : 1.0));
+                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm);
                     if (cp) recs[lane] = ((cmask >> b) & 1u) ? sm * inv4pib : 0.0;
                 }
                 if (K > 1u && (uint32_t)lane < 3u) {
@@ -1318,7 +1313,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             P.eps2_ab[ab] = law.eps_ab[ab] * law.eps_ab[ab];
             P.toff_ab[ab] = law.grid == NGR_GRID_R2 ? (float)(-P.eps2_ab[ab] * ((law.ntab - 1) / rc2)) : 0.0f;
         }
-        for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = 1.5 * law.G[j];   // see eval_records
+        for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = law.G[j];
         P.acc = accv[k];
         P.in_off = t.boff[k];
         P.n = t.boff[k + 1] - t.boff[k];
