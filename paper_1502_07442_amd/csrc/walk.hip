@@ -422,8 +422,8 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
 // 0.42 and 1.54 on [0, 1] and is read, linearly interpolated, from a table
 // of kCoreN intervals (relative error below 3e-7); C(1) = 1 gives the
 // Newtonian factor, so a pair without a core (s = 0) takes the softened law
-// from r -> sqrt(r^2 + eps^2). r and 1 / (s + r) come from the float32
-// hardware estimates refined by one float64 Newton step each. The records
+// from r -> sqrt(r^2 + eps^2). r and 1 / (s + r) are the float32 hardware
+// estimates (rsqrt times r^2, reciprocal). The records
 // carry G m and rs[] the source's core scale.
 template <int GRID, int TAB, bool WRAP, uint32_t K>
 __device__ inline void eval_cored(const PairParams& A, double eps2, const double4* __restrict__ rec,
@@ -431,7 +431,7 @@ __device__ inline void eval_cored(const PairParams& A, double eps2, const double
                                   const float2* __restrict__ core, double s_sink, double ox, double oy, double oz,
                                   double& ax, double& ay, double& az)
 {
-    const float tscale = A.tscale, tmax = A.tmax;
+    const float tscale = A.tscale, tmax = A.tmax, eps2f = (float)eps2;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
     for (uint32_t it = 0; it < iters; ++it) {
         const double4 s = rec[it * K];
@@ -443,14 +443,13 @@ __device__ inline void eval_cored(const PairParams& A, double eps2, const double
             dz -= A.box * rint(dz * A.inv_box);
         }
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const double re2 = sc > 0.0 ? r2 : r2 + eps2;
-        const double z = (double)__builtin_amdgcn_rsqf((float)re2);
-        const double h = re2 * z;                          // r estimate
-        const double rr = h * fma(-0.5 * h, z, 1.5);       // one Newton step on 1 / sqrt
-        const double wd = sc + rr;
-        double y = (double)__builtin_amdgcn_rcpf((float)wd);
-        y = y * fma(-wd, y, 2.0);                          // one Newton step on 1 / w
-        float tu = (float)(rr * y) * (float)kCoreN;
+        // float32 from here: r and 1 / (s + r) from the hardware estimates,
+        // a relative error of a few 1e-7, the precision of the float32 tables
+        const float r2f = (float)r2, scf = (float)sc;
+        const float re2 = scf > 0.0f ? r2f : r2f + eps2f;
+        const float rr = re2 * __builtin_amdgcn_rsqf(re2);         // r (softened when s = 0)
+        const float y = __builtin_amdgcn_rcpf(scf + rr);           // 1 / (s + r)
+        float tu = rr * y * (float)kCoreN;
         tu = __builtin_amdgcn_fmed3f(tu, 0.0f, (float)kCoreN);
         // r = 0 makes tu NaN (its term is dropped below): the unsigned clamp
         // keeps the index inside the table whatever the conversion gives
@@ -472,8 +471,7 @@ __device__ inline void eval_cored(const PairParams& A, double eps2, const double
             const float t0 = tv[k], t1 = tv[k + 1];
             f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
         }
-        const double y3 = y * y * y;
-        double coef = (double)(f * c) * s.w * y3;
+        double coef = (double)(f * c * (y * y * y)) * s.w;
         coef = r2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
@@ -585,7 +583,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         const uint32_t K = 1u << lk;
         const uint32_t sink = (uint32_t)lane & ((64u >> lk) - 1u), replica = (uint32_t)lane >> (6u - lk);
         const double4* const rrec = rec + replica;
-        const double4 pad = make_double4(1e30, 1e30, 1e30, 0.0);
+        // a million boxes away: past every cut-off (the table factor is 0), yet
+        // r^2 stays finite in float32 for boxes below ~1e13
+        const double4 pad = make_double4(1e6 * bx, 1e6 * bx, 1e6 * bx, 0.0);
         double ox = 0.0, oy = 0.0, oz = 0.0;
         if (sink < ns) {
             uint64_t i = s0 + sink;
