@@ -20,9 +20,9 @@
 // (value, slope) pairs and are read by a per-lane gather.
 //
 // Arithmetic per pair: offsets, r^2 and the accumulation in float64 (full
-// rate on the vector ALU, like unpacked float32), the table interpolation in
-// float32, and (r^2 + eps^2)^(-3/2) from the float32 reciprocal square root
-// refined by one float64 correction step.
+// rate on the vector ALU, like unpacked float32); the table interpolation and
+// (r^2 + eps^2)^(-3/2), the cube of the hardware reciprocal square root, in
+// float32.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
