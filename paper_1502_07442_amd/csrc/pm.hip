@@ -53,6 +53,13 @@ __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x *
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
+// Mesh layout: point (x, y, z) of a mesh at x XS + y N + z, XS = (N + 1) N,
+// and mesh g at g N XS. The unused row y = N pads every x plane by N points:
+// the N points of a line along x are then (N + 1) N apart rather than N^2 (a
+// power of two, 16 MiB at N = 1024, which put them all on one HBM channel).
+__host__ __device__ inline uint64_t plane_stride(uint32_t p) { return ((1ull << p) + 1ull) << p; }
+__host__ __device__ inline uint64_t mesh_stride(uint32_t p) { return plane_stride(p) << p; }
+
 // Lower grid index and fraction along one axis of a lattice coordinate:
 // u = X N 2^-64 exactly (N = 2^p).
 __device__ inline void cic_axis(uint64_t X, uint32_t p, uint32_t& i, double& f)
@@ -69,8 +76,8 @@ __global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const dou
 {
     const uint32_t b = blockIdx.y;
     const uint64_t s0 = seg[b], s1 = seg[b + 1];
-    const uint64_t N3 = (uint64_t)N * N * N;
-    double* m = mesh + 2 * N3 * (b / 2) + (b & 1);
+    const uint64_t XS = plane_stride(p);
+    double* m = mesh + 2 * mesh_stride(p) * (b / 2) + (b & 1);
     const uint32_t mask = N - 1;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = s0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s1; i += stride) {
@@ -84,7 +91,7 @@ __global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const dou
         for (int c = 0; c < 8; ++c) {
             const uint32_t cx = (ix + (c >> 2)) & mask, cy = (iy + ((c >> 1) & 1)) & mask, cz = (iz + (c & 1)) & mask;
             const double wt = w * ((c >> 2) ? fx : 1.0 - fx) * (((c >> 1) & 1) ? fy : 1.0 - fy) * ((c & 1) ? fz : 1.0 - fz);
-            unsafeAtomicAdd(m + 2 * (((uint64_t)cx * N + cy) * N + cz), wt);
+            unsafeAtomicAdd(m + 2 * ((uint64_t)cx * XS + (uint64_t)cy * N + cz), wt);
         }
     }
 }
@@ -181,7 +188,7 @@ __device__ __forceinline__ uint64_t tile_origin(uint64_t it, uint32_t p, uint32_
     if (AXIS == 1) {
         const uint64_t line0 = tile << logT;   // T consecutive lines in the (x, z) plane, z fastest
         const uint64_t x = line0 >> p, z = line0 & (N - 1);
-        l0 = (x << (2 * p)) + z;
+        l0 = x * plane_stride(p) + z;
     } else {
         // T lines adjacent in z at one y; consecutive tiles step y first, so
         // the workgroups running at once read rows of many different y (16
@@ -189,7 +196,7 @@ __device__ __forceinline__ uint64_t tile_origin(uint64_t it, uint32_t p, uint32_
         const uint64_t y = tile & (N - 1), z = (tile >> p) << logT;
         l0 = (y << p) + z;
     }
-    return (g << (3 * p)) + l0;
+    return g * mesh_stride(p) + l0;
 }
 
 // The real and imaginary parts go to separate register arrays: an array of
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(NT) void fft_lines(double2* __restrict__ data, uint
         tw[k] = make_double2(w.x, sign * w.y);
     }
     // distance between a tile's lines and between a line's points
-    const uint64_t lstep = 1, stride = AXIS == 1 ? N : (uint64_t)N * N;
+    const uint64_t lstep = 1, stride = AXIS == 1 ? (uint64_t)N : plane_stride(p);
     double rx[EPT], ry[EPT];
     uint64_t it = blockIdx.x;
     if (it < ntiles) load_tile<EPT, NT, AXIS>(rx, ry, data + tile_origin<AXIS>(it, p, logT), p, T, logT, lstep, stride);
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict_
     constexpr uint32_t EMAX = (L * 1024 + NT - 1) / NT;   // elements per thread at N = 1024
     constexpr uint32_t KMAX = (1024 + NT - 1) / NT;       // points per thread in the k-space step
     const uint32_t N = 1u << p, m = N - 1u, LN = L * N;
-    const uint64_t N3 = 1ull << (3 * p);
+    const uint64_t MS = mesh_stride(p), XS = plane_stride(p);
     HIP_DYNAMIC_SHARED(double2, sm);
     double2* twf = sm + (size_t)LN;       // forward twiddles
     double2* twi = twf + N / 2;           // conjugated, for the inverse
@@ -376,13 +383,13 @@ __global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict_
     mirror_pair(P, p, x, y);
     double rx[EMAX], ry[EMAX];
     {
-        const uint64_t la = (((uint64_t)x << p) | y) << p, lb = ((((uint64_t)((N - x) & m)) << p) | ((N - y) & m)) << p;
+        const uint64_t la = x * XS + ((uint64_t)y << p), lb = ((N - x) & m) * XS + ((uint64_t)((N - y) & m) << p);
 #pragma unroll
         for (uint32_t i = 0; i < EMAX; ++i) {
             const uint32_t e = threadIdx.x + i * NT;
             if (e < LN) {
                 const uint32_t l = e >> p, k = e & m;
-                const double2 v = mesh[(l >> 1) * N3 + ((l & 1) ? lb : la) + k];
+                const double2 v = mesh[(l >> 1) * MS + ((l & 1) ? lb : la) + k];
                 rx[i] = v.x;
                 ry[i] = v.y;
             }
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict_
     for (;;) {
         const uint32_t mx = (N - x) & m, my = (N - y) & m;
         const bool self = mx == x && my == y;
-        const uint64_t la = (((uint64_t)x << p) | y) << p, lb = (((uint64_t)mx << p) | my) << p;
+        const uint64_t la = x * XS + ((uint64_t)y << p), lb = mx * XS + ((uint64_t)my << p);
         __syncthreads();                  // the previous pair's read-out is done (and the twiddles are in)
 #pragma unroll
         for (uint32_t i = 0; i < EMAX; ++i) {
@@ -404,14 +411,14 @@ __global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict_
         uint32_t nx, ny;
         mirror_pair(more ? nP : P, p, nx, ny);
         if (more) {
-            const uint64_t na = (((uint64_t)nx << p) | ny) << p,
-                           nb = ((((uint64_t)((N - nx) & m)) << p) | ((N - ny) & m)) << p;
+            const uint64_t na = nx * XS + ((uint64_t)ny << p),
+                           nb = ((N - nx) & m) * XS + ((uint64_t)((N - ny) & m) << p);
 #pragma unroll
             for (uint32_t i = 0; i < EMAX; ++i) {
                 const uint32_t e = threadIdx.x + i * NT;
                 if (e < LN) {
                     const uint32_t l = e >> p, k = e & m;
-                    const double2 v = mesh[(l >> 1) * N3 + ((l & 1) ? nb : na) + k];
+                    const double2 v = mesh[(l >> 1) * MS + ((l & 1) ? nb : na) + k];
                     rx[i] = v.x;
                     ry[i] = v.y;
                 }
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(kFusedThreads) void pm_green_z(double2* __restrict_
                 const uint32_t l = e >> p, k = e & m;
                 if (self && (l & 1)) continue;
                 const uint32_t r = __brev(k) >> (32 - p);
-                mesh[(l >> 1) * N3 + ((l & 1) ? lb : la) + k] = sm[lds_swizzle(l * N + r)];
+                mesh[(l >> 1) * MS + ((l & 1) ? lb : la) + k] = sm[lds_swizzle(l * N + r)];
             }
         }
         if (!more) break;
@@ -501,11 +508,11 @@ __global__ void pm_interp(uint64_t n, const uint64_t* __restrict__ X, const uint
 {
     const uint32_t a = blockIdx.y;
     const uint64_t s0 = seg[a], s1 = seg[a + 1];
-    const uint64_t N3 = (uint64_t)N * N * N;
-    const double* m = mesh + 2 * N3 * (a / 2) + (a & 1);
+    const uint64_t XS = plane_stride(p);
+    const double* m = mesh + 2 * mesh_stride(p) * (a / 2) + (a & 1);
     const uint32_t mask = N - 1;
     auto P = [&](uint32_t x, uint32_t y, uint32_t z) {
-        return m[2 * (((uint64_t)(x & mask) * N + (y & mask)) * N + (z & mask))];
+        return m[2 * ((uint64_t)(x & mask) * XS + (uint64_t)(y & mask) * N + (z & mask))];
     };
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = s0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s1; i += stride) {
@@ -604,7 +611,7 @@ void pm_create(Context& ctx, const ngr_pm_params& pp, const double* G, const dou
     pl.gq = static_cast<double*>(ctx.alloc(gq_bytes));
     pl.s2 = static_cast<double*>(ctx.alloc(N * sizeof(double)));
     pl.tw = static_cast<double2*>(ctx.alloc((N / 2) * sizeof(double2)));
-    pl.mesh = static_cast<double2*>(ctx.alloc((size_t)((D + 1) / 2) * N * N * N * sizeof(double2)));
+    pl.mesh = static_cast<double2*>(ctx.alloc((size_t)((D + 1) / 2) * mesh_stride(pl.p) * sizeof(double2)));
     // host tables: sinc^2 per grid index (signed frequency), twiddles exp(-2 pi i m / N)
     std::vector<double> s2(N);
     for (uint32_t i = 0; i < N; ++i) {
@@ -722,14 +729,14 @@ static void green_z(Context& ctx, PmPlan& pl, uint32_t ngrid)
 void pm_force(Context& ctx, PmPlan& pl, const Tree& t, double* acc, int accumulate, PmTimes* times)
 {
     const uint32_t N = pl.N, D = pl.D, ngrid = (D + 1) / 2;
-    const uint64_t n = t.n, N3 = (uint64_t)N * N * N;
+    const uint64_t n = t.n;
     const double h = pl.box / N;
     hipEvent_t ev[6];
     for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
     HIP_CHECK(hipEventRecord(ev[0], ctx.stream));
     uint64_t* seg = static_cast<uint64_t*>(ctx.alloc((NGR_MAX_SPECIES + 1) * sizeof(uint64_t)));
     ctx.to_device(seg, t.seg, (NGR_MAX_SPECIES + 1) * sizeof(uint64_t));
-    HIP_CHECK(hipMemsetAsync(pl.mesh, 0, (size_t)ngrid * N3 * sizeof(double2), ctx.stream));
+    HIP_CHECK(hipMemsetAsync(pl.mesh, 0, (size_t)ngrid * mesh_stride(pl.p) * sizeof(double2), ctx.stream));
     const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096));
     if (n) {
         hipLaunchKernelGGL(pm_deposit, dim3(gx, D), dim3(256), 0, ctx.stream, n, t.X, t.mass, seg, N, pl.p,
