@@ -49,6 +49,27 @@ def walk_traffic():
     return float(fields["walk_traffic_bytes"])
 
 
+def pm_traffic():
+    """HBM bytes per launch of the PM's forward x and y passes (together) and
+    of the fused z pass, from the committed rocprofv3 counter summary, or None
+    when the PM source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pm_mesh1024_2p24_D6_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        k, _, v = line.strip().partition(": ")
+        if k in ("fft_xy_traffic_bytes", "green_z_traffic_bytes", "source_sha256"):
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1502_07442_amd", "csrc", "pm.hip"), "rb") as fh:
+        h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or len(fields) != 3:
+        return None
+    return float(fields["fft_xy_traffic_bytes"]), float(fields["green_z_traffic_bytes"])
+
+
 def batched(ngr, synth, nbox=256, reps=3):
     """The many-box workload: nbox independent boxes in one
     ngr_batch_build_force call (group size chosen by the library), against
@@ -368,13 +389,14 @@ def pm_leg(ngr, synth, p, tensors, reps=3):
     fft_ms = st["ms_fft_forward"]
     achieved = fft_bytes / (fft_ms * 1e-3) / 1e9
     fused = sweep / (st["ms_green"] * 1e-3) / 1e9       # z transforms and the k-space step, one sweep
+    traffic = pm_traffic() if N == 1024 and p.D == 6 else None
     return {"workload": f"PM of the benchmark box: {p.n} particles, {p.D} species, mesh {N}^3, "
                         f"{ngrid} complex float64 meshes", "N": N, "ms_per_force": float(np.median(walls)) * 1e3,
             "plan_ms": t_plan * 1e3, **st,
             "fft_roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                             "frac": achieved / 8000.0, "traffic": None},
+                             "frac": achieved / 8000.0, "traffic": traffic[0] if traffic else None},
             "green_z_roofline": {"bound": "hbm", "achieved": fused, "peak": 8000.0, "unit": "GB/s",
-                                 "frac": fused / 8000.0, "traffic": None}}
+                                 "frac": fused / 8000.0, "traffic": traffic[1] if traffic else None}}
 
 
 def cpu_baseline(p, gpu_counts, seconds):
