@@ -367,6 +367,12 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
                                     uint32_t iters, const void* __restrict__ tbv, double ox, double oy, double oz,
                                     double& ax, double& ay, double& az, LatticeCorr lc = LatticeCorr{nullptr, 0u, 0.0})
 {
+    // a launch that holds unsoftened pairs evaluates its softened pairs exactly
+    // as a launch without any (a box in a batch equals its single-box call)
+    if (EPS0 && eps2 != 0.0) {
+        eval_records<GRID, TAB, false, WRAP, K, EW>(A, eps2, toff, rec, iters, tbv, ox, oy, oz, ax, ay, az, lc);
+        return;
+    }
     const float tscale = A.tscale, tmax = A.tmax;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
     for (uint32_t it = 0; it < iters; ++it) {
@@ -381,9 +387,19 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
         const float sf = (float)re2;
         // (r^2+eps^2)^(-3/2) in float32 from the hardware rsqrt: a relative
         // error of a few 1e-7, the precision of the float32 table factor it
-        // multiplies (finite for r^2+eps^2 above ~2e-26)
+        // multiplies (finite for r^2+eps^2 above ~2e-26). Without softening
+        // (EPS0, reached only for pairs with eps = 0) a pair can be closer
+        // than that: there the cube is taken in float64 and refined (with
+        // e = 1 - re2 z^2, z^3 (1 + 1.5 e) to ~1e-13).
         const float z = __builtin_amdgcn_rsqf(sf);
-        const float z3 = z * z * z;
+        float z3 = 0.0f;
+        double z3d = 0.0;
+        if (EPS0) {
+            const double zd = (double)z, z2 = zd * zd;
+            z3d = z2 * zd * fma(-1.5 * re2, z2, 2.5);
+        } else {
+            z3 = z * z * z;
+        }
         float t;
         if (GRID == NGR_GRID_R2) t = fmaf(sf, tscale, toff);                 // r^2 / h, from r^2 + eps^2
         else t = __builtin_sqrtf((float)(re2 - eps2)) * tscale;             // r / h
@@ -399,7 +415,7 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
             const float t0 = tv[k], t1 = tv[k + 1];
             f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
         }
-        double coef = (double)(f * z3) * s.w;                              // records carry G m
+        double coef = EPS0 ? (double)f * s.w * z3d : (double)(f * z3) * s.w;   // records carry G m
         if (EPS0) coef = re2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
