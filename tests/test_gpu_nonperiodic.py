@@ -60,9 +60,9 @@ def test_no_images(ctx):
                       eps=0.0, theta=0.5, pos=pos, periodic=False)
     acc = gpu_solve(ctx, p)[0]
     d = 0.95
-    # the pair's kernel factor (r^2)^(-3/2) is float32 from the hardware
-    # rsqrt (a few 1e-7); the image through the face would give -1 / 0.05^2
-    assert acc[0, 0] == pytest.approx(1 / d ** 2, rel=1e-6) and acc[0, 1] == pytest.approx(-1 / d ** 2, rel=1e-6)
+    # eps = 0: the pair's kernel factor is the float64-refined one (~1e-13);
+    # the image through the face would give -1 / 0.05^2
+    assert acc[0, 0] == pytest.approx(1 / d ** 2, rel=1e-12) and acc[0, 1] == pytest.approx(-1 / d ** 2, rel=1e-12)
 
 
 def test_batch_with_periodic_box(ctx):
