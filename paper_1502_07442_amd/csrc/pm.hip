@@ -97,14 +97,14 @@ __global__ void pm_deposit(uint64_t n, const uint64_t* __restrict__ X, const dou
 }
 
 // Batched 1-D FFTs of length N = 2^p along one axis of ngrid complex meshes
-// of N^3 points (index (x N + y) N + z). A workgroup transforms T lines:
-// line l of the batch starts at line_base(l) and its elements are `stride`
-// apart. Radix-2 decimation in frequency in place in LDS, natural order in,
-// bit-reversed order read out. sign = +1: exp(-2 pi i k n / N) (forward),
-// -1: exp(+2 pi i k n / N) (inverse, unnormalised).
-// The LDS holds T lines of N points and the N / 2 twiddles.
-// axis 1: along y (stride N), a tile's lines adjacent in z;
-// axis 2: along x (stride N^2), a tile's lines adjacent in z.
+// (point (x, y, z) at x XS + y N + z, XS = (N + 1) N). A workgroup
+// transforms a tile of T lines adjacent in z. Radix-2 decimation in frequency
+// in place in LDS, natural order in, bit-reversed order read out.
+// sign = +1: exp(-2 pi i k n / N) (forward), -1: exp(+2 pi i k n / N)
+// (inverse, unnormalised). The LDS holds T lines of N points and the N / 2
+// twiddles.
+// axis 1: along y (points N apart);
+// axis 2: along x (points XS apart).
 // The z transforms (contiguous lines) run inside the k-space pass
 // (pm_green_z).
 
