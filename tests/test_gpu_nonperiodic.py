@@ -1,8 +1,9 @@
 """Non-periodic boxes (section 2: isolated runs use the tree alone) on the
 HIP path against the oracle on the same padded lattice: bit-exact lattice and
-tree, exact counts, the force gate, full-range laws; a non-periodic box in a
-batch with a periodic one; positions outside the box, lattice input and a PM
-force on such a tree are refused."""
+tree, exact counts, the force gate, full-range laws; two bodies with no
+softening, far apart and 1e-14 apart; a non-periodic box in a batch with a
+periodic one; positions outside the box, lattice input and a PM force on such
+a tree are refused."""
 import dataclasses
 import math
 
@@ -62,6 +63,22 @@ def test_no_images(ctx):
     d = 0.95
     # eps = 0: the pair's kernel factor is the float64-refined one (~1e-13);
     # the image through the face would give -1 / 0.05^2
+    assert acc[0, 0] == pytest.approx(1 / d ** 2, rel=1e-12) and acc[0, 1] == pytest.approx(-1 / d ** 2, rel=1e-12)
+
+
+def test_unsoftened_close_pair(ctx):
+    """Without softening two bodies 1e-14 apart attract with 1/d^2 ~ 1e28:
+    their (r^2)^(-3/2) ~ 1e42 is beyond float32, and the unsoftened kernel
+    takes it in float64 (d from the lattice the tree quantises to)."""
+    pos = np.array([[0.5, 0.5, 0.5], [0.5 + 1e-14, 0.5, 0.5]]).T.copy()
+    p = synth.Problem(name="close-two", n=2, D=1, box=1.0, species=np.zeros(2, np.uint8), mass=np.ones(2),
+                      G=np.ones((1, 1)), tables=np.ones((1, 1, 16)), grid=synth.GRID_R, r_s=0.0, r_cut=1.75,
+                      eps=0.0, theta=0.5, pos=pos, periodic=False)
+    X = oracle.lattice_of(p).astype(np.float64)
+    d = (X[0, 1] - X[0, 0]) * oracle.box_of(p) * 2.0 ** -64
+    assert 5e-15 < d < 2e-14
+    acc = gpu_solve(ctx, p)[0]
+    assert np.all(np.isfinite(acc))
     assert acc[0, 0] == pytest.approx(1 / d ** 2, rel=1e-12) and acc[0, 1] == pytest.approx(-1 / d ** 2, rel=1e-12)
 
 
