@@ -4,7 +4,8 @@
 One step is the whole hot path on one batch of particles already resident in
 HBM: lattice and keys, sort, octree, per-species monopoles, groups and the
 tree walk (ngr_tree_build + ngr_compute_monopoles + ngr_tree_force), for the
-clustered 2^24-particle, six-species box. Prints one JSON line.
+clustered 2^24-particle, six-species box (2000 Plummer halos, as at 2^21).
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -399,9 +400,13 @@ def pm_leg(ngr, synth, p, tensors, reps=3):
                                  "frac": fused / 8000.0, "traffic": traffic[1] if traffic else None}}
 
 
-def cpu_baseline(p, gpu_counts, seconds):
-    """The FP64 oracle on a bounded, seeded sample of groups of the same
-    workload: interactions per second of its walk on the host cores."""
+def cpu_baseline(p, gpu_group_counts, gpu_acc, seconds, gpu_acc_relative=None):
+    """The CPU-baseline leg, the one place the benchmark runs the oracle.
+    (1) The FP64 oracle on a bounded, seeded sample of groups of the same
+    workload: interactions per second of its walk on the host cores; the
+    oracle's per-group counts of the sample must equal the GPU's. (2) With
+    the GPU's accelerations, the accuracy measure below. Returns (baseline,
+    accuracy or None)."""
     import numpy as np
 
     import oracle
@@ -412,19 +417,129 @@ def cpu_baseline(p, gpu_counts, seconds):
     rng = np.random.default_rng(7)
     order = rng.permutation(T.n_groups).astype(np.uint32)
     # grow a seeded random sample of groups until it takes about `seconds`
-    take, dt, c1 = 64, 0.0, None
+    take, dt, c1, gc = 64, 0.0, None, None
     while True:
         sample = np.sort(order[:take])
         t0 = time.time()
-        _, _, c1, _ = T.force(law, groups=sample)
+        _, _, c1, gc = T.force(law, groups=sample, group_counts=True)
         dt = time.time() - t0
         if dt >= 0.5 * seconds or take >= T.n_groups:
             break
         take = int(min(T.n_groups, take * max(2.0, min(16.0, seconds / max(dt, 1e-3)))))
+    if gpu_group_counts is not None and not np.array_equal(gpu_group_counts[sample], gc):
+        raise SystemExit("the oracle's per-group interaction counts differ from the GPU's on the sample")
     inter = c1["pp"] + c1["pn"]
-    return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{take} of {T.n_groups} groups (seeded random), {inter} interactions in {dt:.1f} s; "
-                      f"oracle tree build {build_s:.1f} s not included"}
+    base = {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{take} of {T.n_groups} groups (seeded random), {inter} interactions in {dt:.1f} s, "
+                      f"per-group counts equal to the GPU's; oracle tree build {build_s:.1f} s not included"}
+    del T
+    return base, (accuracy(p, gpu_acc, gpu_acc_relative) if gpu_acc is not None else None)
+
+
+def accuracy(p, acc_gpu, acc_gpu_relative=None, nsinks=2 ** 16, alpha=0.005):
+    """The paper's force-error measure (Eq. (12)): Delta f / f =
+    |a_tree - a_direct| / |a_direct| of the GPU tree force against the
+    oracle's minimum-image direct sum on a seeded sample of sinks; its 99th
+    percentile against the tree tolerance alpha of the transition tests, for
+    the theta = 0.5 force and the relative criterion's force."""
+    import numpy as np
+
+    import oracle
+    sinks = np.sort(np.random.default_rng(11).choice(p.n, min(nsinks, p.n), replace=False)).astype(np.uint32)
+    t0 = time.time()
+    ad, _ = oracle.direct_of(p, sinks)
+    dt = time.time() - t0
+    nrm = np.linalg.norm(ad, axis=0)
+    keep = nrm > 0
+    e = np.linalg.norm(acc_gpu[:, sinks] - ad, axis=0)[keep] / nrm[keep]
+    q = float(np.percentile(e, 99))
+    out = {"p99_rel_err_tree_vs_direct": q, "median_rel_err": float(np.median(e)), "alpha": alpha,
+           "within_alpha": q <= alpha, "sinks": int(keep.sum()), "sinks_zero_direct_force": int((~keep).sum()),
+           "direct_sum_s": dt}
+    if acc_gpu_relative is not None:
+        er = np.linalg.norm(acc_gpu_relative[:, sinks] - ad, axis=0)[keep] / nrm[keep]
+        qr = float(np.percentile(er, 99))
+        out["relative_criterion"] = {"p99_rel_err_tree_vs_direct": qr, "median_rel_err": float(np.median(er)),
+                                     "within_alpha": qr <= alpha}
+    return out
+
+
+def copy_calibration(gib=1, reps=3):
+    """Device copies of a known size, for scaling rocprofv3's FETCH_SIZE and
+    WRITE_SIZE counters to bytes (profile this run with --pmc)."""
+    import torch
+    n = gib * (1 << 30)
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_per_copy": n, "copies": reps}}), flush=True)
+
+
+def run_box(ngr, p, steps, warmup, tag, relative=None):
+    """Steps (build + monopoles + force) of one box with inputs resident:
+    (ms per step, interactions per step, mean walk ms, mean build ms, mean
+    monopoles ms, last stats)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(p.pos).to(dev)
+    species = torch.from_numpy(p.species).to(dev)
+    mass = torch.from_numpy(p.mass).to(dev)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ctx = ngr.Context(0)
+
+    def step(counts=False):
+        tree = ngr.tree_build(ctx, D=p.D, box=p.box, pos=pos, species=species, mass=mass, leaf_size=p.leaf_size)
+        ngr.compute_monopoles(ctx, tree)
+        st = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
+                            theta=p.theta, group_size=p.group_size, acc=acc, group_counts=counts,
+                            relative=relative)
+        ngr.tree_free(ctx, tree)
+        return st
+
+    for i in range(warmup):
+        st = step()
+        log(f"{tag} warmup {i}: walk {st['ms_walk']:.2f} ms, interactions {st['interactions_pp'] + st['interactions_pn']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(steps):
+        stats.append(step())
+        log(f"{tag} step {i}: walk {stats[-1]['ms_walk']:.2f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    inter = stats[-1]["interactions_pp"] + stats[-1]["interactions_pn"]
+    assert all(s["interactions_pp"] + s["interactions_pn"] == inter for s in stats)
+    mean = lambda k: float(np.mean([s[k] for s in stats]))
+    return dict(ctx=ctx, acc=acc, step=step, tensors=dict(pos=pos, species=species, mass=mass), stats=stats,
+                ms_per_step=ms_per_step, inter=inter, ms_walk=mean("ms_walk"), ms_build=mean("ms_build"),
+                ms_monopoles=mean("ms_monopoles"), ms_groups=mean("ms_groups"), last=stats[-1])
+
+
+def build_roofline(st, n):
+    """Achieved HBM bandwidth of the build phases on their algorithmic bytes
+    (device time of each phase from the library's events, host read-backs
+    between levels included): ingest (read position 24 B, species 1 B, mass
+    8 B; write lattice 24 B, key 8 B, index 4 B, mass 8 B), the sort (eight
+    8-bit passes, each reading and writing key and index, 24 B, and reading
+    the key again for the histogram, 8 B) with the one reordering (read the
+    index 4 B, gather lattice and mass 32 B, write them 32 B), and the
+    monopoles (read every particle's lattice and mass once, 32 B, plus
+    32 B per node and species read and written)."""
+    ingest = 77.0 * n
+    sort = (8 * 32.0 + 68.0) * n
+    mono = 32.0 * n + 2 * 32.0 * st["n_nodes"] * 6
+    gbps = lambda b, ms: b / (ms * 1e-3) / 1e9 if ms > 0 else None
+    return {"ingest_gbps": gbps(ingest, st["ms_build_ingest"]), "sort_and_gather_gbps": gbps(sort, st["ms_build_sort"]),
+            "monopoles_gbps": gbps(mono, st["ms_monopoles"]), "peak_gbps": 8000.0,
+            "ms_ingest": st["ms_build_ingest"], "ms_sort_and_gather": st["ms_build_sort"],
+            "ms_octree": st["ms_build_octree"], "ms_monopoles": st["ms_monopoles"], "ms_groups": st["ms_groups"]}
 
 
 def main():
@@ -435,58 +550,37 @@ def main():
     ap.add_argument("--n", type=int, default=2 ** 24, help="particles (the benchmark workload is 2^24)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-accumulator", action="store_true")
     ap.add_argument("--no-pm", action="store_true")
+    ap.add_argument("--no-scaled", action="store_true", help="skip the box with the halo count scaled with n")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run device copies of 1 GiB (to scale rocprofv3 byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the path is built and "
               f"measured for one MI355X", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
-    import torch
 
     import paper_1502_07442_amd as ngr
     import synth
 
-    log(f"generating the clustered workload n={args.n}")
+    log(f"generating the clustered workload n={args.n} (2000 halos)")
     p = synth.clustered_d6(3, n=args.n)
-    dev = torch.device("cuda", 0)
-    pos = torch.from_numpy(p.pos).to(dev)
-    species = torch.from_numpy(p.species).to(dev)
-    mass = torch.from_numpy(p.mass).to(dev)
-    acc = torch.empty((3, p.n), dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    ctx = ngr.Context(0)
-
-    def step():
-        tree = ngr.tree_build(ctx, D=p.D, box=p.box, pos=pos, species=species, mass=mass, leaf_size=p.leaf_size)
-        ngr.compute_monopoles(ctx, tree)
-        st = ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps,
-                            theta=p.theta, group_size=p.group_size, acc=acc)
-        ngr.tree_free(ctx, tree)
-        return st
-
-    for i in range(args.warmup):
-        st = step()
-        log(f"warmup {i}: walk {st['ms_walk']:.2f} ms, interactions {st['interactions_pp'] + st['interactions_pn']}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        stats.append(step())
-        log(f"step {i}: walk {stats[-1]['ms_walk']:.2f} ms")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    inter = stats[-1]["interactions_pp"] + stats[-1]["interactions_pn"]
-    assert all(s["interactions_pp"] + s["interactions_pn"] == inter for s in stats)
-    ms_walk = float(np.mean([s["ms_walk"] for s in stats]))
+    r = run_box(ngr, p, args.steps, args.warmup, "H2000")
+    ctx, acc, inter = r["ctx"], r["acc"], r["inter"]
+    ms_per_step, ms_walk = r["ms_per_step"], r["ms_walk"]
     # the walk is one launch per step (every sink species), timed with HIP events on its stream
     achieved = FLOPS_PER_INTERACTION * inter / (ms_walk * 1e-3) / 1e12
+    last = r["last"]
     out = {
         "metric": "tree-force interactions/s at 2^24,D=6; batched boxes/s + p50/p99 latency",
         "value": inter / (ms_per_step * 1e-3),
@@ -498,17 +592,53 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "mixed: f64 positions, offsets, r^2 and sums; f32 kernel factor and table lerp",
         "data": "synthetic",
-        "config": {"workload": f"clustered box, {p.n} particles, {p.D} species (Plummer halos + uniform)",
-                   "n": p.n, "D": p.D, "theta": p.theta, "ntab": p.ntab, "grid": p.grid, "leaf_size": p.leaf_size,
-                   "group_size": p.group_size, "r_cut": p.r_cut, "eps": p.eps, "seed": p.seed},
+        "config": {"workload": f"clustered box, {p.n} particles, {p.D} species, 2000 Plummer halos (70%) + uniform",
+                   "n": p.n, "D": p.D, "halos": 2000, "theta": p.theta, "ntab": p.ntab, "grid": p.grid,
+                   "leaf_size": p.leaf_size, "group_size": p.group_size, "r_cut": p.r_cut, "eps": p.eps,
+                   "seed": p.seed},
         "interactions_per_step": inter,
+        "interactions_pp": last["interactions_pp"],
+        "interactions_pn_by_source_species": last["interactions_pn_species"][:p.D],
         "walk_ms": ms_walk,
         "walk_interactions_per_s": inter / (ms_walk * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": walk_traffic()},
+        "build": build_roofline(last, p.n),
     }
+    # the paper's relative criterion (section 2.2) at its tolerance alpha = 0.005, with the previous
+    # accelerations from the theta = 0.5 step (as the stock code does after its first force)
+    import torch
+    old = torch.linalg.vector_norm(acc, dim=0).contiguous()
+    rr = run_box(ngr, p, max(2, args.steps // 2), 1, "relative", relative={"alpha": 0.005, "old_acc": old})
+    out["relative_criterion"] = {"workload": "the same box, relative opening criterion alpha 0.005 with the previous "
+                                             "|a| from the theta 0.5 force",
+                                 "ms_per_step": rr["ms_per_step"], "interactions_per_step": rr["inter"],
+                                 "interactions_per_s": rr["inter"] / (rr["ms_per_step"] * 1e-3),
+                                 "walk_ms": rr["ms_walk"], "walk_interactions_per_s": rr["inter"] / (rr["ms_walk"] * 1e-3)}
+    acc_rel = rr["acc"].cpu().numpy() if not (args.no_accuracy or args.no_cpu_baseline) else None
+    rr["ctx"].close()
+    del rr, old
+    gpu_gc = None
+    if not args.no_cpu_baseline:
+        # one more step with per-group counts (untimed), for the baseline's count check
+        _, gpu_gc = r["step"](counts=True)
+    gpu_acc = acc.cpu().numpy() if not (args.no_accuracy or args.no_cpu_baseline) else None
+    tensors = r["tensors"]
+    if not args.no_scaled:
+        log("the 2^24 box with 16000 halos (halo count scaled with n)")
+        q = synth.clustered_d6_scaled(3, n=args.n)
+        rs = run_box(ngr, q, max(2, args.steps // 4), 1, "H16000")
+        out["scaled_halos"] = {"workload": f"clustered box, {q.n} particles, {q.D} species, 16000 Plummer halos "
+                                           f"(70%) + uniform", "ms_per_step": rs["ms_per_step"],
+                               "interactions_per_step": rs["inter"],
+                               "interactions_per_s": rs["inter"] / (rs["ms_per_step"] * 1e-3), "walk_ms": rs["ms_walk"],
+                               "walk_interactions_per_s": rs["inter"] / (rs["ms_walk"] * 1e-3),
+                               "roofline_frac": FLOPS_PER_INTERACTION * rs["inter"] / (rs["ms_walk"] * 1e-3) / 1e12
+                               / PEAK_FP32_VECTOR_TFLOPS}
+        rs["ctx"].close()
+        del rs
     if not args.no_batched:
         log("many-box workload: one batched call against the single-box loop")
         out["batched"] = batched(ngr, synth)
@@ -519,7 +649,7 @@ def main():
         log("served: " + json.dumps({k: v for k, v in out["served"].items() if k.startswith(("load", "satur"))}))
     if not args.no_pm:
         log("PM long-range force of the benchmark box")
-        out["pm"] = pm_leg(ngr, synth, p, dict(pos=pos, species=species, mass=mass))
+        out["pm"] = pm_leg(ngr, synth, p, tensors)
         log(f"pm: {out['pm']['ms_per_force']:.1f} ms per force, mesh {out['pm']['N']}^3")
     log("exact short-range tables")
     out["short_tables"] = short_tables(ngr, synth)
@@ -529,10 +659,13 @@ def main():
         out["accumulator"] = accumulator(ngr, synth)
         log(f"accumulator: walk {out['accumulator']['walk_ms']:.2f} ms, "
             f"{out['accumulator']['cored_walk_over_table_walk']:.2f}x the table-law walk")
-    if not args.no_cpu_baseline:
-        log("oracle baseline on the host cores")
-        out["cpu_baseline"] = cpu_baseline(p, inter, args.cpu_seconds)
     ctx.close()
+    if not args.no_cpu_baseline:
+        log("oracle baseline on the host cores (and the tree-vs-direct accuracy on 2^16 sinks)")
+        out["cpu_baseline"], accu = cpu_baseline(p, gpu_gc, gpu_acc, args.cpu_seconds, acc_rel)
+        if accu is not None:
+            out["accuracy"] = accu
+            log(f"accuracy: p99 {accu['p99_rel_err_tree_vs_direct']:.3e}")
     print(json.dumps(out), flush=True)
 
 

@@ -215,7 +215,23 @@ typedef struct {
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the
  * pair term on an interaction-list entry: a particle of an opened leaf
  * (sink itself excluded) or a non-empty species monopole of an accepted
- * node, whether or not it falls inside r_cut. */
+ * node, whether or not it falls inside r_cut.
+ *   interactions_pn_species  interactions_pn split by the monopole's
+ *            (source) species b; entries b >= D are 0
+ *   near_ties  pair terms whose r^2 lies within 1e-6 r_cut^2 of r_cut^2: a
+ *            finite-precision evaluation may keep or drop such a pair (the
+ *            per-pair cut-off test is taken in each implementation's own
+ *            precision). Counted by ngr_tree_force_counts on a one-box tree
+ *            with the table laws and no lattice corrections; NGR_NOT_COUNTED
+ *            from every other call.
+ *   ms_build, ms_build_ingest, ms_build_sort, ms_build_octree  device time
+ *            (hipEvents) of the tree's ngr_tree_build: all of it; the input
+ *            checks, lattice and keys; the radix sort and the one reordering;
+ *            the level-by-level octree (each level's size is read back)
+ *   ms_monopoles  device time of the tree's ngr_compute_monopoles
+ *   ms_groups, ms_walk  device time of this call's sink groups (with the
+ *            ordering of the walk queue) and of its walk launch */
+#define NGR_NOT_COUNTED UINT64_MAX
 typedef struct {
     uint64_t interactions_pp;
     uint64_t interactions_pn;
@@ -226,6 +242,13 @@ typedef struct {
     uint32_t depth;
     double ms_groups;
     double ms_walk;
+    uint64_t interactions_pn_species[NGR_MAX_SPECIES];
+    uint64_t near_ties;
+    double ms_build;
+    double ms_build_ingest;
+    double ms_build_sort;
+    double ms_build_octree;
+    double ms_monopoles;
 } ngr_force_stats;
 
 /*
@@ -399,8 +422,10 @@ ngr_status ngr_groups_export(ngr_context* ctx, const ngr_tree* tree,
 
 /* As ngr_tree_force, and also write per-group counts to the host array
  * group_counts (4 x n_groups uint64 per group: accepted nodes, opened
- * leaves, pn interactions, pp interactions), groups in the order of
- * ngr_groups_export. */
+ * leaves, pn interactions, pp interactions; may be NULL), groups in the
+ * order of ngr_groups_export, and count the near ties (ngr_force_stats). The
+ * near-tie count runs a separate instantiation of the walk with one more
+ * compare per pair term; accelerations are bitwise those of ngr_tree_force. */
 ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree,
                                  const ngr_force_params* fp, double* acc,
                                  ngr_force_stats* st, uint64_t* group_counts);

@@ -267,12 +267,12 @@ class Tree:
 
     def force(self, law, groups: Optional[np.ndarray] = None, group_counts: bool = False):
         """Tree force. Returns (acc (3, n) in input order, slack (n,), counts
-        {'pp','pn'}, per-group counts or None). Rows of sinks outside the
-        listed groups are NaN."""
+        {'pp', 'pn', 'near_ties', 'pn_species'}, per-group counts or None).
+        Rows of sinks outside the listed groups are NaN."""
         n = self.n
         acc = np.full((3, n), np.nan)
         slack = np.full(n, np.nan)
-        cnt = np.zeros(2, np.uint64)
+        cnt = np.zeros(3 + 6, np.uint64)
         gsel = None if groups is None else np.ascontiguousarray(groups, np.uint32)
         nsel = self.n_groups if gsel is None else gsel.shape[0]
         gc = np.zeros((nsel, 4), np.uint64) if group_counts else None
@@ -280,7 +280,8 @@ class Tree:
                                   _p(acc), _p(slack), _p(cnt), _p(gc))
         if rc != 0:
             raise RuntimeError("oracle tree force failed")
-        return acc, slack, {"pp": int(cnt[0]), "pn": int(cnt[1])}, gc
+        return acc, slack, {"pp": int(cnt[0]), "pn": int(cnt[1]), "near_ties": int(cnt[2]),
+                            "pn_species": [int(c) for c in cnt[3:3 + self.D]]}, gc
 
 
 def direct(X, species, mass, D: int, box: float, law, sinks: Optional[np.ndarray] = None):

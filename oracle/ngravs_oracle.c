@@ -690,14 +690,14 @@ static void lattice_correction(const double* T, uint32_t n, double scale, const 
         if (d[x] < 0.0) out[x] = -out[x];
 }
 
-static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, double mu_body,
-                      double m_sink, const double d[3], double acc[3], double* slack)
+static int pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, double mu_body,
+                     double m_sink, const double d[3], double acc[3], double* slack)
 {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (r2 == 0.0) return;           /* coincident: no direction, no force */
+    if (r2 == 0.0) return 0;         /* coincident: no direction, no force */
     int inside = r2 < P->rc2;
     int tie = fabs(r2 - P->rc2) <= P->band;
-    if (!inside && !tie) return;
+    if (!inside && !tie) return 0;
     const double* T = P->tab + ((uint64_t)a * P->D + b) * P->ntab;
     double f = orc_factor(T, P->ntab, P->grid, r2, P->rc);
     double radial;
@@ -722,6 +722,7 @@ static void pair_term(const pair_ctx* P, uint32_t a, uint32_t b, double mu, doub
         for (unsigned x = 0; x < 3; ++x) acc[x] += gm * cr[x];
     }
     if (tie) *slack += fabs(k) * sqrt(r2);
+    return tie;
 }
 
 static void make_pair_ctx(pair_ctx* P, const orc_law* law, uint32_t D, double box)
@@ -750,9 +751,12 @@ static double wrap_periodic(double d, double box)
  * groups == NULL). The walk runs once per group and its list is used for
  * every sink of the group; each accepted node contributes one monopole per
  * non-empty species (section 2.2), each opened leaf its particles. Output is
- * in input order; counts = {particle-particle, particle-node} interactions,
- * each being one evaluation of the pair term on a list entry. group_counts
- * (4 per group, optional) = {accepted nodes, opened leaves, pn, pp}.
+ * in input order; counts (3 + ORC_MAX_SPECIES entries) = {particle-particle,
+ * particle-node interactions, near ties, particle-node interactions of each
+ * source species}, an interaction being one evaluation of the pair term on a
+ * list entry and a near tie one whose r^2 lies within 1e-6 r_cut^2 of r_cut^2.
+ * group_counts (4 per group, optional) = {accepted nodes, opened leaves, pn,
+ * pp}.
  */
 int orc_tree_force(const orc_tree* t, const orc_law* law,
                    const uint32_t* groups, uint64_t n_sub,
@@ -765,8 +769,9 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
     make_pair_ctx(&P, law, t->D, t->box);
     const double scale = t->box * TWO_M64;
     const uint64_t n = t->n;
-    uint64_t pp = 0, pn = 0;
-#pragma omp parallel reduction(+ : pp, pn)
+    uint64_t pp = 0, pn = 0, ties = 0;
+    uint64_t pnb[ORC_MAX_SPECIES] = {0};
+#pragma omp parallel reduction(+ : pp, pn, ties, pnb[:ORC_MAX_SPECIES])
     {
         list_t L = {0, 0, 0};
 #pragma omp for schedule(dynamic, 1)
@@ -780,7 +785,10 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
                 uint64_t node = L.e[k] & 0xffffffffull;
                 if ((L.e[k] >> 32) == 1) {
                     n_acc++;
-                    for (uint32_t b = 0; b < t->D; ++b) g_pn += t->M[b][node] > 0.0;
+                    for (uint32_t b = 0; b < t->D; ++b) {
+                        g_pn += t->M[b][node] > 0.0;
+                        pnb[b] += (t->M[b][node] > 0.0) * ns;
+                    }
                 } else {
                     n_leaf++;
                     for (uint32_t b = 0; b < t->D; ++b) g_pp += t->count[b][node];
@@ -811,7 +819,7 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
                                 d[x] = wrap_periodic(t->com[b][x][node] - xi[x], t->box);
                             double body = Mb;
                             if (law->track_counts && t->count[b][node]) body = Mb / (double)t->count[b][node];
-                            pair_term(&P, a, b, Mb, body, t->m[i], d, ai, &sl);
+                            ties += pair_term(&P, a, b, Mb, body, t->m[i], d, ai, &sl);
                         }
                     } else {
                         for (uint32_t b = 0; b < t->D; ++b) {
@@ -821,7 +829,7 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
                                 double d[3];
                                 for (unsigned x = 0; x < 3; ++x)
                                     d[x] = (double)(int64_t)(t->X[x][j] - t->X[x][i]) * scale;
-                                pair_term(&P, a, b, t->m[j], t->m[j], t->m[i], d, ai, &sl);
+                                ties += pair_term(&P, a, b, t->m[j], t->m[j], t->m[i], d, ai, &sl);
                             }
                         }
                     }
@@ -833,7 +841,12 @@ int orc_tree_force(const orc_tree* t, const orc_law* law,
         }
         free(L.e);
     }
-    if (counts) { counts[0] = pp; counts[1] = pn; }
+    if (counts) {
+        counts[0] = pp;
+        counts[1] = pn;
+        counts[2] = ties;
+        for (uint32_t b = 0; b < ORC_MAX_SPECIES; ++b) counts[3 + b] = pnb[b];
+    }
     return 0;
 }
 

@@ -52,13 +52,21 @@ class ForceParams(C.Structure):
                 ("lattice_corr", C.c_void_p), ("corr_n", C.c_uint32)]
 
 
+NOT_COUNTED = 2 ** 64 - 1     # NGR_NOT_COUNTED
+
+
 class ForceStats(C.Structure):
     _fields_ = [("interactions_pp", C.c_uint64), ("interactions_pn", C.c_uint64), ("n_nodes", C.c_uint64),
                 ("n_leaves", C.c_uint64), ("n_groups", C.c_uint64), ("group_size", C.c_uint32),
-                ("depth", C.c_uint32), ("ms_groups", C.c_double), ("ms_walk", C.c_double)]
+                ("depth", C.c_uint32), ("ms_groups", C.c_double), ("ms_walk", C.c_double),
+                ("interactions_pn_species", C.c_uint64 * 6), ("near_ties", C.c_uint64),
+                ("ms_build", C.c_double), ("ms_build_ingest", C.c_double), ("ms_build_sort", C.c_double),
+                ("ms_build_octree", C.c_double), ("ms_monopoles", C.c_double)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["interactions_pn_species"] = list(d["interactions_pn_species"])
+        return d
 
 
 class Box(C.Structure):

@@ -130,6 +130,20 @@ void Context::to_device(void* dev, const void* host, size_t bytes)
 
 void Context::sync() { hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize", __FILE__, __LINE__); }
 
+hipEvent_t Context::event(int k)
+{
+    if (!ev[k]) hip_check(hipEventCreate(&ev[k]), "hipEventCreate", __FILE__, __LINE__);
+    return ev[k];
+}
+
+float Context::elapsed(int k0, int k1)
+{
+    hip_check(hipEventSynchronize(ev[k1]), "hipEventSynchronize", __FILE__, __LINE__);
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, ev[k0], ev[k1]), "hipEventElapsedTime", __FILE__, __LINE__);
+    return ms;
+}
+
 }  // namespace ngr
 
 namespace ngr {
@@ -265,7 +279,7 @@ ngr_status guarded(ngr_context* ctx, F&& f)
 }
 
 ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
-                      ngr_force_stats* st, uint64_t* group_counts_host)
+                      ngr_force_stats* st, uint64_t* group_counts_host, bool count_ties)
 {
     return guarded(ctx, [&] {
         using ngr::fail;
@@ -293,7 +307,7 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             laws[0].track = tree->track_counts ? 1u : 0u;
             if (tree->n) tab_block = ngr::upload_tables(c, laws, tabs);
             if (group_counts_host && g.ng) gc = static_cast<uint64_t*>(c.alloc(g.ng * 4 * sizeof(uint64_t)));
-            ngr::walk_force(c, *tree, g, laws, tabs, std::vector<double*>{acc}, gc, wo);
+            ngr::walk_force(c, *tree, g, laws, tabs, std::vector<double*>{acc}, gc, wo, count_ties);
             if (gc) c.to_host(group_counts_host, gc, g.ng * 4 * sizeof(uint64_t));
             c.sync();
         } catch (...) {
@@ -319,6 +333,13 @@ ngr_status force_impl(ngr_context* ctx, const ngr_tree* tree, const ngr_force_pa
             st->depth = tree->depth;
             st->ms_groups = ms_groups + wo.ms_order;
             st->ms_walk = wo.ms_walk;
+            for (int b = 0; b < NGR_MAX_SPECIES; ++b) st->interactions_pn_species[b] = wo.pnb[b];
+            st->near_ties = wo.ties;
+            st->ms_build_ingest = tree->ms_ingest;
+            st->ms_build_sort = tree->ms_sort;
+            st->ms_build_octree = tree->ms_octree;
+            st->ms_build = (double)tree->ms_ingest + tree->ms_sort + tree->ms_octree;
+            st->ms_monopoles = tree->ms_monopoles;
         }
         c.release(gc);
         c.release(tab_block);
@@ -362,6 +383,8 @@ NGR_API void ngr_context_destroy(ngr_context* ctx)
 {
     if (!ctx) return;
     if (!ctx->poisoned) (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     ctx->free_all();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -380,7 +403,7 @@ NGR_API ngr_status ngr_tree_build(ngr_context* ctx, const ngr_particles* p, cons
         ngr::check_particles(p, tp, "", boxes[0]);
         ngr_tree* t = new ngr_tree();
         try {
-            ngr::build_forest(*ctx, boxes, *t);
+            ngr::build_forest(*ctx, boxes, *t, true);
             ctx->sync();
         } catch (...) {
             try {
@@ -398,22 +421,25 @@ NGR_API ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int t
 {
     return guarded(ctx, [&] {
         if (!tree) ngr::fail(NGR_EINVAL, "tree is NULL");
+        ngr::hip_check(hipEventRecord(ctx->event(4), ctx->stream), "hipEventRecord", __FILE__, __LINE__);
         ngr::compute_monopoles(*ctx, *tree);
+        ngr::hip_check(hipEventRecord(ctx->event(5), ctx->stream), "hipEventRecord", __FILE__, __LINE__);
         tree->track_counts = track_counts != 0;
         ctx->sync();
+        tree->ms_monopoles = ctx->elapsed(4, 5);
     });
 }
 
 NGR_API ngr_status ngr_tree_force(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp, double* acc,
                                   ngr_force_stats* st)
 {
-    return force_impl(ctx, tree, fp, acc, st, nullptr);
+    return force_impl(ctx, tree, fp, acc, st, nullptr, false);
 }
 
 NGR_API ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree, const ngr_force_params* fp,
                                          double* acc, ngr_force_stats* st, uint64_t* group_counts)
 {
-    return force_impl(ctx, tree, fp, acc, st, group_counts);
+    return force_impl(ctx, tree, fp, acc, st, group_counts, true);
 }
 
 NGR_API ngr_status ngr_tree_free(ngr_context* ctx, ngr_tree* tree)
@@ -612,6 +638,8 @@ NGR_API ngr_status ngr_batch_build_force(ngr_context* ctx, uint32_t nbox, const 
                 b.n_groups = g.first.empty() ? 0 : g.first[(size_t)(k + 1) * D] - g.first[(size_t)k * D];
                 b.group_size = gs[k];
                 b.depth = bdepth[k];
+                for (int q = 0; q < NGR_MAX_SPECIES; ++q) b.interactions_pn_species[q] = wo.box_pnb[(size_t)k * NGR_MAX_SPECIES + q];
+                b.near_ties = NGR_NOT_COUNTED;
             }
         }
         ngr::free_tree(c, t);

@@ -406,8 +406,11 @@ void free_tree(Context& ctx, Tree& t)
     t.boff_dev = nullptr;
 }
 
-void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
+void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool timed)
 {
+    auto mark = [&](int k) {
+        if (timed) HIP_CHECK(hipEventRecord(ctx.event(k), ctx.stream));
+    };
     const uint32_t nbox = (uint32_t)boxes.size();
     if (nbox == 0 || nbox > 65535) fail(NGR_EINVAL, "the number of boxes must be in 1..65535");
     uint32_t D = 0;
@@ -438,6 +441,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
 
     // ---- input checks, lattice, keys and species counts (one synchronisation)
     ctx.stage("build: input checks and keys");
+    mark(0);
     const uint64_t n1 = std::max<uint64_t>(n, 1);
     t.X = static_cast<uint64_t*>(ctx.alloc(3 * n1 * sizeof(uint64_t)));
     t.mass = static_cast<double*>(ctx.alloc(n1 * sizeof(double)));
@@ -469,6 +473,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
         hipLaunchKernelGGL(ingest, dim3(gx, nbox), dim3(256), 0, ctx.stream, bin_dev, n, Xin, t.keys, t.perm, mass_cat,
                            boxid, flags_dev, counts_dev);
         LAUNCH_CHECK("ingest");
+        mark(1);
         ctx.to_host(flags.data(), flags_dev, nbox * sizeof(uint32_t));
         ctx.to_host(counts.data(), counts_dev, (size_t)nbox * NGR_MAX_SPECIES * sizeof(uint64_t));
         ctx.release(bin_dev);
@@ -497,6 +502,8 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
 
     // ---- sort by (box, species, key) and the one reordering
     ctx.stage("build: sort");
+    if (!n) mark(1);
+    mark(2);
     if (n) {
         uint64_t* ktmp = static_cast<uint64_t*>(ctx.alloc(n * sizeof(uint64_t)));
         uint32_t* vtmp = static_cast<uint32_t*>(ctx.alloc(n * sizeof(uint32_t)));
@@ -529,6 +536,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
     }
 
     // ---- breadth-first octree over all boxes, level by level
+    mark(3);
     ctx.stage("build: octree");
     t.nn = 0;
     t.cap = 0;
@@ -581,9 +589,15 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t)
     hipLaunchKernelGGL(count_leaves, dim3((unsigned)std::min<uint64_t>(blocks_for(t.nn, 256), 4u * ctx.num_cu)), dim3(256),
                        0, ctx.stream, t.nn, t.n_child, leaves);
     LAUNCH_CHECK("count_leaves");
+    mark(4);
     ctx.stage("build: done");
     uint64_t nleaves = 0;
     ctx.read_words(&nleaves, leaves, 1);
+    if (timed) {
+        t.ms_ingest = ctx.elapsed(0, 1);
+        t.ms_sort = ctx.elapsed(2, 3);
+        t.ms_octree = ctx.elapsed(3, 4);
+    }
     ctx.release(leaves);
     ctx.release(leaf_dev);
     t.n_leaves = nleaves;

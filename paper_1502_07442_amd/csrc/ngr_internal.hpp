@@ -59,6 +59,9 @@ struct Context {
     std::map<uint64_t, uint32_t> tuned;           // group size per class (D << 8 | floor(log2 n))
     uint64_t* pinned = nullptr;                   // pinned host staging, kPinnedWords
     static constexpr size_t kPinnedWords = 64;
+    hipEvent_t ev[8] = {};                        // timing events, created on first use
+    hipEvent_t event(int k);
+    float elapsed(int k0, int k1);                // ms between two recorded events (synchronises)
 
     void* alloc(size_t bytes);
     void release(void* p);
@@ -132,6 +135,8 @@ struct Tree {
     double4* mono = nullptr;
     bool has_monopoles = false;
     bool track_counts = true;      // N_perp option of the monopoles (accumulator laws)
+    // device time of the build's phases and of the monopoles (single-box calls)
+    float ms_ingest = 0.0f, ms_sort = 0.0f, ms_octree = 0.0f, ms_monopoles = 0.0f;
 };
 void free_tree(Context& ctx, Tree& t);
 
@@ -159,7 +164,8 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
 // ---- build steps (build.hip) ----
 // Check, key, sort and build the tree of every box in one pass. Boxes with an
 // invalid species id, mass or position fail with NGR_EINVAL naming the box.
-void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t);
+// timed: record the phases' device times in t (events on the context's stream).
+void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool timed = false);
 // The device checks of one box's inputs alone (NGR_EINVAL as build_forest).
 void validate_box(Context& ctx, const BoxIn& b, const std::string& where);
 void compute_monopoles(Context& ctx, Tree& t);
@@ -220,7 +226,10 @@ void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawT
 
 struct WalkOut {
     uint64_t pp = 0, pn = 0;
+    uint64_t pnb[NGR_MAX_SPECIES] = {0, 0, 0, 0, 0, 0};   // pn by source species
+    uint64_t ties = NGR_NOT_COUNTED;        // near ties (counted on request, one-box table laws)
     std::vector<uint64_t> box_pp, box_pn;   // per box
+    std::vector<uint64_t> box_pnb;          // per box, NGR_MAX_SPECIES each
     double ms_walk = 0.0, ms_order = 0.0;
 };
 // laws and acc: one per box of the tree; acc[k] is box k's 3 x n_k output.
@@ -249,7 +258,7 @@ void short_range_tables(Context& ctx, const ngr_short_params& sp, const double* 
                         double* tables);
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
                 const std::vector<LawTables>& tables, const std::vector<double*>& acc, uint64_t* group_counts_dev,
-                WalkOut& out);
+                WalkOut& out, bool count_ties = false);
 
 // ---- served requests (serve.hip) ----
 struct Server;

@@ -226,9 +226,9 @@ __global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t D, const uint
 constexpr uint32_t kPrune = 0, kAccept = 1, kOpen = 2;
 constexpr int kBuf = 128;              // node / leaf buffer entries per wave
 constexpr int kRec = 68;               // record slots per wave: 64 and up to 3 pads
-constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4;   // bytes of LDS per wave
+constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4 + 8 * 4;   // bytes of LDS per wave
 constexpr int kMaxWaves = 16;          // waves per workgroup
-constexpr int kCtrlBytes = 512;        // LDS control area ahead of the tables
+constexpr int kCtrlBytes = 1536;       // LDS control area ahead of the tables (next segment, per-wave counts)
 // Accumulator laws: per wave, the core scale of each record (float64) after
 // the other buffers; per workgroup, the core-factor table after the force
 // tables (kCoreN intervals on u = r / (s + r) in [0, 1], PAIR layout, the
@@ -262,6 +262,7 @@ struct BoxParams {
     double corr_scale;         // corr_n / (box / 2)
     double eps2_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // per-pair eps^2, row a = sink species
     float toff_ab[NGR_MAX_SPECIES * NGR_MAX_SPECIES];    // r^2-grid table offset -eps_ab^2 / h of each pair
+    double tie_rc2, tie_band;  // near ties: r_cut^2 and the band 1e-6 r_cut^2
 };
 
 // Per-lane-invariant values of the pair term, taken from the box.
@@ -296,7 +297,7 @@ struct WalkArgs {
     uint32_t nsched;
     uint32_t* cursor;          // next entry of sched to start
     const BoxParams* boxes;
-    unsigned long long* seg_counts;   // nseg x 2: pp and pn interactions of each segment
+    unsigned long long* seg_counts;   // nseg x kSegCounts: pp, pn, near ties, pn by source species
     unsigned long long* gcounts;
     uint32_t* stacks;
     uint32_t stack_cap;
@@ -362,17 +363,25 @@ struct LatticeCorr {
     double scale;
 };
 
-template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K, bool EW = false>
-__device__ inline void eval_records(const PairParams& A, double eps2, float toff, const double4* __restrict__ rec,
-                                    uint32_t iters, const void* __restrict__ tbv, double ox, double oy, double oz,
-                                    double& ax, double& ay, double& az, LatticeCorr lc = LatticeCorr{nullptr, 0u, 0.0})
+// Near-tie count (TIES): pair terms whose r^2 lies within `band` of rc2,
+// the pairs a finite-precision cut-off test may keep or drop. Returned by
+// the pair loop (0 without TIES).
+struct TieBand {
+    double rc2, band;
+};
+
+template <int GRID, int TAB, bool EPS0, bool WRAP, uint32_t K, bool EW = false, bool TIES = false>
+__device__ inline uint32_t eval_records(const PairParams& A, double eps2, float toff, const double4* __restrict__ rec,
+                                        uint32_t iters, const void* __restrict__ tbv, double ox, double oy, double oz,
+                                        double& ax, double& ay, double& az,
+                                        LatticeCorr lc = LatticeCorr{nullptr, 0u, 0.0}, TieBand tb = TieBand{0.0, -1.0})
 {
     // a launch that holds unsoftened pairs evaluates its softened pairs exactly
     // as a launch without any (a box in a batch equals its single-box call)
-    if (EPS0 && eps2 != 0.0) {
-        eval_records<GRID, TAB, false, WRAP, K, EW>(A, eps2, toff, rec, iters, tbv, ox, oy, oz, ax, ay, az, lc);
-        return;
-    }
+    if (EPS0 && eps2 != 0.0)
+        return eval_records<GRID, TAB, false, WRAP, K, EW, TIES>(A, eps2, toff, rec, iters, tbv, ox, oy, oz, ax, ay, az,
+                                                                 lc, tb);
+    uint32_t nties = 0;
     const float tscale = A.tscale, tmax = A.tmax;
     NGR_PRAGMA_UNROLL(NGR_EVAL_UNROLL)
     for (uint32_t it = 0; it < iters; ++it) {
@@ -384,6 +393,10 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
             dz -= A.box * rint(dz * A.inv_box);
         }
         const double re2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));   // r^2 + eps^2
+        if (TIES) {
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            nties += fabs(r2 - tb.rc2) <= tb.band ? 1u : 0u;
+        }
         const float sf = (float)re2;
         // (r^2+eps^2)^(-3/2) in float32 from the hardware rsqrt: a relative
         // error of a few 1e-7, the precision of the float32 table factor it
@@ -429,6 +442,7 @@ __device__ inline void eval_records(const PairParams& A, double eps2, float toff
             az = fma(gm, cz, az);
         }
     }
+    return nties;
 }
 
 // Pair terms of a cored pair of species (accumulator laws). With s the
@@ -502,7 +516,10 @@ __host__ __device__ inline uint32_t table_bytes(int mode, uint32_t D, uint32_t n
     return (raw + 255u) & ~255u;
 }
 
-template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC, bool EW = false>
+// Counters of one segment: pp, pn, near ties, then pn by source species.
+constexpr int kSegCounts = 3 + NGR_MAX_SPECIES;
+
+template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC, bool EW = false, bool TIES = false>
 __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
     HIP_DYNAMIC_SHARED(unsigned char, smem);
@@ -511,7 +528,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     // LDS: control area (next segment; per-wave counts), the tables of one
     // segment, then per-wave buffers
     int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
-    unsigned long long* part = reinterpret_cast<unsigned long long*>(smem + 256);   // 2 per wave
+    unsigned long long* part = reinterpret_cast<unsigned long long*>(smem + 256);   // kSegCounts per wave
     unsigned char* tsm = smem + kCtrlBytes;
     constexpr int kWL = ACC ? kWaveLdsAcc : kWaveLds;
     unsigned char* wb = tsm + A.tab_bytes + wave * kWL;
@@ -522,6 +539,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     uint32_t* ppb = pnb + kBuf;
     uint32_t* scanb = ppb + kBuf;        // 68 entries
     uint32_t* pst = scanb + 68;          // 64 entries
+    uint32_t* gpn = pst + 64;            // the group's particle-node records by source species (8 entries)
+    unsigned long long* wcnt = part + kSegCounts * wave;   // this wave's counts of the segment
     uint32_t* stack = A.stacks + ((uint64_t)blockIdx.x * nwaves + wave) * A.stack_cap;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint64_t n = A.n;
@@ -563,7 +582,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         const double inv4pib = P.inv4pib;
         const bool track = P.track != 0u;
         uint32_t* const queue = A.queues + seg;
-        unsigned long long tot_pp = 0, tot_pn = 0;
+        const double tie_rc2 = P.tie_rc2, tie_band = P.tie_band;
+        // the segment's counts accumulate in LDS (no registers held across groups)
+        if ((uint32_t)lane < (uint32_t)kSegCounts) wcnt[lane] = 0ull;
 
     // Waves take groups from the segment's queue. Every lane executes the
     // atomic (lane 0 adds one, the others add zero), so no lane-dependent
@@ -611,6 +632,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         }
         double ax = 0.0, ay = 0.0, az = 0.0;
         unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
+        const TieBand tband{tie_rc2, tie_band};
+        if ((uint32_t)lane < (uint32_t)NGR_MAX_SPECIES) gpn[lane] = 0u;
+        uint32_t nties = 0;                  // TIES: this lane's near ties
         // relative opening test: the smallest previous |a| of the group's sinks
         const bool rel = P.relative != 0u;
         double a_min = 0.0;
@@ -647,10 +671,13 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 eval_records<GRID, TAB, EPS0, true, 1, true>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, lc);
                 return;
             }
-            if (wrap) eval_records<GRID, TAB, EPS0, true, 1>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 0u) eval_records<GRID, TAB, EPS0, false, 1>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az);
-            else if (lk == 1u) eval_records<GRID, TAB, EPS0, false, 2>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az);
-            else eval_records<GRID, TAB, EPS0, false, 4>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az);
+            const LatticeCorr nolc{nullptr, 0u, 0.0};
+            uint32_t t;
+            if (wrap) t = eval_records<GRID, TAB, EPS0, true, 1, false, TIES>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, nolc, tband);
+            else if (lk == 0u) t = eval_records<GRID, TAB, EPS0, false, 1, false, TIES>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, nolc, tband);
+            else if (lk == 1u) t = eval_records<GRID, TAB, EPS0, false, 2, false, TIES>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az, nolc, tband);
+            else t = eval_records<GRID, TAB, EPS0, false, 4, false, TIES>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az, nolc, tband);
+            if (TIES && sink < ns) nties += t;
         };
 
         // Accepted nodes: one record per non-empty species monopole. The next
@@ -686,6 +713,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 if (b + 1 < Dk && (uint32_t)lane < k) r = A.mono[(uint64_t)(b + 1) * A.nn + node];
                 if (nrec) eval(b, nrec);
                 pn_src += nrec;
+                if (lane == 0) gpn[b] += nrec;
                 wave_sync();
             }
         };
@@ -904,18 +932,25 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             acc[2 * nbx + p] = az;
         }
         const unsigned long long pn = pn_src * ns, pp = pp_src * ns - ns;
-        tot_pp += pp;
-        tot_pn += pn;
+        unsigned long long gties = 0;
+        if (TIES) {
+            uint32_t t = nties;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) t += (uint32_t)__shfl_xor((int)t, d, 64);
+            gties = uniform(t);
+        }
+        wave_sync();                       // lane 0's gpn updates are visible
+        if ((uint32_t)lane < (uint32_t)kSegCounts) {
+            const unsigned long long v = lane == 0 ? pp : lane == 1 ? pn : lane == 2 ? gties
+                                                                   : (unsigned long long)gpn[lane - 3] * ns;
+            wcnt[lane] += v;
+        }
         if (A.gcounts && (uint32_t)lane < 4u) {
             const unsigned long long v[4] = {n_acc, n_leaf, pn, pp};
             A.gcounts[4ull * g + lane] = v[lane];
         }
     }
-        __syncthreads();                   // every wave is done with this segment's tables
-        if (lane == 0) {
-            part[2 * wave] = tot_pp;
-            part[2 * wave + 1] = tot_pn;
-        }
+        __syncthreads();                   // every wave is done with this segment's tables and counts
         if (wave == 0) {
             // next segment: the next one not started, else the one with the most groups left
             const uint32_t t = uniform(atomicAdd(A.cursor, lane == 0 ? 1u : 0u));
@@ -946,14 +981,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             ctrl[0] = (int32_t)next;       // every lane stores the same value
         }
         __syncthreads();
-        if (threadIdx.x == 0) {            // the segment's counts: one global atomic per workgroup
-            unsigned long long spp = 0, spn = 0;
-            for (int w = 0; w < nwaves; ++w) {
-                spp += part[2 * w];
-                spn += part[2 * w + 1];
-            }
-            if (spp) atomicAdd(&A.seg_counts[2ull * seg], spp);
-            if (spn) atomicAdd(&A.seg_counts[2ull * seg + 1], spn);
+        if (threadIdx.x < (unsigned)kSegCounts) {   // the segment's counts: one global atomic each per workgroup
+            unsigned long long v = 0;
+            for (int w = 0; w < nwaves; ++w) v += part[kSegCounts * w + threadIdx.x];
+            if (v) atomicAdd(&A.seg_counts[(uint64_t)kSegCounts * seg + threadIdx.x], v);
         }
         seg = uniform((uint32_t)ctrl[0]);
         if (seg >= A.nseg) break;
@@ -1240,13 +1271,17 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
 
 void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
                 const std::vector<LawTables>& tables, const std::vector<double*>& accv, uint64_t* group_counts_dev,
-                WalkOut& out)
+                WalkOut& out, bool count_ties)
 {
     out = WalkOut{};
     const uint32_t nbox = t.nbox, D = t.D;
     out.box_pp.assign(nbox, 0);
     out.box_pn.assign(nbox, 0);
-    if (t.n == 0 || g.ng == 0) return;
+    out.box_pnb.assign((size_t)nbox * NGR_MAX_SPECIES, 0);
+    if (t.n == 0 || g.ng == 0) {
+        if (count_ties) out.ties = 0;
+        return;
+    }
     const uint32_t grid = laws[0].grid;
     bool eps0 = false, acc_law = false, ew = false;
     for (uint32_t k = 0; k < nbox; ++k) {
@@ -1325,6 +1360,8 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             P.toff = 0.0f;
         }
         P.tmax = (float)(law.ntab - 1);
+        P.tie_rc2 = rc2;
+        P.tie_band = 1e-6 * rc2;
         for (uint32_t ab = 0; ab < law.D * law.D; ++ab) {
             P.eps2_ab[ab] = law.eps_ab[ab] * law.eps_ab[ab];
             P.toff_ab[ab] = law.grid == NGR_GRID_R2 ? (float)(-P.eps2_ab[ab] * ((law.ntab - 1) / rc2)) : 0.0f;
@@ -1366,8 +1403,8 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         return g.first[x + 1] - g.first[x] > g.first[y + 1] - g.first[y];
     });
     const uint32_t nsched = (uint32_t)sched.size();
-    // control block: seg_counts (2 x nseg u64) | queues (nseg) | cursor | error | seg_first (nseg+1) | sched
-    const size_t cnt_bytes = 2ull * nseg * sizeof(uint64_t);
+    // control block: seg_counts (kSegCounts x nseg u64) | queues (nseg) | cursor | error | seg_first (nseg+1) | sched
+    const size_t cnt_bytes = (size_t)kSegCounts * nseg * sizeof(uint64_t);
     const size_t ctl_words = (size_t)nseg + 2 + (nseg + 1) + nsched;
     unsigned char* ctl = static_cast<unsigned char*>(ctx.alloc(cnt_bytes + ctl_words * sizeof(uint32_t)));
     unsigned long long* seg_counts = reinterpret_cast<unsigned long long*>(ctl);
@@ -1435,10 +1472,20 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         LAUNCH_CHECK("walk_kernel");
     };
     // a one-box call reads its box's parameters from the kernel arguments;
-    // the accumulator laws read them from the table in device memory
-    const int sel = (ew ? 24 : acc_law ? 16 : nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) +
+    // the accumulator laws read them from the table in device memory. The
+    // near-tie count is an instantiation of the one-box table-law walk.
+    const bool ties = count_ties && nbox == 1 && !acc_law && !ew;
+    const int sel = (ties ? 32 : ew ? 24 : acc_law ? 16 : nbox == 1 ? 8 : 0) + (grid == NGR_GRID_R2 ? 4 : 0) +
                     (mode == kValue ? 2 : 0) + (eps0 ? 1 : 0);
     switch (sel) {
+    case 32: launch(walk_kernel<NGR_GRID_R, kPair, false, true, false, false, true>); break;
+    case 33: launch(walk_kernel<NGR_GRID_R, kPair, true, true, false, false, true>); break;
+    case 34: launch(walk_kernel<NGR_GRID_R, kValue, false, true, false, false, true>); break;
+    case 35: launch(walk_kernel<NGR_GRID_R, kValue, true, true, false, false, true>); break;
+    case 36: launch(walk_kernel<NGR_GRID_R2, kPair, false, true, false, false, true>); break;
+    case 37: launch(walk_kernel<NGR_GRID_R2, kPair, true, true, false, false, true>); break;
+    case 38: launch(walk_kernel<NGR_GRID_R2, kValue, false, true, false, false, true>); break;
+    case 39: launch(walk_kernel<NGR_GRID_R2, kValue, true, true, false, false, true>); break;
     case 24: launch(walk_kernel<NGR_GRID_R, kPair, false, false, false, true>); break;
     case 25: launch(walk_kernel<NGR_GRID_R, kPair, true, false, false, true>); break;
     case 26: launch(walk_kernel<NGR_GRID_R, kValue, false, false, false, true>); break;
@@ -1473,7 +1520,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     default: launch(walk_kernel<NGR_GRID_R2, kValue, true, false, true>); break;
     }
     HIP_CHECK(hipEventRecord(e2, ctx.stream));
-    std::vector<uint64_t> counts(2ull * nseg);
+    std::vector<uint64_t> counts((size_t)kSegCounts * nseg);
     uint32_t herr = 0;
     ctx.to_host(counts.data(), seg_counts, cnt_bytes);
     ctx.to_host(&herr, err, sizeof herr);
@@ -1489,14 +1536,20 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     HIP_CHECK(hipEventDestroy(e1));
     HIP_CHECK(hipEventDestroy(e2));
     if (herr) fail(NGR_ENOMEM, "walk stack or step capacity exceeded");
+    uint64_t nties = 0;
     for (uint32_t q = 0; q < nseg; ++q) {
-        out.box_pp[q / D] += counts[2ull * q];
-        out.box_pn[q / D] += counts[2ull * q + 1];
+        const uint64_t* c = &counts[(size_t)kSegCounts * q];
+        out.box_pp[q / D] += c[0];
+        out.box_pn[q / D] += c[1];
+        nties += c[2];
+        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) out.box_pnb[(size_t)(q / D) * NGR_MAX_SPECIES + b] += c[3 + b];
     }
     for (uint32_t k = 0; k < nbox; ++k) {
         out.pp += out.box_pp[k];
         out.pn += out.box_pn[k];
+        for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) out.pnb[b] += out.box_pnb[(size_t)k * NGR_MAX_SPECIES + b];
     }
+    if (ties) out.ties = nties;
     out.ms_walk = ms;
     out.ms_order = ms_order;
 }

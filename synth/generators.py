@@ -29,6 +29,7 @@ __all__ = [
     "uniform_positions", "uniform_lattice", "clustered_positions",
     "newtonian_treepm_factor", "yukawa_product_factor", "table_abscissae",
     "sample_table", "scaled_params", "random_laws", "uniform_4096", "clustered_yukawa_d3", "clustered_d6",
+    "clustered_d6_scaled",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
     "accumulator_problem", "yukawa_law", "exact_split_laws", "isolated_problem",
     "newtonian_lattice_correction", "periodic_tree_problem",
@@ -275,11 +276,22 @@ def clustered_problem(n: int, D: int, seed: int, *, f_cl: float = 0.7,
                    leaf_size=leaf_size, group_size=group_size, pos=pos, seed=seed)
 
 
-def clustered_d6(seed: int = 3, n: int = 2 ** 24) -> Problem:
-    """Clustered box at scale: six species, random G and random mixed laws."""
-    p = clustered_problem(n, 6, seed, grid=GRID_R2, ntab=2048)
-    p.name = f"clustered-{n}-D6-seed{seed}"
+def clustered_d6(seed: int = 3, n: int = 2 ** 24, halos: Optional[int] = 2000) -> Problem:
+    """Clustered box at scale: six species, random G and random mixed laws.
+    By default the same generator as the 2^21 box, 2000 halos whatever n
+    (at 2^24 each halo then holds eight times the particles); halos=None
+    scales the halo count with n (2000 n / 2^21), keeping the halos' mean
+    occupancy of the 2^21 box."""
+    p = clustered_problem(n, 6, seed, grid=GRID_R2, ntab=2048, halos=halos)
+    h = halos if halos is not None else max(1, int(round(2000 * n / 2 ** 21)))
+    p.name = f"clustered-{n}-D6-H{h}-seed{seed}"
     return p
+
+
+def clustered_d6_scaled(seed: int = 3, n: int = 2 ** 24) -> Problem:
+    """The six-species box with the halo count scaled with n (16000 halos at
+    2^24)."""
+    return clustered_d6(seed, n, halos=None)
 
 
 def uniform_problem(n: int, D: int, seed: int, *, grid: str = GRID_R,

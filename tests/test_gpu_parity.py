@@ -21,6 +21,11 @@ from gpu_util import device_inputs, force_gate, gpu_solve
 pytestmark = pytest.mark.gpu
 
 
+def torch_acc(n):
+    import torch
+    return torch.empty((3, n), dtype=torch.float64, device="cuda")
+
+
 @pytest.fixture(scope="module")
 def ctx():
     import torch
@@ -64,6 +69,8 @@ def full_parity(ctx, p, group_size=None, check_tree=True):
                 assert np.array_equal(g[k], go[k]), k
         ao, so, co, gco = T.force(oracle.law_of(p), group_counts=True)
         assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"])
+        assert st["interactions_pn_species"][:p.D] == co["pn_species"]
+        assert st["near_ties"] == co["near_ties"]
         assert np.array_equal(gc, gco)
         ok, worst, rms, mx = force_gate(acc, ao, so)
         print(f"  interactions={co['pp'] + co['pn']} worst/allowed={worst:.3g} max|da|/rms={mx:.3g}", flush=True)
@@ -240,27 +247,42 @@ def test_errors_are_reported(ctx):
     ngr.tree_free(ctx, tree)
 
 
-def test_sampled_parity_at_2_21(ctx):
-    """The three-species clustered box at full size: exact counts and the
-    force gate on a seeded sample of groups (the oracle computes only those)."""
-    sampled_parity(ctx, synth.clustered_yukawa_d3(2), n_groups=400)
+def test_full_parity_at_2_21(ctx, capsys):
+    """The three-species clustered box at full size, against the oracle over
+    every group: exact counts and the force gate with the oracle's rms."""
+    full_box_parity(ctx, capsys, synth.clustered_yukawa_d3(2), chunks=2)
 
 
 @pytest.mark.slow
-def test_sampled_parity_at_2_24_six_species(ctx):
-    """The 2^24, six-species workload of the benchmark, in its launch
-    configuration, on a seeded sample of groups."""
-    sampled_parity(ctx, synth.clustered_d6(3), n_groups=300)
+@pytest.mark.parametrize("halos", [2000, None], ids=["H2000", "H16000"])
+def test_full_parity_at_2_24_six_species(ctx, capsys, halos):
+    """The 2^24, six-species workload in the benchmark's launch
+    configuration, against the oracle over every group: exact tree, groups,
+    per-group and total counts (so the benchmark's interaction count is the
+    oracle's), and the per-particle force gate with the oracle's own rms.
+    2000 halos is the benchmark box (the generator of the 2^21 box at 2^24);
+    halos=None scales the halo count with n (16000)."""
+    p = synth.clustered_d6(3, halos=halos)
+    full_box_parity(ctx, capsys, p, chunks=8)
 
 
-def sampled_parity(ctx, p, n_groups):
-    print(f"case {p.name} n={p.n} D={p.D}", flush=True)
+def full_box_parity(ctx, capsys, p, chunks):
+    def say(msg):
+        with capsys.disabled():
+            print(msg, flush=True)
+    say(f"case {p.name} n={p.n} D={p.D} (full oracle)")
     acc, st, gc, tree = gpu_solve(ctx, p, group_counts=True, keep_tree=True)
     try:
+        # the benchmark's instantiation (no counts) gives the same accelerations bit for bit
+        plain = torch_acc(p.n)
+        ngr.tree_force(ctx, tree, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                       group_size=p.group_size, acc=plain)
+        assert np.array_equal(plain.cpu().numpy(), acc)
+        del plain
         ex = ngr.tree_export(ctx, tree)
-        print("  gpu done", flush=True)
+        say("  gpu done")
         T = oracle.Tree.of(p)
-        print("  oracle tree done", flush=True)
+        say(f"  oracle tree done: {T.n_nodes} nodes, {T.n_groups} groups")
         nd = T.nodes()
         assert np.array_equal(ex["perm"], nd["perm"]) and np.array_equal(ex["keys"], nd["keys"])
         assert tree.n_nodes == T.n_nodes
@@ -270,22 +292,30 @@ def sampled_parity(ctx, p, n_groups):
         g = ngr.groups_export(ctx, tree, p.group_size)
         for k in go:
             assert np.array_equal(g[k], go[k]), k
-        rng = np.random.default_rng(1234)
-        sel = np.sort(rng.choice(T.n_groups, min(n_groups, T.n_groups), replace=False)).astype(np.uint32)
-        # always include the largest-count groups (the densest regions)
-        dense = np.argsort(-(gc[:, 2] + gc[:, 3]))[:20].astype(np.uint32)
-        sel = np.unique(np.concatenate([sel, dense]))
-        ao, so, co, gco = T.force(oracle.law_of(p), groups=sel, group_counts=True)
-        assert np.array_equal(gc[sel], gco)
-        assert st["interactions_pp"] == int(gc[:, 3].sum()) and st["interactions_pn"] == int(gc[:, 2].sum())
-        sinks = np.concatenate([np.arange(go["start"][k], go["start"][k] + go["count"][k]) for k in sel])
-        idx = nd["perm"][sinks]
-        # the rms over every particle needs every force: take it from the GPU
-        # result (it enters only the tolerance scale)
-        rms = float(np.sqrt(np.mean(np.sum(acc ** 2, axis=0))))
-        da = np.linalg.norm(acc[:, idx] - ao[:, idx], axis=0)
-        worst = float(np.max(da / (1e-5 * rms + so[idx])))
-        print(f"  sampled sinks={len(idx)} worst/allowed={worst:.3g}", flush=True)
-        assert worst <= 1.0
     finally:
         ngr.tree_free(ctx, tree)
+    law = oracle.law_of(p)
+    ao = np.full((3, p.n), np.nan)
+    so = np.full(p.n, np.nan)
+    pp = pn = ties = 0
+    pnb = np.zeros(p.D, np.int64)
+    parts = np.array_split(np.arange(T.n_groups, dtype=np.uint32), chunks)
+    for c, sel in enumerate(parts):
+        a, s, co, gco = T.force(law, groups=sel, group_counts=True)
+        assert np.array_equal(gc[sel], gco)
+        sinks = np.concatenate([np.arange(go["start"][k], go["start"][k] + go["count"][k]) for k in sel])
+        idx = nd["perm"][sinks]
+        ao[:, idx] = a[:, idx]
+        so[idx] = s[idx]
+        pp += co["pp"]
+        pn += co["pn"]
+        ties += co["near_ties"]
+        pnb += np.array(co["pn_species"], np.int64)
+        say(f"  oracle chunk {c + 1}/{chunks}: {co['pp'] + co['pn']} interactions")
+    assert not np.isnan(ao).any()
+    assert (st["interactions_pp"], st["interactions_pn"]) == (pp, pn)
+    assert st["interactions_pn_species"][:p.D] == pnb.tolist()
+    assert st["near_ties"] == ties
+    ok, worst, rms, mx = force_gate(acc, ao, so)
+    say(f"  interactions={pp + pn} worst/allowed={worst:.3g} max|da|/rms={mx:.3g}")
+    assert ok, f"force gate: worst ratio {worst}"

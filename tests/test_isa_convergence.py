@@ -41,5 +41,8 @@ def test_no_convergent_op_in_divergent_loop(src, tmp_path):
     kernels = list(re.finditer(r"^(_Z\S+):\s*;", text, re.M))
     assert kernels
     for km in kernels:
-        body = text[km.end(): text.find("s_endpgm", km.end())].splitlines()
+        # a function's code ends at its .Lfunc_end label (a kernel at its
+        # s_endpgm, an outlined device function at its return)
+        end = text.find(".Lfunc_end", km.end())
+        body = text[km.end(): end if end >= 0 else len(text)].splitlines()
         assert check(body) == [], f"{km.group(1)}: cross-lane op inside a divergent loop"

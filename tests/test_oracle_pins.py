@@ -530,3 +530,42 @@ def test_counts_and_self_exclusion(oracle_lib):
         pn = int((M[:, node[kind == 1]] > 0).sum()) * ns
         assert (int(gc[k, 2]), int(gc[k, 3])) == (pn, pp)
         assert len(set(node.tolist())) == len(node)  # each node at most once
+
+
+def test_counts_per_source_species(oracle_lib):
+    """Particle-node interactions split by source species: one per accepted
+    node whose species-b monopole is non-empty, times the group's sinks, and
+    the split adds up to the total."""
+    p = synth.clustered_problem(6000, 3, 8, ntab=64)
+    T = oracle_lib.Tree.of(p)
+    law = oracle_lib.law_of(p)
+    _, _, cnt, gc = T.force(law, group_counts=True)
+    assert sum(cnt["pn_species"]) == cnt["pn"]
+    M, _ = T.monopole_arrays()
+    g = T.group_arrays()
+    want = np.zeros(p.D, np.int64)
+    for k in range(T.n_groups):
+        L = T.group_list(law, k)
+        node = (L & np.uint64(0xffffffff)).astype(np.int64)[(L >> np.uint64(32)) == 1]
+        want += (M[:, node] > 0).sum(axis=1) * int(g["count"][k])
+    assert want.tolist() == cnt["pn_species"]
+
+
+@pytest.mark.parametrize("rel,ties", [(2.5e-7, 2), (-2.5e-7, 2), (1.5e-6, 0), (-1.5e-6, 0)])
+def test_near_tie_count(oracle_lib, rel, ties):
+    """Two bodies at r = r_cut (1 + rel) along x: both see the other within
+    1e-6 r_cut^2 of the cut-off (|r^2 - r_cut^2| = 2 |rel| r_cut^2 to first
+    order) exactly when |rel| < 5e-7, one near tie per sink."""
+    r_cut, box = 0.1, 1.0
+    d = r_cut * (1.0 + rel)
+    X = np.zeros((3, 2), np.uint64)
+    X[0, 0] = np.uint64(1) << np.uint64(60)
+    X[0, 1] = X[0, 0] + np.uint64(round(d / box * 2.0 ** 64))
+    t = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, 0.02), 256, r_cut, "r")
+    law = oracle_lib.make_law(np.ones((1, 1)), t[None, None], "r", r_cut, 1e-3, 0.5)
+    T = oracle_lib.Tree(X, np.zeros(2, np.uint8), np.full(2, 0.5), 1, box, 16)
+    T.monopoles()
+    T.groups(64)
+    _, slack, cnt, _ = T.force(law)
+    assert cnt["pp"] == 2 and cnt["near_ties"] == ties
+    assert np.all((slack > 0) == (ties > 0))
