@@ -47,6 +47,10 @@ def lib():
             "orc_num_threads": (C.c_int, []),
             "orc_lattice": (None, [u64, P, dbl, P]),
             "orc_morton": (u64, [u32, u32, u32]),
+            "orc_hilbert": (u64, [u32, u32, u32]),
+            "orc_hilbert_decode": (None, [u64, P]),
+            "orc_keys_order": (None, [u64, P, P, u32, P]),
+            "orc_tree_build_order": (P, [u64, u32, dbl, P, P, P, u32, u32]),
             "orc_keys": (None, [u64, P, P, P]),
             "orc_sort": (None, [u64, P, P]),
             "orc_tree_build": (P, [u64, u32, dbl, P, P, P, u32]),
@@ -164,11 +168,24 @@ def morton(kx: int, ky: int, kz: int) -> int:
     return int(lib().orc_morton(kx, ky, kz))
 
 
-def keys(X: np.ndarray, species: np.ndarray) -> np.ndarray:
+KEY_ORDER = {"morton": 0, "hilbert": 1}
+
+
+def hilbert(kx: int, ky: int, kz: int) -> int:
+    return int(lib().orc_hilbert(kx, ky, kz))
+
+
+def hilbert_decode(h: int):
+    k = np.zeros(3, np.uint32)
+    lib().orc_hilbert_decode(int(h), _p(k))
+    return tuple(int(v) for v in k)
+
+
+def keys(X: np.ndarray, species: np.ndarray, key_order: str = "morton") -> np.ndarray:
     X = np.ascontiguousarray(X, dtype=np.uint64)
     s = np.ascontiguousarray(species, dtype=np.uint8)
     K = np.empty(s.shape[0], dtype=np.uint64)
-    lib().orc_keys(s.shape[0], _p(X), _p(s), _p(K))
+    lib().orc_keys_order(s.shape[0], _p(X), _p(s), KEY_ORDER[key_order], _p(K))
     return K
 
 
@@ -187,21 +204,21 @@ def factor(T: np.ndarray, grid: str, r2: float, r_cut: float) -> float:
 class Tree:
     """The oracle's tree over one particle set (lattice positions)."""
 
-    def __init__(self, X, species, mass, D: int, box: float, leaf_size: int = 16):
+    def __init__(self, X, species, mass, D: int, box: float, leaf_size: int = 16, key_order: str = "morton"):
         self.X = np.ascontiguousarray(X, dtype=np.uint64)
         self.species = np.ascontiguousarray(species, dtype=np.uint8)
         self.mass = np.ascontiguousarray(mass, dtype=np.float64)
         self.n = int(self.species.shape[0])
         self.D, self.box = int(D), float(box)
-        self._t = lib().orc_tree_build(self.n, self.D, self.box, _p(self.X), _p(self.species),
-                                       _p(self.mass), int(leaf_size))
+        self._t = lib().orc_tree_build_order(self.n, self.D, self.box, _p(self.X), _p(self.species),
+                                             _p(self.mass), int(leaf_size), KEY_ORDER[key_order])
         self.n_nodes = int(lib().orc_tree_n_nodes(self._t))
         self._mono = False
         self.n_groups = None
 
     @classmethod
     def of(cls, p, group_size: Optional[int] = None):
-        t = cls(lattice_of(p), p.species, p.mass, p.D, box_of(p), p.leaf_size)
+        t = cls(lattice_of(p), p.species, p.mass, p.D, box_of(p), p.leaf_size, getattr(p, "key_order", "morton"))
         t.monopoles()
         t.groups(p.group_size if group_size is None else group_size)
         return t

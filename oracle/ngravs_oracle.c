@@ -27,6 +27,7 @@
 struct orc_tree {
     uint64_t n;
     uint32_t D, B;
+    uint32_t key_order;   /* ORC_KEY_MORTON or ORC_KEY_HILBERT */
     double box;
     /* particle data in sorted order */
     uint32_t* perm;       /* sorted position -> input index */
@@ -94,14 +95,95 @@ uint64_t orc_morton(uint32_t kx, uint32_t ky, uint32_t kz)
     return m;
 }
 
-void orc_keys(uint64_t n, const uint64_t* X, const uint8_t* species, uint64_t* K)
+/*
+ * The Peano-Hilbert curve the paper's code sorts by (section 2.4), on the
+ * same 20-bit lattice, by the transpose method of J. Skilling, "Programming
+ * the Hilbert curve" (AIP Conf. Proc. 707, 2004). The three coordinates are
+ * turned into the curve's transposed form (bit j of component i is bit
+ * 3j + 2 - i of the index) by undoing, from the top bit down, the reflections
+ * and axis exchanges of each sub-cube and then Gray-coding; the index is the
+ * interleave of the transposed components, x's component the most
+ * significant of every 3-bit digit (as in the Morton layout). Every aligned
+ * cube of side 2^(20-l) is one contiguous index range of 3(20-l) low bits.
+ */
+static void hilbert_axes_to_transpose(uint32_t x[3])
+{
+    const uint32_t top = 1u << (ORC_LEVELS - 1);
+    for (uint32_t q = top; q > 1; q >>= 1) {
+        const uint32_t low = q - 1;
+        for (unsigned i = 0; i < 3; ++i) {
+            if (x[i] & q) {
+                x[0] ^= low;                        /* reflect the low bits of x */
+            } else {
+                const uint32_t t = (x[0] ^ x[i]) & low;   /* exchange the low bits of x and axis i */
+                x[0] ^= t;
+                x[i] ^= t;
+            }
+        }
+    }
+    x[1] ^= x[0];                                   /* Gray code */
+    x[2] ^= x[1];
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (x[2] & q) t ^= q - 1;
+    for (unsigned i = 0; i < 3; ++i) x[i] ^= t;
+}
+
+static void hilbert_transpose_to_axes(uint32_t x[3])
+{
+    const uint32_t t0 = x[2] >> 1;                  /* Gray decode */
+    x[2] ^= x[1];
+    x[1] ^= x[0];
+    x[0] ^= t0;
+    for (uint32_t q = 2; q != (1u << ORC_LEVELS); q <<= 1) {   /* redo the exchanges and reflections */
+        const uint32_t low = q - 1;
+        for (int i = 2; i >= 0; --i) {
+            if (x[i] & q) {
+                x[0] ^= low;
+            } else {
+                const uint32_t t = (x[0] ^ x[i]) & low;
+                x[0] ^= t;
+                x[i] ^= t;
+            }
+        }
+    }
+}
+
+uint64_t orc_hilbert(uint32_t kx, uint32_t ky, uint32_t kz)
+{
+    uint32_t x[3] = {kx, ky, kz};
+    hilbert_axes_to_transpose(x);
+    uint64_t h = 0;
+    for (unsigned b = 0; b < ORC_LEVELS; ++b)
+        for (unsigned i = 0; i < 3; ++i)
+            h |= (uint64_t)((x[i] >> b) & 1u) << (3 * b + 2 - i);
+    return h;
+}
+
+void orc_hilbert_decode(uint64_t h, uint32_t k[3])
+{
+    uint32_t x[3] = {0, 0, 0};
+    for (unsigned b = 0; b < ORC_LEVELS; ++b)
+        for (unsigned i = 0; i < 3; ++i)
+            x[i] |= (uint32_t)((h >> (3 * b + 2 - i)) & 1u) << b;
+    hilbert_transpose_to_axes(x);
+    for (unsigned i = 0; i < 3; ++i) k[i] = x[i];
+}
+
+void orc_keys_order(uint64_t n, const uint64_t* X, const uint8_t* species, uint32_t key_order, uint64_t* K)
 {
     for (uint64_t i = 0; i < n; ++i) {
         uint32_t kx = (uint32_t)(X[i] >> 44);
         uint32_t ky = (uint32_t)(X[n + i] >> 44);
         uint32_t kz = (uint32_t)(X[2 * n + i] >> 44);
-        K[i] = ((uint64_t)species[i] << KEY_BITS) | orc_morton(kx, ky, kz);
+        uint64_t c = key_order == ORC_KEY_HILBERT ? orc_hilbert(kx, ky, kz) : orc_morton(kx, ky, kz);
+        K[i] = ((uint64_t)species[i] << KEY_BITS) | c;
     }
+}
+
+void orc_keys(uint64_t n, const uint64_t* X, const uint8_t* species, uint64_t* K)
+{
+    orc_keys_order(n, X, species, ORC_KEY_MORTON, K);
 }
 
 /* ---------------------------------------------------------------- sort --
@@ -133,12 +215,20 @@ static uint32_t deinterleave(uint64_t prefix, unsigned level, unsigned axis_shif
     return c;
 }
 
-/* Cell of a node in 20-bit key units: [c, c + 2^(20-level)) per axis. */
+/* Cell of a node in 20-bit key units: [c, c + 2^(20-level)) per axis. With
+ * the Hilbert order the prefix is decoded (the point at the start of the
+ * node's index range lies in its cell) and cut to the level. */
 static void node_cell(const orc_tree* t, uint64_t i, uint32_t c[3], uint32_t* S)
 {
     unsigned l = t->level[i];
-    for (unsigned a = 0; a < 3; ++a)
-        c[a] = l ? deinterleave(t->prefix[i], l, 2 - a) << (ORC_LEVELS - l) : 0u;
+    if (t->key_order == ORC_KEY_HILBERT) {
+        uint32_t k[3];
+        orc_hilbert_decode(l ? t->prefix[i] << (KEY_BITS - 3 * l) : 0u, k);
+        for (unsigned a = 0; a < 3; ++a) c[a] = l ? (k[a] >> (ORC_LEVELS - l)) << (ORC_LEVELS - l) : 0u;
+    } else {
+        for (unsigned a = 0; a < 3; ++a)
+            c[a] = l ? deinterleave(t->prefix[i], l, 2 - a) << (ORC_LEVELS - l) : 0u;
+    }
     *S = 1u << (ORC_LEVELS - l);
 }
 
@@ -178,16 +268,18 @@ static void grow_nodes(orc_tree* t)
  * section 2.2). Nodes are appended breadth first, which orders them by level
  * and then by prefix.
  */
-orc_tree* orc_tree_build(uint64_t n, uint32_t D, double box, const uint64_t* X,
-                         const uint8_t* species, const double* mass, uint32_t leaf_size)
+orc_tree* orc_tree_build_order(uint64_t n, uint32_t D, double box, const uint64_t* X,
+                               const uint8_t* species, const double* mass, uint32_t leaf_size,
+                               uint32_t key_order)
 {
     orc_tree* t = calloc(1, sizeof(orc_tree));
     t->n = n;
     t->D = D;
     t->B = leaf_size;
+    t->key_order = key_order;
     t->box = box;
     uint64_t* Kin = malloc((n ? n : 1) * sizeof(uint64_t));
-    orc_keys(n, X, species, Kin);
+    orc_keys_order(n, X, species, key_order, Kin);
     t->perm = malloc((n ? n : 1) * sizeof(uint32_t));
     orc_sort(n, Kin, t->perm);
     t->K = malloc((n ? n : 1) * sizeof(uint64_t));
@@ -253,6 +345,12 @@ orc_tree* orc_tree_build(uint64_t n, uint32_t D, double box, const uint64_t* X,
         }
     }
     return t;
+}
+
+orc_tree* orc_tree_build(uint64_t n, uint32_t D, double box, const uint64_t* X,
+                         const uint8_t* species, const double* mass, uint32_t leaf_size)
+{
+    return orc_tree_build_order(n, D, box, X, species, mass, leaf_size, ORC_KEY_MORTON);
 }
 
 void orc_tree_free(orc_tree* t)

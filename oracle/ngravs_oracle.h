@@ -13,8 +13,9 @@
  * Conventions (all arrays are structure-of-arrays):
  *   - positions are 64-bit lattice coordinates X in [0, 2^64)^3; the point is
  *     X * 2^-64 * box;
- *   - "sorted order" is the order of the stable sort by (species, Morton key);
- *   - nodes are stored breadth first: by level, then by Morton prefix;
+ *   - "sorted order" is the order of the stable sort by (species, curve key),
+ *     the curve Morton or Peano-Hilbert;
+ *   - nodes are stored breadth first: by level, then by curve prefix;
  *   - per-species node arrays are laid out [species][node].
  */
 #ifndef NGRAVS_ORACLE_H
@@ -64,11 +65,22 @@ int      orc_num_threads(void);
 void     orc_lattice(uint64_t n, const double* x, double box, uint64_t* X);
 uint64_t orc_morton(uint32_t kx, uint32_t ky, uint32_t kz);
 void     orc_keys(uint64_t n, const uint64_t* X, const uint8_t* species, uint64_t* K);
+/* Peano-Hilbert index (60 bits) of a point of the 20-bit lattice, its
+ * inverse, and keys species << 60 | curve index in either order. */
+enum { ORC_KEY_MORTON = 0, ORC_KEY_HILBERT = 1 };
+uint64_t orc_hilbert(uint32_t kx, uint32_t ky, uint32_t kz);
+void     orc_hilbert_decode(uint64_t h, uint32_t k[3]);
+void     orc_keys_order(uint64_t n, const uint64_t* X, const uint8_t* species, uint32_t key_order, uint64_t* K);
 void     orc_sort(uint64_t n, const uint64_t* K, uint32_t* perm);
 
 /* tree */
 orc_tree* orc_tree_build(uint64_t n, uint32_t D, double box, const uint64_t* X,
                          const uint8_t* species, const double* mass, uint32_t leaf_size);
+/* As orc_tree_build with the particles sorted along the given curve
+ * (ORC_KEY_MORTON or ORC_KEY_HILBERT); prefixes are then curve prefixes. */
+orc_tree* orc_tree_build_order(uint64_t n, uint32_t D, double box, const uint64_t* X,
+                               const uint8_t* species, const double* mass, uint32_t leaf_size,
+                               uint32_t key_order);
 void     orc_tree_free(orc_tree* t);
 uint64_t orc_tree_n_nodes(const orc_tree* t);
 void     orc_tree_export(const orc_tree* t, uint32_t* perm, uint64_t* keys,

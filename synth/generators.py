@@ -77,6 +77,8 @@ class Problem:
     relative: Optional[dict] = None
     # pure-tree periodic mode: (D, D, n+1, n+1, n+1, 3) lattice correction tables, or None
     lattice_corr: Optional[np.ndarray] = None
+    # space-filling curve of the sort (section 2.4): "morton" or "hilbert" (Peano-Hilbert)
+    key_order: str = "morton"
 
     @property
     def ntab(self) -> int:
