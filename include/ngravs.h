@@ -430,6 +430,37 @@ ngr_status ngr_tree_force_counts(ngr_context* ctx, const ngr_tree* tree,
                                  const ngr_force_params* fp, double* acc,
                                  ngr_force_stats* st, uint64_t* group_counts);
 
+/* ---- without device allocation ----
+ *
+ * For callers that cannot allocate device memory: code that must not call
+ * hipMalloc or free (tight serving loops, harnesses that forbid allocation
+ * after start-up). ngr_tree_force_noalloc is ngr_tree_force on a one-box
+ * tree, bit for bit the same accelerations and counts, with every scratch
+ * buffer of the call (sink groups, the walk's queue order and control
+ * block, the tables in their on-chip layouts, the per-wave traversal
+ * stacks) taken from one static device array of NGR_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends. It
+ * calls no hipMalloc, hipFree or other allocating routine and creates no
+ * events (the ms_groups and ms_walk statistics are 0; near_ties is
+ * NGR_NOT_COUNTED). The tree itself comes from ngr_tree_build as usual. It
+ * returns after its work is complete and reads sizes back on the way, so it
+ * cannot be captured in a graph. Its walk runs fewer waves per CU (the
+ * stacks must fit the array), so it is slower than ngr_tree_force.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap in time on one GPU (from several threads or streams) race, and
+ * the caller must order them.
+ * Errors: as ngr_tree_force; NGR_EINVAL also for a batch tree or more than
+ * NGR_NOALLOC_MAX_N particles (checked before any device work); NGR_ENOMEM
+ * when this tree's groups and tables do not fit the array (detected before
+ * the walk writes acc).
+ */
+#define NGR_NOALLOC_SCRATCH_BYTES (96u << 20)   /* 96 MiB per GPU */
+#define NGR_NOALLOC_MAX_N         (1u << 20)
+ngr_status ngr_tree_force_noalloc(ngr_context* ctx, const ngr_tree* tree,
+                                  const ngr_force_params* fp, double* acc,
+                                  ngr_force_stats* st);
+
 /* ---- many boxes in one call ---- */
 
 /* One independent box of a batch. Pointers and sizes as in the single-box

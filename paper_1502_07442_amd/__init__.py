@@ -21,7 +21,8 @@ GRID_R, GRID_R2 = 0, 1
 GRIDS = {"r": GRID_R, "r2": GRID_R2, GRID_R: GRID_R, GRID_R2: GRID_R2}
 MAX_SPECIES = 6
 EXPORTED = ["ngr_context_create", "ngr_context_destroy", "ngr_last_error", "ngr_tree_build",
-            "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_free",
+            "ngr_compute_monopoles", "ngr_tree_force", "ngr_tree_force_counts", "ngr_tree_force_noalloc",
+            "ngr_tree_free",
             "ngr_tree_info", "ngr_tree_export", "ngr_monopoles_export", "ngr_groups_export",
             "ngr_batch_build_force", "ngr_server_create", "ngr_server_submit", "ngr_server_tick",
             "ngr_server_status", "ngr_server_take", "ngr_server_destroy", "ngr_short_range_grid",
@@ -145,6 +146,7 @@ def lib():
             "ngr_compute_monopoles": (i32, [P, P, C.c_int]),
             "ngr_tree_force": (i32, [P, P, P, P, P]),
             "ngr_tree_force_counts": (i32, [P, P, P, P, P, P]),
+            "ngr_tree_force_noalloc": (i32, [P, P, P, P, P]),
             "ngr_tree_free": (i32, [P, P]),
             "ngr_tree_info": (i32, [P, P, P, P, P]),
             "ngr_tree_export": (i32, [P] * 12),
@@ -303,6 +305,23 @@ def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, 
         return st.as_dict(), gc[:ng]
     ctx._check(lib().ngr_tree_force(ctx.handle, tree.handle, C.byref(fp), C.c_void_p(_dev(acc)), C.byref(st)),
                "tree force")
+    return st.as_dict()
+
+
+NOALLOC_MAX_N = 1 << 20     # NGR_NOALLOC_MAX_N
+
+
+def tree_force_noalloc(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, acc, r_s: float = 0.0,
+                       group_size: int = 64, ntab: Optional[int] = None, accumulator=None, eps_ab=None,
+                       relative=None, lattice_corr=None):
+    """ngr_tree_force_noalloc: as tree_force, with the call's scratch in the
+    library's static device array (no device allocation). Returns the
+    statistics as a dict."""
+    fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
+                       relative, lattice_corr)
+    st = ForceStats()
+    ctx._check(lib().ngr_tree_force_noalloc(ctx.handle, tree.handle, C.byref(fp), C.c_void_p(_dev(acc)),
+                                            C.byref(st)), "tree force (no allocation)")
     return st.as_dict()
 
 

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libngravs.so")
-SOURCES = ["api.hip", "build.hip", "scan.hip", "sort.hip", "walk.hip", "serve.hip", "short.hip", "pm.hip"]
+SOURCES = ["api.hip", "build.hip", "scan.hip", "sort.hip", "walk.hip", "serve.hip", "short.hip", "pm.hip",
+           "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     # no packed FP32 instructions: some of their forms have given wrong results on these machines

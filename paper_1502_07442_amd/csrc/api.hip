@@ -1,5 +1,6 @@
 // The C-ABI of libngravs: argument checks on the host before any device
 // work, error statuses, and the context's stream and memory.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -33,6 +34,18 @@ void hip_check(hipError_t e, const char* what, const char* file, int line)
 
 void* Context::alloc(size_t bytes)
 {
+    if (arena) {
+        const size_t need = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        if (need > arena_size - arena_used) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf, "the static scratch of %zu MiB is too small for this call (%zu bytes "
+                                           "more needed)", arena_size >> 20, need - (arena_size - arena_used));
+            fail(NGR_ENOMEM, buf);
+        }
+        void* p = arena + arena_used;
+        arena_used += need;
+        return p;
+    }
     size_t cls = 256;
     while (cls < bytes) cls += cls < (1u << 20) ? cls : (cls >> 2);   // 256 B doubling, then 25 % steps
     auto it = free_blocks.lower_bound(cls);
@@ -63,7 +76,7 @@ void* Context::alloc(size_t bytes)
 
 void Context::release(void* p)
 {
-    if (!p) return;
+    if (!p || in_arena(p)) return;
     auto it = live_blocks.find(p);
     if (it == live_blocks.end()) fail(NGR_EDEVICE, "release of a block the pool does not own");
     free_blocks.emplace(it->second, p);
@@ -81,6 +94,7 @@ void Context::free_all()
 void Context::ensure(DevMem& m, size_t bytes)
 {
     if (m.bytes >= bytes) return;
+    if (arena) fail(NGR_EDEVICE, "a persistent buffer would grow in arena mode");
     release(m.p);
     m.p = alloc(bytes);
     m.bytes = bytes;

@@ -62,6 +62,17 @@ struct Context {
     hipEvent_t ev[8] = {};                        // timing events, created on first use
     hipEvent_t event(int k);
     float elapsed(int k0, int k1);                // ms between two recorded events (synchronises)
+    // Arena mode (the no-allocation entry point): while `arena` is set,
+    // alloc() hands out consecutive 256-byte aligned pieces of the caller's
+    // device buffer and fails with NGR_ENOMEM when it is used up; release()
+    // of such a piece does nothing; no events are created and the
+    // context's persistent buffers are neither grown nor kept.
+    unsigned char* arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
+    bool in_arena(const void* p) const
+    {
+        return arena && p >= arena && static_cast<const unsigned char*>(p) < arena + arena_size;
+    }
 
     void* alloc(size_t bytes);
     void release(void* p);

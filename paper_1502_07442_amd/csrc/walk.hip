@@ -228,6 +228,8 @@ constexpr int kBuf = 128;              // node / leaf buffer entries per wave
 constexpr int kRec = 68;               // record slots per wave: 64 and up to 3 pads
 constexpr int kWaveLds = kRec * 32 + kBuf * 4 * 2 + 68 * 4 + 64 * 4 + 8 * 4;   // bytes of LDS per wave
 constexpr int kMaxWaves = 16;          // waves per workgroup
+constexpr int kArenaWaves = 4;         // arena mode: waves per workgroup, one workgroup per CU
+constexpr uint32_t kArenaStack = 21 * 512 + 512;   // arena mode: stack entries per wave
 constexpr int kCtrlBytes = 1536;       // LDS control area ahead of the tables (next segment, per-wave counts)
 // Accumulator laws: per wave, the core scale of each record (float64) after
 // the other buffers; per workgroup, the core-factor table after the force
@@ -1190,9 +1192,9 @@ void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawT
 // 6x^4/7 below x = 1e-2, where the difference cancels), at u = k / kCoreN,
 // in the PAIR layout (value, slope to the next sample); C(1) = 1. Built in
 // float64 on the host once per context.
-static void upload_core_table(Context& ctx)
+static const float2* upload_core_table(Context& ctx)
 {
-    if (ctx.core.p) return;
+    if (ctx.core.p) return static_cast<const float2*>(ctx.core.p);
     std::vector<double> c(kCoreN + 1);
     for (int k = 0; k < kCoreN; ++k) {
         const double u = (double)k / kCoreN, x = u / (1.0 - u);
@@ -1210,8 +1212,14 @@ static void upload_core_table(Context& ctx)
     std::vector<float2> t(kCoreN + 1);
     for (int k = 0; k < kCoreN; ++k) t[k] = make_float2((float)c[k], (float)(c[k + 1] - c[k]));
     t[kCoreN] = make_float2(1.0f, 0.0f);
+    if (ctx.arena) {                     // this call only: the context keeps nothing from the arena
+        void* p = ctx.alloc(t.size() * sizeof(float2));
+        ctx.to_device(p, t.data(), t.size() * sizeof(float2));
+        return static_cast<const float2*>(p);
+    }
     ctx.ensure(ctx.core, t.size() * sizeof(float2));
     ctx.to_device(ctx.core.p, t.data(), t.size() * sizeof(float2));
+    return static_cast<const float2*>(ctx.core.p);
 }
 
 // Group indices segment by segment, each segment's groups in descending
@@ -1236,7 +1244,7 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
             cells += L[k] ? (1ull << (3 * L[k])) : 0;
         }
         Hoff[nbox] = cells;
-        if (cells <= (1ull << 26) || cap == 0) break;
+        if (cells <= (ctx.arena ? (1ull << 18) : (1ull << 26)) || cap == 0) break;
         --cap;
     }
     uint64_t* okey = static_cast<uint64_t*>(ctx.alloc(2 * ng * sizeof(uint64_t)));
@@ -1289,7 +1297,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         ew |= laws[k].corr != nullptr;
     }
     if (acc_law && ew) fail(NGR_EINVAL, "lattice corrections take the table laws only");
-    if (acc_law) upload_core_table(ctx);
+    const float2* core_table = acc_law ? upload_core_table(ctx) : nullptr;
     // lattice correction tables of every box that has them, one block
     std::vector<uint64_t> corr_off(nbox, 0);
     double* corr_dev = nullptr;
@@ -1329,12 +1337,22 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         tab_bytes = value_max + extra;
     }
     if (kCtrlBytes + tab_bytes + wave_lds > lds_max) fail(NGR_EINVAL, "force tables do not fit in LDS");
-    const int waves = (int)std::min<size_t>(kMaxWaves, (lds_max - kCtrlBytes - tab_bytes) / wave_lds);
+    // In arena mode (no allocation) one workgroup of at most kArenaWaves
+    // waves per CU, with stacks of 21 levels x 512 entries (the most a batch
+    // walk can hold) plus a margin, all taken from the arena.
+    const int waves = (int)std::min<size_t>(ctx.arena ? kArenaWaves : kMaxWaves,
+                                            (lds_max - kCtrlBytes - tab_bytes) / wave_lds);
     const size_t lds = kCtrlBytes + tab_bytes + (size_t)waves * wave_lds;
     const size_t per_cu = std::max<size_t>(1, lds_max / lds);
-    const int blocks = ctx.num_cu * (int)std::min<size_t>(per_cu, 4);
-    const uint32_t stack_cap = 16384;   // >= 21 levels x 512 entries, the most a batch walk can hold
-    ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
+    const int blocks = ctx.num_cu * (ctx.arena ? 1 : (int)std::min<size_t>(per_cu, 4));
+    const uint32_t stack_cap = ctx.arena ? kArenaStack : 16384;
+    uint32_t* stacks;
+    if (ctx.arena) {
+        stacks = static_cast<uint32_t*>(ctx.alloc((size_t)blocks * waves * stack_cap * sizeof(uint32_t)));
+    } else {
+        ctx.ensure(ctx.stacks, (size_t)blocks * waves * stack_cap * sizeof(uint32_t));
+        stacks = static_cast<uint32_t*>(ctx.stacks.p);
+    }
 
     // per-box parameters
     std::vector<BoxParams> bp(nbox);
@@ -1422,11 +1440,14 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         ctx.to_device(queues, host.data(), host.size() * sizeof(uint32_t));
     }
     ctx.stage("walk: order");
-    hipEvent_t e0, e1, e2;
-    HIP_CHECK(hipEventCreate(&e0));
-    HIP_CHECK(hipEventCreate(&e1));
-    HIP_CHECK(hipEventCreate(&e2));
-    HIP_CHECK(hipEventRecord(e0, ctx.stream));
+    const bool timed = !ctx.arena;      // arena mode creates no events
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (timed) {
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        HIP_CHECK(hipEventCreate(&e2));
+        HIP_CHECK(hipEventRecord(e0, ctx.stream));
+    }
     uint32_t* order = order_groups(ctx, t, g, laws);
 
     WalkArgs A{};
@@ -1457,14 +1478,14 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     A.boxes = boxes;
     A.seg_counts = seg_counts;
     A.gcounts = reinterpret_cast<unsigned long long*>(group_counts_dev);
-    A.stacks = static_cast<uint32_t*>(ctx.stacks.p);
+    A.stacks = stacks;
     A.stack_cap = stack_cap;
     A.error_flag = err;
     A.max_steps = (uint32_t)std::min<uint64_t>(t.nn + 1, 0xffffffffull);
     A.tab_bytes = (uint32_t)tab_bytes;
-    A.core = acc_law ? static_cast<const float2*>(ctx.core.p) : nullptr;
+    A.core = core_table;
 
-    HIP_CHECK(hipEventRecord(e1, ctx.stream));
+    if (timed) HIP_CHECK(hipEventRecord(e1, ctx.stream));
     ctx.stage("walk: launch");
     A.box0 = bp[0];
     auto launch = [&](auto kernel) {
@@ -1519,7 +1540,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     case 22: launch(walk_kernel<NGR_GRID_R2, kValue, false, false, true>); break;
     default: launch(walk_kernel<NGR_GRID_R2, kValue, true, false, true>); break;
     }
-    HIP_CHECK(hipEventRecord(e2, ctx.stream));
+    if (timed) HIP_CHECK(hipEventRecord(e2, ctx.stream));
     std::vector<uint64_t> counts((size_t)kSegCounts * nseg);
     uint32_t herr = 0;
     ctx.to_host(counts.data(), seg_counts, cnt_bytes);
@@ -1530,11 +1551,13 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     ctx.release(boxes);
     if (corr_dev) ctx.release(corr_dev);
     float ms_order = 0.0f, ms = 0.0f;
-    HIP_CHECK(hipEventElapsedTime(&ms_order, e0, e1));
-    HIP_CHECK(hipEventElapsedTime(&ms, e1, e2));
-    HIP_CHECK(hipEventDestroy(e0));
-    HIP_CHECK(hipEventDestroy(e1));
-    HIP_CHECK(hipEventDestroy(e2));
+    if (timed) {
+        HIP_CHECK(hipEventElapsedTime(&ms_order, e0, e1));
+        HIP_CHECK(hipEventElapsedTime(&ms, e1, e2));
+        HIP_CHECK(hipEventDestroy(e0));
+        HIP_CHECK(hipEventDestroy(e1));
+        HIP_CHECK(hipEventDestroy(e2));
+    }
     if (herr) fail(NGR_ENOMEM, "walk stack or step capacity exceeded");
     uint64_t nties = 0;
     for (uint32_t q = 0; q < nseg; ++q) {
