@@ -92,6 +92,11 @@ typedef struct {
 
 /* leaf_size: a node is a leaf once it holds at most this many particles of
  * all species together (1..64; 0 means 16), or at the deepest level (20).
+ * key_order: the space-filling curve of the sort (section 2.4), NGR_KEY_MORTON
+ * (0) or NGR_KEY_HILBERT (1, the Peano-Hilbert curve of the paper's code). The
+ * curve orders particles and children only: the node cells, counts and
+ * leaves are the same; sink groups, being runs of consecutive children,
+ * follow the order (and with them the interaction lists).
  * non_periodic: nonzero for a non-periodic box (section 2: non-periodic
  * runs use the tree alone). Positions (pos, not lattice) must lie in
  * [0, box)^3 and pairs interact by their plain separation, with no image:
@@ -100,9 +105,12 @@ typedef struct {
  * exported lattice coordinates and centres of mass refer to that larger
  * box. r_cut may then reach 2 box (any r_cut >= sqrt(3) box keeps every
  * pair). A non-periodic tree takes no PM force. */
+#define NGR_KEY_MORTON  0
+#define NGR_KEY_HILBERT 1
 typedef struct {
     uint32_t leaf_size;
     uint32_t non_periodic;
+    uint32_t key_order;
 } ngr_tree_params;
 
 /*
@@ -111,9 +119,10 @@ typedef struct {
  * tree spans all species and every node records, per species, where its
  * particles start and how many there are, N_perp).
  * Steps on the device: positions -> 64-bit lattice, keys species<<60 |
- * Morton60, stable radix sort, gather, breadth-first octree.
+ * curve index (Morton or Peano-Hilbert, 60 bits), stable radix sort, gather,
+ * breadth-first octree.
  * Errors: NGR_EINVAL for D outside 1..6, box <= 0 or not finite, n >= 2^32,
- * leaf_size > 64, missing pointers, both or neither of pos / lattice, a
+ * leaf_size > 64, key_order not 0 or 1, missing pointers, both or neither of pos / lattice, a
  * species id >= D, a mass < 0 or not finite, a position not finite; for a
  * non-periodic box also lattice input and a position outside [0, box).
  * On success *out owns device memory until ngr_tree_free.
@@ -141,7 +150,10 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *            line through the two neighbours, f = 0 for r >= r_cut
  *   r_s      split scale, used only when tables == NULL (> 0 then)
  *   r_cut    cut-off radius, 0 < r_cut < box / 2 (see lattice_corr)
- *   eps      Plummer softening, >= 0
+ *   eps      Plummer softening: 0, or at least 1e-12 box (the kernel factor
+ *            (r^2 + eps^2)^(-3/2) is taken in float32 in units of the box;
+ *            with eps = 0 a separate float64-refined factor serves pairs
+ *            down to ~1e-19 box, and coincident pairs contribute nothing)
  *   theta    opening angle, > 0
  *   group_size  sinks per walk, 16, 32 or 64 (0: the library's choice: 32, or
  *            what ngr_autotune chose for the box's class on this context)
@@ -156,12 +168,13 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *            and of the sink (c_a, its mass m). Readings: the core radius
  *            of the Eq. (15) density is M / (4 pi beta), the radius with
  *            which it holds mass M; a point-like source adds no core, in
- *            Eq. (10) as elsewhere. A pair with s = 0 (massless cored
+ *            Phi_10, Eq. (16), as elsewhere. A pair with s = 0 (massless cored
  *            bodies) keeps the softened law. f_ab still multiplies.
  *   cored    accumulator: bit b set = species b is cored (< 2^D)
  *   beta     accumulator: the dimensionless scale of Eqs. (13)-(15), > 0
  *   eps_ab   host, D x D float64 Plummer softening of each species pair (row =
- *            sink species; section 2's D^2 softenings), each finite and >= 0,
+ *            sink species; section 2's D^2 softenings), each 0 or at least
+ *            1e-12 box as eps,
  *            or NULL for eps everywhere
  *   opening  NGR_OPEN_GEOMETRIC (0), the test described at ngr_tree_force, or
  *            NGR_OPEN_RELATIVE: section 2.2 keeps the stock code's relative
@@ -278,7 +291,7 @@ ngr_status ngr_tree_force(ngr_context* ctx, const ngr_tree* tree,
  * Gaussian split of scale r_s is
  *   f_short(r) = f_full(r) + 1/(2 pi^2) int_0^inf phibar(k) exp(-k^2 r_s^2)
  *                                       [sin(kr)/k - r cos(kr)] dk,
- * the derivative of phi - F^-1[phi(k) exp(-k^2 r_s^2)] (Eqs. (10), (11) with
+ * the derivative of phi - F^-1[phi(k) exp(-k^2 r_s^2)] (Eqs. (9), (10) with
  * the r'-integral in closed form); for Newton it is the factor
  * erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2). The integral is the
  * trapezoid rule on k_m = m dk, m = 0 .. nk-1, evaluated on the device.

@@ -707,7 +707,7 @@ double orc_factor(const double* T, uint32_t ntab, uint32_t grid, double r2, doub
  * density integrate to M / 2; M / (4 beta pi) integrates to M and, since the
  * mutual potential of two such densities has the sum of their core radii as
  * its scale, reproduces the scale (M_1 + m_1) / (4 pi beta) of Eq. (14). In
- * Eq. (10) (cored sink, point-like sources) the source carries no core, so
+ * Phi_10, Eq. (16) (cored sink, point-like sources) the source carries no core, so
  * its body count N_perp cannot enter the scale: s = m_1 / (4 pi beta) (the
  * printed form agrees for N_perp = 1). A monopole of N_perp bodies of a cored
  * species weighs M / N_perp per body (section 2.2's optional N_perp tracking);

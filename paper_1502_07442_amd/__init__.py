@@ -41,8 +41,11 @@ class Particles(C.Structure):
                 ("lattice", C.c_void_p), ("species", C.c_void_p), ("mass", C.c_void_p)]
 
 
+KEY_ORDER = {"morton": 0, "hilbert": 1}     # NGR_KEY_MORTON, NGR_KEY_HILBERT
+
+
 class TreeParams(C.Structure):
-    _fields_ = [("leaf_size", C.c_uint32), ("non_periodic", C.c_uint32)]
+    _fields_ = [("leaf_size", C.c_uint32), ("non_periodic", C.c_uint32), ("key_order", C.c_uint32)]
 
 
 class ForceParams(C.Structure):
@@ -234,13 +237,14 @@ class Tree:
 
 
 def tree_build(ctx: Context, *, D: int, box: float, species, mass, pos=None, lattice=None,
-               leaf_size: int = 16, periodic: bool = True) -> Tree:
+               leaf_size: int = 16, periodic: bool = True, key_order: str = "morton") -> Tree:
     """ngr_tree_build: device tensors species (uint8, n), mass (float64, n) and
     either pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n).
-    periodic=False: a non-periodic box (positions in [0, box)^3 only)."""
+    periodic=False: a non-periodic box (positions in [0, box)^3 only);
+    key_order "morton" or "hilbert" (the Peano-Hilbert curve)."""
     n = int(species.shape[0])
     p = Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
-    tp = TreeParams(leaf_size, 0 if periodic else 1)
+    tp = TreeParams(leaf_size, 0 if periodic else 1, KEY_ORDER[key_order])
     h = C.c_void_p()
     ctx._check(lib().ngr_tree_build(ctx.handle, C.byref(p), C.byref(tp), C.byref(h)), "tree build")
     return Tree(ctx, h)
@@ -448,10 +452,11 @@ class BatchBox:
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
                  leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
-                 accumulator=None, eps_ab=None, relative=None, lattice_corr=None):
+                 accumulator=None, eps_ab=None, relative=None, lattice_corr=None,
+                 key_order: str = "morton"):
         self.n = int(species.shape[0])
         self.particles = Particles(self.n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass))
-        self.tree = TreeParams(leaf_size)
+        self.tree = TreeParams(leaf_size, 0, KEY_ORDER[key_order])
         self.force = _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
                                    relative, lattice_corr)
         self.acc = _dev(acc)

@@ -187,6 +187,8 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
         fail(NGR_EINVAL, where + "r_cut must be < box / 2");
     }
     if (!(std::isfinite(fp->eps) && fp->eps >= 0.0)) fail(NGR_EINVAL, where + "eps must be finite and >= 0");
+    // the pair factor (r^2 + eps^2)^(-3/2) is taken in float32 in units of the box
+    if (fp->eps > 0.0 && fp->eps < 1e-12 * box) fail(NGR_EINVAL, where + "eps must be 0 or at least 1e-12 box");
     if (!ngr::finite_pos(fp->theta)) fail(NGR_EINVAL, where + "theta must be finite and > 0");
     if (!fp->tables && !ngr::finite_pos(fp->r_s)) fail(NGR_EINVAL, where + "r_s must be finite and > 0 when tables is NULL");
     const uint32_t gs = fp->group_size;
@@ -207,8 +209,9 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
     }
     if (fp->eps_ab)
         for (uint32_t k = 0; k < D * D; ++k)
-            if (!(std::isfinite(fp->eps_ab[k]) && fp->eps_ab[k] >= 0.0))
-                fail(NGR_EINVAL, where + "eps_ab entries must be finite and >= 0");
+            if (!(std::isfinite(fp->eps_ab[k]) && fp->eps_ab[k] >= 0.0) ||
+                (fp->eps_ab[k] > 0.0 && fp->eps_ab[k] < 1e-12 * box))
+                fail(NGR_EINVAL, where + "eps_ab entries must be finite and 0 or at least 1e-12 box");
     if (fp->tables)
         for (uint64_t k = 0; k < (uint64_t)D * D * fp->ntab; ++k)
             if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, where + "a table entry is not finite");
@@ -244,6 +247,9 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
     if (p->n >= (1ull << 32) - 1) fail(NGR_EINVAL, where + "n must be < 2^32 - 1");
     const uint32_t B = tp && tp->leaf_size ? tp->leaf_size : 16;
     if (B > 64) fail(NGR_EINVAL, where + "leaf_size must be in 1..64");
+    const uint32_t order = tp ? tp->key_order : NGR_KEY_MORTON;
+    if (order != NGR_KEY_MORTON && order != NGR_KEY_HILBERT)
+        fail(NGR_EINVAL, where + "key_order must be NGR_KEY_MORTON or NGR_KEY_HILBERT");
     if (p->n) {
         if (!p->species || !p->mass) fail(NGR_EINVAL, where + "species or mass is NULL");
         if ((p->pos == nullptr) == (p->lattice == nullptr)) fail(NGR_EINVAL, where + "exactly one of pos and lattice must be set");
@@ -260,6 +266,7 @@ void check_particles(const ngr_particles* p, const ngr_tree_params* tp, const st
         b.box = 4.0 * p->box;
     }
     b.leaf_size = B;
+    b.key_order = order;
     b.pos = p->pos;
     b.lattice = p->lattice;
     b.species = p->species;

@@ -26,7 +26,7 @@ struct BoxInDev {
     uint64_t n, off;          // particles and first index in the concatenated arrays
     double box;
     double region;            // non-periodic: positions must lie in [0, region); 0 for periodic
-    uint32_t D, leaf;
+    uint32_t D, leaf, key_order;
 };
 
 // Spread the low 20 bits of v so that bit i lands on bit 3i.
@@ -41,12 +41,50 @@ __device__ inline uint64_t spread3(uint64_t v)
     return v;
 }
 
+// Peano-Hilbert index of a point of the 20-bit key lattice (the curve of
+// section 2.4), by J. Skilling's transpose method ("Programming the Hilbert
+// curve", 2004): from the top bit down, the low bits are reflected (x) or
+// exchanged with x (y, z) wherever the sub-cube of that bit requires; the
+// result is Gray-coded and the three components interleaved like the Morton
+// key (x's bit the highest of each 3-bit digit).
+__device__ inline uint64_t hilbert60(uint32_t x, uint32_t y, uint32_t z)
+{
+    for (uint32_t q = 1u << (kLevels - 1); q > 1u; q >>= 1) {
+        const uint32_t low = q - 1u;
+        if (x & q) x ^= low;
+        if (y & q) {
+            x ^= low;
+        } else {
+            const uint32_t t = (x ^ y) & low;
+            x ^= t;
+            y ^= t;
+        }
+        if (z & q) {
+            x ^= low;
+        } else {
+            const uint32_t t = (x ^ z) & low;
+            x ^= t;
+            z ^= t;
+        }
+    }
+    y ^= x;
+    z ^= y;
+    uint32_t flip = 0;
+    for (uint32_t q = 1u << (kLevels - 1); q > 1u; q >>= 1)
+        if (z & q) flip ^= q - 1u;
+    x ^= flip;
+    y ^= flip;
+    z ^= flip;
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
 // One thread per particle of box blockIdx.y (grid-stride over a bounded
 // grid): checks the species id, mass and position; converts the position to
 // the 64-bit lattice, X = floor(u * 2^64) with u = x / box taken modulo 1 (the
-// box is periodic); forms the key species << 60 | Morton interleave of the top
-// 20 bits of each axis (x the most significant bit of each 3-bit digit); and
-// counts each species of the box (the counts give its species segments).
+// box is periodic); forms the key species << 60 | curve index of the top 20
+// bits of each axis (Morton: x the most significant bit of each 3-bit digit;
+// or Peano-Hilbert); and counts each species of the box (the counts give its
+// species segments).
 // Per-box flags and counts take one global atomic per workgroup.
 __global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64_t* __restrict__ Xin,
                        uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, double* __restrict__ mass_cat,
@@ -90,7 +128,9 @@ __global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64
         Xin[g] = X[0];
         Xin[ntot + g] = X[1];
         Xin[2 * ntot + g] = X[2];
-        const uint64_t mo = (spread3(X[0] >> 44) << 2) | (spread3(X[1] >> 44) << 1) | spread3(X[2] >> 44);
+        const uint64_t mo = B.key_order == NGR_KEY_HILBERT
+                                ? hilbert60((uint32_t)(X[0] >> 44), (uint32_t)(X[1] >> 44), (uint32_t)(X[2] >> 44))
+                                : (spread3(X[0] >> 44) << 2) | (spread3(X[1] >> 44) << 1) | spread3(X[2] >> 44);
         keys[g] = ((uint64_t)(s & 0xfu) << kKeyBits) | mo;
         idx[g] = (uint32_t)g;
         mass_cat[g] = m;
@@ -224,14 +264,16 @@ __global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl
     flags[t] = tot > 0;
 }
 
-// Write the children found by split_level (in octant order, after all
-// children of earlier nodes of the level) and the parents' child links.
+// Write the children found by split_level (in key order, after all
+// children of earlier nodes of the level) and the parents' child links. A
+// child's cell is read off its first particle: the top lvl + 1 bits of each
+// lattice coordinate (whatever curve ordered the keys).
 __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t next_begin, uint32_t lvl,
                               uint32_t D, const uint32_t* __restrict__ flags, const uint32_t* __restrict__ offs,
                               const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ ccount,
                               uint8_t* level, uint64_t* prefix, int32_t* parent, int32_t* first_child,
                               uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count,
-                              uint32_t* node_box)
+                              uint32_t* node_box, const uint64_t* __restrict__ X, uint64_t n)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_level * 8) return;
@@ -252,14 +294,19 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
     node_box[c] = node_box[p];
     first_child[c] = -1;
     n_child[c] = 0;
-    uint4 pc = cell[p];
-    uint32_t half = 1u << (kLevels - lvl - 1);
-    cell[c] = make_uint4(pc.x + ((o >> 2) & 1u) * half, pc.y + ((o >> 1) & 1u) * half, pc.z + (o & 1u) * half,
-                         lvl + 1);
+    uint64_t j = 0;
+    bool found = false;
     for (uint32_t b = 0; b < D; ++b) {
         start[c * D + b] = cstart[t * D + b];
         count[c * D + b] = ccount[t * D + b];
+        if (!found && ccount[t * D + b]) {
+            j = cstart[t * D + b];
+            found = true;
+        }
     }
+    const uint32_t sh = 64u - (lvl + 1u), up = (uint32_t)kLevels - (lvl + 1u);
+    cell[c] = make_uint4((uint32_t)(X[j] >> sh) << up, (uint32_t)(X[n + j] >> sh) << up,
+                         (uint32_t)(X[2 * n + j] >> sh) << up, lvl + 1);
 }
 
 // Number of leaves (nodes without children), over a bounded grid with one
@@ -428,7 +475,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
         t.bD[k] = b.D;
         t.bbox[k] = b.box;
         t.bleaf[k] = b.leaf_size;
-        bin[k] = BoxInDev{b.pos, b.lattice, b.species, b.mass, b.n, n, b.box, b.region, b.D, b.leaf_size};
+        bin[k] = BoxInDev{b.pos, b.lattice, b.species, b.mass, b.n, n, b.box, b.region, b.D, b.leaf_size, b.key_order};
         n += b.n;
     }
     t.boff[nbox] = n;
@@ -578,7 +625,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
         grow_nodes(ctx, t, nb + next);
         hipLaunchKernelGGL(emit_children, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, nb, lvl, D, fl,
                            offs, cst, ccn, t.level, t.prefix, t.parent, t.first_child, t.n_child, t.cell, t.start,
-                           t.count, t.node_box);
+                           t.count, t.node_box, t.X, t.n);
         LAUNCH_CHECK("emit_children");
         ctx.release(fl);
         ctx.release(cst);

@@ -95,6 +95,7 @@ struct BoxIn {
     uint32_t D = 1;
     double box = 1.0;
     uint32_t leaf_size = 16;
+    uint32_t key_order = NGR_KEY_MORTON; // space-filling curve of the keys
     const double* pos = nullptr;         // 3 x n, or NULL
     const uint64_t* lattice = nullptr;   // 3 x n, or NULL
     const uint8_t* species = nullptr;

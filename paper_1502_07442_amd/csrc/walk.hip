@@ -244,7 +244,11 @@ constexpr int kCoreBytes = ((kCoreN + 1) * 8 + 255) & ~255;
 // r >= r_cut zeroed by a compare; half the LDS for twice the tables.
 enum TableMode { kPair = 0, kValue = 1 };
 
-// Force-law and walk parameters of one box.
+// Force-law and walk parameters of one box. The walk works in units of the
+// box side: offsets, eps^2 and the table scales are in those units and the
+// records carry G_ab m / box^2, so that the pair term's float32 kernel factor
+// (r^2 + eps^2)^(-3/2) has the same range whatever the caller's length unit
+// (box is 1 here; the accelerations come out in the caller's units).
 struct BoxParams {
     double box, inv_box, eps2, R2, theta2;
     double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];   // G_ab, row a = sink species, D x D
@@ -455,8 +459,8 @@ __device__ inline uint32_t eval_records(const PairParams& A, double eps2, float 
 // of kCoreN intervals (relative error below 3e-7); C(1) = 1 gives the
 // Newtonian factor, so a pair without a core (s = 0) takes the softened law
 // from r -> sqrt(r^2 + eps^2). r and 1 / (s + r) are the float32 hardware
-// estimates (rsqrt times r^2, reciprocal). The records
-// carry G m and rs[] the source's core scale.
+// estimates (rsqrt times r^2, reciprocal), cubed in float64. The records
+// carry G m / box^2 and rs[] the source's core scale (lengths in box units).
 template <int GRID, int TAB, bool WRAP, uint32_t K>
 __device__ inline void eval_cored(const PairParams& A, double eps2, const double4* __restrict__ rec,
                                   const double* __restrict__ rs, uint32_t iters, const void* __restrict__ tbv,
@@ -503,7 +507,10 @@ __device__ inline void eval_cored(const PairParams& A, double eps2, const double
             const float t0 = tv[k], t1 = tv[k + 1];
             f = t < tmax ? fmaf(w, t1 - t0, t0) : 0.0f;
         }
-        double coef = (double)(f * c * (y * y * y)) * s.w;
+        // the cube in float64: a pair without core or softening (s = eps = 0)
+        // may be closer than float32's cube allows (r below ~1e-13 box)
+        const double yd = (double)y;
+        double coef = (double)(f * c) * (yd * yd * yd) * s.w;
         coef = r2 > 0.0 ? coef : 0.0;
         ax = fma(coef, dx, ax);
         ay = fma(coef, dy, ay);
@@ -1311,11 +1318,18 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
             }
         }
         corr_dev = static_cast<double*>(ctx.alloc(total * sizeof(double)));
+        std::vector<double> scaled;
         for (uint32_t k = 0; k < nbox; ++k)
             if (laws[k].corr) {
-                const uint64_t m = laws[k].corr_n + 1ull;
-                ctx.to_device(corr_dev + corr_off[k], laws[k].corr,
-                              (uint64_t)laws[k].D * laws[k].D * m * m * m * 3ull * sizeof(double));
+                const uint64_t m = laws[k].corr_n + 1ull, cnt = (uint64_t)laws[k].D * laws[k].D * m * m * m * 3ull;
+                const double* src = laws[k].corr;
+                const double b2 = t.bbox[k] * t.bbox[k];   // the records carry G m / box^2
+                if (b2 != 1.0) {
+                    scaled.assign(src, src + cnt);
+                    for (double& v : scaled) v *= b2;
+                    src = scaled.data();
+                }
+                ctx.to_device(corr_dev + corr_off[k], src, cnt * sizeof(double));
             }
     }
     uint32_t pair_max = 0, value_max = 0;
@@ -1361,30 +1375,33 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         BoxParams& P = bp[k];
         std::memset(&P, 0, sizeof P);
         const double box = t.bbox[k];
-        P.box = box;
-        P.inv_box = 1.0 / box;
-        P.eps2 = law.eps * law.eps;
+        const double ib2 = 1.0 / (box * box);          // lengths squared in box units
+        P.box = 1.0;
+        P.inv_box = 1.0;
+        P.eps2 = law.eps * law.eps * ib2;
         const double q = law.r_cut / box * 2097152.0;   // r_cut in half key units
         P.R2 = law.corr ? __builtin_inf() : q * q;      // with lattice corrections every pair interacts
         P.theta2 = law.theta * law.theta;
         const double wl = std::floor(1048576.0 * (1.0 - 2.0 * law.r_cut / box)) - 1.0;
         P.wrap_limit = wl < 0.0 ? 0u : (uint32_t)wl;
-        const double rc2 = law.r_cut * law.r_cut;
+        const double rc2 = law.r_cut * law.r_cut;      // caller's units
+        const double rc2u = rc2 * ib2, rcu = law.r_cut / box;
         if (law.grid == NGR_GRID_R2) {
-            P.tscale = (float)((law.ntab - 1) / rc2);
-            P.toff = (float)(-P.eps2 * ((law.ntab - 1) / rc2));
+            P.tscale = (float)((law.ntab - 1) / rc2u);
+            P.toff = (float)(-(law.eps * law.eps) * ((law.ntab - 1) / rc2));   // -eps^2 / h, no unit
         } else {
-            P.tscale = (float)((law.ntab - 1) / law.r_cut);
+            P.tscale = (float)((law.ntab - 1) / rcu);
             P.toff = 0.0f;
         }
         P.tmax = (float)(law.ntab - 1);
-        P.tie_rc2 = rc2;
-        P.tie_band = 1e-6 * rc2;
+        P.tie_rc2 = rc2u;
+        P.tie_band = 1e-6 * rc2u;
         for (uint32_t ab = 0; ab < law.D * law.D; ++ab) {
-            P.eps2_ab[ab] = law.eps_ab[ab] * law.eps_ab[ab];
-            P.toff_ab[ab] = law.grid == NGR_GRID_R2 ? (float)(-P.eps2_ab[ab] * ((law.ntab - 1) / rc2)) : 0.0f;
+            const double e2 = law.eps_ab[ab] * law.eps_ab[ab];
+            P.eps2_ab[ab] = e2 * ib2;
+            P.toff_ab[ab] = law.grid == NGR_GRID_R2 ? (float)(-e2 * ((law.ntab - 1) / rc2)) : 0.0f;
         }
-        for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = law.G[j];
+        for (uint32_t j = 0; j < law.D * law.D; ++j) P.G[j] = law.G[j] * ib2;
         P.acc = accv[k];
         P.in_off = t.boff[k];
         P.n = t.boff[k + 1] - t.boff[k];
@@ -1394,13 +1411,13 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         P.value = tables[k].value;
         if (law.kind == NGR_LAW_ACCUMULATOR) {
             P.cored = law.cored;
-            P.inv4pib = 1.0 / (4.0 * M_PI * law.beta);
+            P.inv4pib = 1.0 / (4.0 * M_PI * law.beta * box);   // core scale in box units
         }
         P.track = law.track;
         if (law.corr) {
             P.corr = corr_dev + corr_off[k];
             P.corr_n = law.corr_n;
-            P.corr_scale = (double)law.corr_n / (0.5 * box);
+            P.corr_scale = (double)law.corr_n / 0.5;
         }
         if (law.opening == NGR_OPEN_RELATIVE) {
             const double u = box / 2097152.0;   // one half key unit

@@ -25,7 +25,8 @@ def gpu_solve(ctx, p, group_counts=False, keep_tree=False, group_size=None, trac
     tree or None)."""
     import torch
     t = device_inputs(p)
-    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, periodic=getattr(p, "periodic", True), **t)
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, periodic=getattr(p, "periodic", True),
+                          key_order=getattr(p, "key_order", "morton"), **t)
     ngr.compute_monopoles(ctx, tree, track_counts=track_counts)
     acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
     gs = p.group_size if group_size is None else group_size

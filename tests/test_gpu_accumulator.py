@@ -77,6 +77,36 @@ def test_massless_cored_bodies(ctx):
     parity(ctx, dataclasses.replace(p, mass=m), group_size=32)
 
 
+def test_massless_cored_sink_unsoftened_close_pair(ctx):
+    """A massless cored sink 1e-14 box from a point-like source, eps = 0:
+    the pair has no core and no softening, so its force is Newton's
+    G m f(0) / d^2 (f(0) = 1 for the Newtonian factor), far beyond float32's
+    cube of 1 / (s + r); taken in float64 it stays finite and right."""
+    import torch
+    d = 1e-14
+    X = np.zeros((3, 2), np.uint64)
+    X[:, 0] = np.uint64(1) << np.uint64(62)
+    X[:, 1] = X[:, 0]
+    X[0, 1] += np.uint64(round(d * 2.0 ** 64))
+    ntab, r_s = 512, 0.02
+    r_cut = 4.5 * r_s
+    t = synth.sample_table(lambda r: synth.newtonian_treepm_factor(r, r_s), ntab, r_cut, "r2")
+    lat = torch.from_numpy(X.view(np.int64)).cuda()
+    species = torch.tensor([0, 1], dtype=torch.uint8, device="cuda")
+    mass = torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda")
+    tree = ngr.tree_build(ctx, D=2, box=1.0, lattice=lat, species=species, mass=mass)
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.empty((3, 2), dtype=torch.float64, device="cuda")
+    ngr.tree_force(ctx, tree, G=np.ones((2, 2)), tables=np.broadcast_to(t, (2, 2, ntab)).copy(), grid="r2",
+                   r_cut=r_cut, eps=0.0, theta=0.5, group_size=64, acc=acc,
+                   accumulator={"cored": [0], "beta": 1.0})
+    ngr.tree_free(ctx, tree)
+    a = acc.cpu().numpy()
+    dl = float(np.uint64(round(d * 2.0 ** 64))) * 2.0 ** -64
+    assert np.all(np.isfinite(a))
+    assert abs(a[0, 0] - 1.0 / dl ** 2) <= 1e-5 / dl ** 2 and a[1, 0] == 0.0 and a[2, 0] == 0.0
+
+
 def test_tracking_matters(ctx):
     """Tracked and untracked results differ well beyond the gate (section 3.3)."""
     p = synth.accumulator_problem(20000, 3)

@@ -319,3 +319,28 @@ def full_box_parity(ctx, capsys, p, chunks):
     ok, worst, rms, mx = force_gate(acc, ao, so)
     say(f"  interactions={pp + pn} worst/allowed={worst:.3g} max|da|/rms={mx:.3g}")
     assert ok, f"force gate: worst ratio {worst}"
+
+
+@pytest.mark.parametrize("L", [1e-9, 1e12])
+def test_length_units(ctx, L):
+    """Boxes far from unit size: the walk works in units of the box, so the
+    float32 kernel factor has the same range (exact counts, force gate)."""
+    p = synth.clustered_problem(20000, 3, 41, ntab=512)
+    p.lattice, p.pos = oracle.lattice_of(p), None
+    p.box, p.r_s, p.r_cut, p.eps = L, p.r_s * L, p.r_cut * L, p.eps * L
+    p.name += f"-box{L:g}"
+    full_parity(ctx, p)
+
+
+def test_softening_below_range_is_refused(ctx):
+    import torch
+    p = synth.uniform_4096(1)
+    t = device_inputs(p)
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    kw = dict(G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut, theta=p.theta, acc=acc)
+    assert _status(lambda: ngr.tree_force(ctx, tree, eps=1e-14, **kw)) == ngr.EINVAL
+    assert _status(lambda: ngr.tree_force(ctx, tree, eps=0.0, eps_ab=np.full((2, 2), 1e-14), **kw)) == ngr.EINVAL
+    assert _status(lambda: ngr.tree_force(ctx, tree, eps=1e-12, **kw)) == ngr.OK
+    ngr.tree_free(ctx, tree)

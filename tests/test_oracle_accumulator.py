@@ -135,7 +135,7 @@ def test_tracking_reduces_tree_errors():
 
 def test_direct_sum_brute_force():
     """The direct sum with an accumulator law against a 50-digit brute force
-    written from Eqs. (10) and (14): the core scale of a pair adds the cores
+    written from Eqs. (16) and (14): the core scale of a pair adds the cores
     of whichever of the two species carry one, point-like pairs keep the
     softened Newtonian law, and G is taken as G[sink species, source species]."""
     rng = np.random.default_rng(17)

@@ -569,3 +569,22 @@ def test_near_tie_count(oracle_lib, rel, ties):
     _, slack, cnt, _ = T.force(law)
     assert cnt["pp"] == 2 and cnt["near_ties"] == ties
     assert np.all((slack > 0) == (ties > 0))
+
+
+@pytest.mark.parametrize("L", [1e-9, 1e12])
+def test_length_unit_scaling(oracle_lib, L):
+    """The same lattice in a box of side L, with r_s, r_cut and eps scaled
+    by L and the same masses and tables (f depends on r / r_s): the tree and
+    its lists are unchanged and every acceleration scales as 1 / L^2."""
+    p = synth.clustered_problem(4000, 2, 11, ntab=256)
+    p.lattice, p.pos = oracle_lib.lattice_of(p), None
+    T1 = oracle_lib.Tree.of(p)
+    a1, _, c1, _ = T1.force(oracle_lib.law_of(p))
+    q = synth.clustered_problem(4000, 2, 11, ntab=256)
+    q.lattice, q.pos = p.lattice, None
+    q.box, q.r_s, q.r_cut, q.eps = L, p.r_s * L, p.r_cut * L, p.eps * L
+    TL = oracle_lib.Tree.of(q)
+    aL, _, cL, _ = TL.force(oracle_lib.law_of(q))
+    assert (c1["pp"], c1["pn"]) == (cL["pp"], cL["pn"])
+    rms = np.sqrt(np.mean(np.sum(a1 ** 2, axis=0)))
+    assert np.max(np.abs(aL * L * L - a1)) <= 1e-12 * rms
