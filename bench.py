@@ -557,6 +557,7 @@ def main():
     ap.add_argument("--no-accumulator", action="store_true")
     ap.add_argument("--no-pm", action="store_true")
     ap.add_argument("--no-scaled", action="store_true", help="skip the box with the halo count scaled with n")
+    ap.add_argument("--no-relative", action="store_true", help="skip the relative-criterion leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of 1 GiB (to scale rocprofv3 byte counters), then exit")
     args = ap.parse_args()
@@ -610,16 +611,19 @@ def main():
     # the paper's relative criterion (section 2.2) at its tolerance alpha = 0.005, with the previous
     # accelerations from the theta = 0.5 step (as the stock code does after its first force)
     import torch
-    old = torch.linalg.vector_norm(acc, dim=0).contiguous()
-    rr = run_box(ngr, p, max(2, args.steps // 2), 1, "relative", relative={"alpha": 0.005, "old_acc": old})
-    out["relative_criterion"] = {"workload": "the same box, relative opening criterion alpha 0.005 with the previous "
-                                             "|a| from the theta 0.5 force",
-                                 "ms_per_step": rr["ms_per_step"], "interactions_per_step": rr["inter"],
-                                 "interactions_per_s": rr["inter"] / (rr["ms_per_step"] * 1e-3),
-                                 "walk_ms": rr["ms_walk"], "walk_interactions_per_s": rr["inter"] / (rr["ms_walk"] * 1e-3)}
-    acc_rel = rr["acc"].cpu().numpy() if not (args.no_accuracy or args.no_cpu_baseline) else None
-    rr["ctx"].close()
-    del rr, old
+    acc_rel = None
+    if not args.no_relative:
+        old = torch.linalg.vector_norm(acc, dim=0).contiguous()
+        rr = run_box(ngr, p, max(2, args.steps // 2), 1, "relative", relative={"alpha": 0.005, "old_acc": old})
+        out["relative_criterion"] = {"workload": "the same box, relative opening criterion alpha 0.005 with the "
+                                                 "previous |a| from the theta 0.5 force",
+                                     "ms_per_step": rr["ms_per_step"], "interactions_per_step": rr["inter"],
+                                     "interactions_per_s": rr["inter"] / (rr["ms_per_step"] * 1e-3),
+                                     "walk_ms": rr["ms_walk"],
+                                     "walk_interactions_per_s": rr["inter"] / (rr["ms_walk"] * 1e-3)}
+        acc_rel = rr["acc"].cpu().numpy() if not (args.no_accuracy or args.no_cpu_baseline) else None
+        rr["ctx"].close()
+        del rr, old
     gpu_gc = None
     if not args.no_cpu_baseline:
         # one more step with per-group counts (untimed), for the baseline's count check

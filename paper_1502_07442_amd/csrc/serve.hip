@@ -10,6 +10,7 @@
 // with (section 3).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -20,10 +21,14 @@ namespace {
 
 inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
 
-// One admitted request as the step kernels see it.
+// One admitted request as the step kernels see it: the state is read from
+// X, v and written to Xo, vo (the tick's new state, kept only if its force
+// evaluation succeeds); the closing kick updates vo in place.
 struct StepDev {
-    uint64_t* X;
-    double* v;
+    const uint64_t* X;
+    const double* v;
+    uint64_t* Xo;
+    double* vo;
     const double* a;
     uint64_t n;
     double h;          // dt / 2
@@ -46,8 +51,8 @@ __global__ void kick_drift(const StepDev* __restrict__ req)
         if (i >= R.n) continue;
         for (int c = 0; c < 3; ++c) {
             const uint64_t j = (uint64_t)c * R.n + i;
-            const double v = R.v[j] + R.a[j] * R.h;
-            R.v[j] = v;
+            const double v = (DRIFT ? R.v[j] : R.vo[j]) + R.a[j] * R.h;
+            R.vo[j] = v;
             if (DRIFT) {
                 // displacement in box units, folded into [-1/2, 1/2] (a wrap),
                 // then in lattice units 2^64 per box
@@ -55,7 +60,7 @@ __global__ void kick_drift(const StepDev* __restrict__ req)
                 d -= rint(d);
                 d = fmin(fmax(d, -0.5), 0.5 - 0x1p-53);
                 const int64_t dl = (int64_t)(d * 18446744073709551616.0);
-                R.X[j] += (uint64_t)dl;
+                R.Xo[j] = R.X[j] + (uint64_t)dl;
             }
         }
     }
@@ -102,7 +107,10 @@ struct Server {
     uint32_t max_active = 0;
     uint64_t next_id = 1;
     std::vector<Request*> all;        // every request not yet taken, in submission order
-    uint64_t admitted_bytes = 0;      // resident plus tree estimate of admitted requests
+    uint64_t held_bytes = 0;          // device bytes of every request not yet taken (waiting, admitted, finished)
+    uint64_t tree_bytes = 0;          // tree estimate of the admitted requests (one tick's build)
+    uint64_t ticks = 0;               // ticks that evaluated a force
+    uint64_t fail_tick = 0;           // error-path check: this tick fails after its kick and drift (0: none)
 };
 
 static void release_request(Context& ctx, Request* r)
@@ -126,6 +134,9 @@ Server* server_create(Context& ctx, const ngr_server_params* sp)
     s->ctx = &ctx;
     s->budget = sp && sp->hbm_budget ? sp->hbm_budget : 200000000000ull;
     s->max_active = sp ? sp->max_active : 0;
+    // error-path check of the all-or-nothing tick: NGR_SERVER_FAIL_TICK=k makes
+    // the k-th evaluating tick fail (NGR_ENOMEM) after its kick and drift
+    if (const char* f = std::getenv("NGR_SERVER_FAIL_TICK")) s->fail_tick = std::strtoull(f, nullptr, 10);
     return s;
 }
 
@@ -142,7 +153,16 @@ void server_destroy(Server* s)
     delete s;
 }
 
-static uint64_t footprint(const Request& r) { return r.bytes + r.in.n * kTreeBytesPerParticle; }
+static uint64_t tree_estimate(const Request& r) { return r.in.n * kTreeBytesPerParticle; }
+
+// Device bytes a request holds from submit to take: lattice, velocity and
+// acceleration (3 x n each), species, mass, and its tables in both layouts.
+static uint64_t request_bytes(uint64_t n, uint32_t D, uint32_t ntab)
+{
+    const uint64_t n1 = std::max<uint64_t>(n, 1);
+    return 3 * n1 * (sizeof(uint64_t) + 2 * sizeof(double)) + n1 * (1 + sizeof(double)) +
+           (n ? (uint64_t)D * D * (ntab * 12ull + 4) : 0);
+}
 
 uint64_t server_submit(Server& s, const ngr_request* rq)
 {
@@ -162,6 +182,13 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
         r->steps = rq->steps;
         const uint64_t n = r->in.n;
         const uint32_t D = r->in.D;
+        // the budget covers every request held from submit to take: refuse
+        // before allocating anything when this one would overrun it
+        const uint64_t need = request_bytes(n, D, rq->force.ntab);
+        if (need + n * kTreeBytesPerParticle > s.budget)
+            fail(NGR_ENOMEM, "the request does not fit the server's device memory budget");
+        if (s.held_bytes + s.tree_bytes + need + n * kTreeBytesPerParticle > s.budget)
+            fail(NGR_ENOMEM, "the server's device memory budget is held by other requests (take finished ones)");
         if (rq->force.tables) r->tables.assign(rq->force.tables, rq->force.tables + (size_t)D * D * rq->force.ntab);
         validate_box(ctx, r->in, "");
         make_law(rq->force, D, r->law);
@@ -173,7 +200,7 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
         r->a = static_cast<double*>(ctx.alloc(3 * n1 * sizeof(double)));
         r->species = static_cast<uint8_t*>(ctx.alloc(n1));
         r->mass = static_cast<double*>(ctx.alloc(n1 * sizeof(double)));
-        r->bytes = 3 * n1 * (sizeof(uint64_t) + 2 * sizeof(double)) + n1 * (1 + sizeof(double));
+        r->bytes = need;
         if (n) {
             if (rq->particles.lattice) {
                 HIP_CHECK(hipMemcpyAsync(r->X, rq->particles.lattice, 3 * n * sizeof(uint64_t), hipMemcpyDeviceToDevice,
@@ -192,13 +219,11 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
             HIP_CHECK(hipMemsetAsync(r->a, 0, 3 * n * sizeof(double), ctx.stream));
             std::vector<Law> one(1, r->law);
             r->tab_block = upload_tables(ctx, one, r->tab);
-            r->bytes += (uint64_t)D * D * (r->law.ntab * 12ull + 4);
         }
         r->in.pos = nullptr;
         r->in.lattice = r->X;
         r->in.species = r->species;
         r->in.mass = r->mass;
-        if (footprint(*r) > s.budget) fail(NGR_ENOMEM, "the request does not fit the server's device memory budget");
         ctx.sync();
     } catch (...) {
         try {
@@ -210,6 +235,7 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
     }
     r->id = s.next_id++;
     s.all.push_back(r);
+    s.held_bytes += r->bytes;
     return r->id;
 }
 
@@ -224,9 +250,9 @@ void server_tick(Server& s, ngr_tick_stats* st)
     for (Request* r : s.all) {
         if (r->state != 0) continue;
         if (s.max_active && active >= s.max_active) break;
-        if (s.admitted_bytes + footprint(*r) > s.budget) break;
+        if (s.held_bytes + s.tree_bytes + tree_estimate(*r) > s.budget) break;
         r->state = 1;
-        s.admitted_bytes += footprint(*r);
+        s.tree_bytes += tree_estimate(*r);
         ++active;
         ++out.admitted;
     }
@@ -234,67 +260,122 @@ void server_tick(Server& s, ngr_tick_stats* st)
     for (Request* r : s.all)
         if (r->state == 1) act.push_back(r);
     if (!act.empty()) {
+        ++s.ticks;
         hipEvent_t e0, e1;
         HIP_CHECK(hipEventCreate(&e0));
         HIP_CHECK(hipEventCreate(&e1));
         HIP_CHECK(hipEventRecord(e0, ctx.stream));
-        // kick and drift of the requests past their first evaluation
+        // The tick is all or nothing: kick and drift write each stepping
+        // request's new X and v to fresh buffers, which replace the old ones
+        // only once the force evaluation has succeeded (a failed tick leaves
+        // every request as it was).
         std::vector<StepDev> steps;
+        std::vector<Request*> stepping;
+        std::vector<void*> fresh;
         uint64_t nmax = 0;
-        for (Request* r : act)
-            if (r->evals > 0 && r->in.n) {
-                steps.push_back(StepDev{r->X, r->v, r->a, r->in.n, 0.5 * r->dt, r->dt / r->in.box});
-                nmax = std::max(nmax, r->in.n);
-            }
         StepDev* steps_dev = nullptr;
-        const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(nmax, 256), 64));
-        if (!steps.empty()) {
-            steps_dev = static_cast<StepDev*>(ctx.alloc(steps.size() * sizeof(StepDev)));
-            ctx.to_device(steps_dev, steps.data(), steps.size() * sizeof(StepDev));
-            hipLaunchKernelGGL(kick_drift<true>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream, steps_dev);
-            LAUNCH_CHECK("kick_drift");
+        auto drop_fresh = [&] {
+            for (void* p : fresh) ctx.release(p);
+            fresh.clear();
+            ctx.release(steps_dev);
+            steps_dev = nullptr;
+        };
+        try {
+            for (Request* r : act)
+                if (r->evals > 0 && r->in.n) {
+                    uint64_t* Xo = static_cast<uint64_t*>(ctx.alloc(3 * r->in.n * sizeof(uint64_t)));
+                    fresh.push_back(Xo);
+                    double* vo = static_cast<double*>(ctx.alloc(3 * r->in.n * sizeof(double)));
+                    fresh.push_back(vo);
+                    steps.push_back(StepDev{r->X, r->v, Xo, vo, r->a, r->in.n, 0.5 * r->dt, r->dt / r->in.box});
+                    stepping.push_back(r);
+                    nmax = std::max(nmax, r->in.n);
+                }
+        } catch (...) {
+            drop_fresh();
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
         }
-        // one force evaluation of every admitted request
+        const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(nmax, 256), 64));
+        // one force evaluation of every admitted request, at the drifted positions
         std::vector<BoxIn> in;
         std::vector<uint32_t> gs;
         std::vector<Law> laws;
         std::vector<LawTables> tabs;
         std::vector<double*> acc;
+        std::vector<double*> acc_new;
         for (Request* r : act) {
-            in.push_back(r->in);
+            BoxIn b = r->in;
+            for (size_t k = 0; k < stepping.size(); ++k)
+                if (stepping[k] == r) b.lattice = steps[k].Xo;
+            in.push_back(b);
             gs.push_back(r->gs);
             laws.push_back(r->law);
             tabs.push_back(r->tab.empty() ? LawTables{} : r->tab[0]);
-            acc.push_back(r->a);
             out.particles += r->in.n;
         }
         Tree t;
         Groups g;
         WalkOut wo;
         try {
+            // the new accelerations also go to fresh buffers
+            for (Request* r : act) {
+                double* an = static_cast<double*>(ctx.alloc(3 * std::max<uint64_t>(r->in.n, 1) * sizeof(double)));
+                fresh.push_back(an);
+                acc_new.push_back(an);
+            }
+            if (!steps.empty()) {
+                steps_dev = static_cast<StepDev*>(ctx.alloc(steps.size() * sizeof(StepDev)));
+                ctx.to_device(steps_dev, steps.data(), steps.size() * sizeof(StepDev));
+                hipLaunchKernelGGL(kick_drift<true>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream,
+                                   steps_dev);
+                LAUNCH_CHECK("kick_drift");
+            }
+            if (s.fail_tick && s.ticks == s.fail_tick) fail(NGR_ENOMEM, "tick failed on request (NGR_SERVER_FAIL_TICK)");
             build_forest(ctx, in, t);
             compute_monopoles(ctx, t);
             make_groups(ctx, t, gs, g);
-            walk_force(ctx, t, g, laws, tabs, acc, nullptr, wo);
+            walk_force(ctx, t, g, laws, tabs, acc_new, nullptr, wo);
+            free_tree(ctx, t);
+            g.free(ctx);
+            // closing half kick with the new accelerations
+            if (steps_dev) {
+                for (size_t k = 0; k < steps.size(); ++k)
+                    for (size_t q = 0; q < act.size(); ++q)
+                        if (act[q] == stepping[k]) steps[k].a = acc_new[q];
+                ctx.to_device(steps_dev, steps.data(), steps.size() * sizeof(StepDev));
+                hipLaunchKernelGGL(kick_drift<false>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream,
+                                   steps_dev);
+                LAUNCH_CHECK("kick");
+            }
+            ctx.sync();
         } catch (...) {
             try {
                 free_tree(ctx, t);
                 g.free(ctx);
-                ctx.release(steps_dev);
+                drop_fresh();
             } catch (...) {
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             throw;
         }
-        free_tree(ctx, t);
-        g.free(ctx);
-        // closing half kick
-        if (steps_dev) {
-            hipLaunchKernelGGL(kick_drift<false>, dim3(gx, (unsigned)steps.size()), dim3(256), 0, ctx.stream, steps_dev);
-            LAUNCH_CHECK("kick");
-            ctx.release(steps_dev);
+        // commit: every request takes its new state
+        for (size_t q = 0; q < act.size(); ++q) {
+            Request* r = act[q];
+            ctx.release(r->a);
+            r->a = acc_new[q];
+            for (size_t k = 0; k < stepping.size(); ++k)
+                if (stepping[k] == r) {
+                    ctx.release(r->X);
+                    ctx.release(r->v);
+                    r->X = steps[k].Xo;
+                    r->v = steps[k].vo;
+                    r->in.lattice = r->X;
+                }
         }
+        ctx.release(steps_dev);
         HIP_CHECK(hipEventRecord(e1, ctx.stream));
         ctx.sync();
         float ms = 0.0f;
@@ -308,7 +389,7 @@ void server_tick(Server& s, ngr_tick_stats* st)
             ++r->evals;
             if (r->evals == r->steps + 1) {
                 r->state = 2;
-                s.admitted_bytes -= footprint(*r);
+                s.tree_bytes -= tree_estimate(*r);
                 ++out.finished;
             }
         }
@@ -316,7 +397,7 @@ void server_tick(Server& s, ngr_tick_stats* st)
     for (Request* r : s.all) {
         out.active += r->state == 1 ? 1u : 0u;
         out.pending += r->state == 0 ? 1u : 0u;
-        out.resident_bytes += r->state == 1 ? r->bytes : 0u;
+        out.resident_bytes += r->bytes;
     }
     if (st) *st = out;
 }
@@ -351,6 +432,7 @@ void server_take(Server& s, uint64_t id, uint64_t* lattice, double* vel, double*
     }
     ctx.sync();
     release_request(ctx, r);
+    s.held_bytes -= r->bytes;
     s.all.erase(std::find(s.all.begin(), s.all.end(), r));
     delete r;
 }

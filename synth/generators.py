@@ -32,7 +32,7 @@ __all__ = [
     "clustered_d6_scaled",
     "clustered_problem", "uniform_problem", "batch_box", "serve_request", "poisson_arrivals",
     "accumulator_problem", "yukawa_law", "exact_split_laws", "isolated_problem",
-    "newtonian_lattice_correction", "periodic_tree_problem",
+    "newtonian_lattice_correction", "periodic_tree_problem", "transition_problem",
 ]
 
 GRID_R = "r"     # table samples uniform in r on [0, r_cut]
@@ -492,3 +492,37 @@ def periodic_tree_problem(n: int, D: int, seed: int, *, EN: int = 32, ntab: int 
                    mass=np.full(n, 1.0 / n), G=G, tables=np.ones((D, D, ntab)), grid=GRID_R2, r_s=0.0,
                    r_cut=0.9 * box, eps=box / n ** (1.0 / 3.0) / 40.0, theta=theta, leaf_size=leaf_size,
                    group_size=group_size, pos=pos, seed=seed, lattice_corr=corr)
+
+
+def transition_problem(seed: int, *, shells: int = 20, per_shell: int = 5000, r_min: float = 1e-3,
+                       r_max: float = 0.5, mesh: int = 64, ntab: int = 2048, box: float = 1.0) -> Problem:
+    """The transition test of section 3.1: one massive source at a random
+    place (species 0, mass 1) and `shells` spherical shells of `per_shell`
+    massless test particles (species 1) around it, the shells equal in log r
+    between r_min and r_max (so the density falls as 1 / r^3 and every shell
+    holds the same number), random directions. Only the test particles feel
+    the source (G_10 = 1, every other G_ab = 0: intra-type interactions off);
+    Newtonian short-range tables for a mesh of `mesh` points (r_s = 1.25
+    cells, r_cut = 4.5 r_s), no softening."""
+    rng = np.random.default_rng(seed)
+    src = rng.random(3) * box
+    edges = np.exp(np.linspace(math.log(r_min), math.log(r_max), shells + 1)) * box
+    r = np.concatenate([np.exp(rng.uniform(math.log(edges[k]), math.log(edges[k + 1]), per_shell))
+                        for k in range(shells)])
+    u = rng.normal(size=(r.size, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    pos = np.mod(np.vstack([src[None, :], src[None, :] + r[:, None] * u]), box)
+    pos[pos >= box] = 0.0
+    n = pos.shape[0]
+    species = np.ones(n, np.uint8)
+    species[0] = 0
+    mass = np.zeros(n)
+    mass[0] = 1.0
+    G = np.zeros((2, 2))
+    G[1, 0] = 1.0
+    r_s = 1.25 * box / mesh
+    r_cut = 4.5 * r_s
+    t = sample_table(lambda x: newtonian_treepm_factor(x, r_s), ntab, r_cut, GRID_R2)
+    return Problem(name=f"transition-seed{seed}", n=n, D=2, box=box, species=species, mass=mass, G=G,
+                   tables=np.broadcast_to(t, (2, 2, ntab)).copy(), grid=GRID_R2, r_s=r_s, r_cut=r_cut, eps=0.0,
+                   theta=0.5, pos=np.ascontiguousarray(pos.T), seed=seed)

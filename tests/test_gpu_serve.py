@@ -170,3 +170,87 @@ def test_budget_and_errors(ctx):
     assert st["evaluated"] == 0 and st["active"] == 0 and st["pending"] == 0
     srv.close()
     assert torch.cuda.is_available()
+
+
+def request_bytes(p):
+    """The device bytes a request holds from submit to take (its own copies:
+    lattice, velocity, acceleration, species, mass, tables in two layouts)."""
+    n = max(p.n, 1)
+    return 3 * n * (8 + 16) + n * 9 + p.D * p.D * (p.ntab * 12 + 4)
+
+
+def test_budget_covers_every_held_request(ctx):
+    """Held requests (waiting, admitted, finished and not taken) count
+    against the budget from submit (their data) and admitted ones also with
+    one tick's tree estimate: a submit that would overrun it is refused
+    before anything is allocated; resident_bytes reports every held byte,
+    finished requests included until taken."""
+    probs = [synth.uniform_problem(3000, 2, 40 + k, grid=R2) for k in range(3)]
+    data = [request_bytes(p) for p in probs]
+    per = [request_bytes(p) + p.n * 400 for p in probs]
+    srv = ngr.Server(ctx, hbm_budget=per[0] + per[1] + 1000)
+    a = submit(srv, probs[0], 1)
+    b = submit(srv, probs[1], 1)
+    st = srv.tick()                        # both admitted: data and trees fill the budget
+    assert st["admitted"] == 2 and st["resident_bytes"] == data[0] + data[1]
+    with pytest.raises(ngr.NgravsError) as e:
+        submit(srv, probs[2], 1)
+    assert e.value.status == ngr.ENOMEM
+    st = srv.tick()                        # both finish; their data stay held until taken
+    assert st["finished"] == 2 and st["resident_bytes"] == data[0] + data[1]
+    c = submit(srv, probs[2], 1)           # fits beside the finished requests' data
+    st = srv.tick()
+    assert st["admitted"] == 1 and st["resident_bytes"] == data[0] + data[1] + data[2]
+    take(srv, a, probs[0].n)
+    take(srv, b, probs[1].n)
+    st = srv.tick()
+    assert st["resident_bytes"] == data[2] and srv.status(c)[0] == ngr.FINISHED
+    take(srv, c, probs[2].n)
+    srv.close()
+
+
+def test_failed_tick_changes_nothing(ctx, monkeypatch):
+    """A tick whose force evaluation fails (forced from the host after its
+    kick and drift) leaves every request as it was: the run then ends bitwise
+    where an undisturbed run ends."""
+    probs = [synth.clustered_problem(4096, 3, 51, ntab=512), synth.uniform_problem(2000, 2, 52, grid=R2)]
+    steps = [4, 3]
+    clean = run(ctx, probs, steps)
+    monkeypatch.setenv("NGR_SERVER_FAIL_TICK", "3")
+    srv = ngr.Server(ctx)
+    monkeypatch.delenv("NGR_SERVER_FAIL_TICK")
+    ids = [submit(srv, p, s) for p, s in zip(probs, steps)]
+    failed = 0
+    for _ in range(20):
+        before = [srv.status(r) for r in ids]
+        try:
+            srv.tick()
+        except ngr.NgravsError as e:
+            assert e.status == ngr.ENOMEM
+            assert [srv.status(r) for r in ids] == before
+            failed += 1
+        if all(srv.status(r)[0] == ngr.FINISHED for r in ids):
+            break
+    assert failed == 1
+    for j, r in enumerate(ids):
+        for x, y in zip(take(srv, r, probs[j].n), clean[j]):
+            assert np.array_equal(x, y)
+    srv.close()
+
+
+def test_sixteen_requests_alone_and_mixed(ctx):
+    """Sixteen requests of the served workload's recipe (small sizes), staggered
+    through one server: each ends bitwise as it does alone."""
+    probs, steps = [], []
+    for r in range(16):
+        rng = np.random.default_rng(9000 + r)
+        n = int(round(2.0 ** rng.uniform(10, 14)))
+        D = int(rng.integers(1, 7))
+        probs.append(synth.clustered_problem(n, D, 9000 + r, f_cl=float(rng.uniform(0, 0.8)), ntab=512))
+        steps.append(int(rng.integers(0, 6)))
+    print("case 16 requests, staggered", flush=True)
+    mix = run(ctx, probs, steps, every=1)
+    for j, p in enumerate(probs):
+        alone = run(ctx, [p], [steps[j]])[0]
+        for a, b in zip(alone, mix[j]):
+            assert np.array_equal(a, b), (p.name, j)
