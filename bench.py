@@ -34,7 +34,7 @@ def walk_traffic():
     None when the walk kernel's source has changed since the counters were
     taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "walk_clustered_2p24_D6_counters.md")
+    path = os.path.join(ROOT, "profiles", "walk_clustered_2p24_D6_H2000_counters.md")
     if not os.path.exists(path):
         return None
     fields = {}
