@@ -181,18 +181,31 @@ __global__ void gather_keys(uint64_t n, const uint32_t* __restrict__ perm, const
     if (i < n) kout[i] = kin[perm[i]];
 }
 
-// The single reordering of the particle data into sorted order.
+// The single reordering of the particle data into sorted order: the
+// lattice coordinates and masses, and the walk's split records.
 __global__ void gather_particles(uint64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ Xin,
                                  const double* __restrict__ min, uint64_t* __restrict__ Xout,
-                                 double* __restrict__ mout)
+                                 double* __restrict__ mout, PRec* __restrict__ Pout)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t p = perm[i];
-    Xout[i] = Xin[p];
-    Xout[n + i] = Xin[n + p];
-    Xout[2 * n + i] = Xin[2 * n + p];
-    mout[i] = min[p];
+    const uint64_t x = Xin[p], y = Xin[n + p], z = Xin[2 * n + p];
+    const double m = min[p];
+    Xout[i] = x;
+    Xout[n + i] = y;
+    Xout[2 * n + i] = z;
+    mout[i] = m;
+    PRec r;
+    r.hx = (double)(x & ~kLowBits) * 0x1p-64;
+    r.hy = (double)(y & ~kLowBits) * 0x1p-64;
+    r.hz = (double)(z & ~kLowBits) * 0x1p-64;
+    r.m = m;
+    r.lx = (float)(uint32_t)(x & kLowBits) * 0x1p-64f;
+    r.ly = (float)(uint32_t)(y & kLowBits) * 0x1p-64f;
+    r.lz = (float)(uint32_t)(z & kLowBits) * 0x1p-64f;
+    r.pad = 0.0f;
+    Pout[i] = r;
 }
 
 // The roots: node k is box k's root, holding its species segments.
@@ -432,12 +445,13 @@ void validate_box(Context& ctx, const BoxIn& b, const std::string& where)
 
 void free_tree(Context& ctx, Tree& t)
 {
-    for (void* q : {(void*)t.X, (void*)t.mass, (void*)t.perm, (void*)t.keys, (void*)t.level, (void*)t.prefix,
+    for (void* q : {(void*)t.X, (void*)t.mass, (void*)t.P, (void*)t.perm, (void*)t.keys, (void*)t.level, (void*)t.prefix,
                     (void*)t.parent, (void*)t.first_child, (void*)t.n_child, (void*)t.cell, (void*)t.start,
                     (void*)t.count, (void*)t.node_box, (void*)t.mono, (void*)t.boff_dev})
         ctx.release(q);
     t.X = nullptr;
     t.mass = nullptr;
+    t.P = nullptr;
     t.perm = nullptr;
     t.keys = nullptr;
     t.level = nullptr;
@@ -492,6 +506,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
     const uint64_t n1 = std::max<uint64_t>(n, 1);
     t.X = static_cast<uint64_t*>(ctx.alloc(3 * n1 * sizeof(uint64_t)));
     t.mass = static_cast<double*>(ctx.alloc(n1 * sizeof(double)));
+    t.P = static_cast<PRec*>(ctx.alloc(n1 * sizeof(PRec)));
     t.perm = static_cast<uint32_t*>(ctx.alloc(n1 * sizeof(uint32_t)));
     t.keys = static_cast<uint64_t*>(ctx.alloc(n1 * sizeof(uint64_t)));
     t.boff_dev = static_cast<uint64_t*>(ctx.alloc((nbox + 1) * sizeof(uint64_t)));
@@ -573,7 +588,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
             ctx.release(keys0);
         }
         hipLaunchKernelGGL(gather_particles, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, Xin, mass_cat,
-                           t.X, t.mass);
+                           t.X, t.mass, t.P);
         LAUNCH_CHECK("gather_particles");
         ctx.release(ktmp);
         ctx.release(vtmp);

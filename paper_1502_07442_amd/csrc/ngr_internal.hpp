@@ -108,6 +108,18 @@ struct BoxIn {
 // over all boxes (level by level, box after box within a level); the roots
 // are nodes 0 .. nbox-1. Per-node arrays of species use the largest D of the
 // boxes as stride (species a box does not have are empty).
+// A particle as the walk reads it for its leaf records: the position as a
+// fraction of the box, split into a high part (the lattice coordinate with
+// its low 11 bits cleared, exact in float64) and a low part (those 11 bits,
+// exact in float32), and the mass. The high part minus a group centre is
+// exact, so adding the low part rounds once, exactly as converting the
+// integer lattice difference would.
+struct alignas(16) PRec {
+    double hx, hy, hz, m;
+    float lx, ly, lz, pad;
+};
+constexpr uint64_t kLowBits = 0x7ffull;
+
 struct Tree {
     uint64_t n = 0;                // particles of all boxes
     uint32_t D = 0;                // species stride: the largest D of the boxes
@@ -127,6 +139,7 @@ struct Tree {
     // particles in sorted order (box, species, Morton key)
     uint64_t* X = nullptr;         // 3 x n lattice coordinates
     double* mass = nullptr;        // n
+    PRec* P = nullptr;             // n, the same particles split for the walk's leaf records
     uint32_t* perm = nullptr;      // n, sorted position -> input index (over all boxes)
     uint64_t* keys = nullptr;      // n sorted keys (species << 60 | Morton), per box
     // nodes, breadth first; capacity cap

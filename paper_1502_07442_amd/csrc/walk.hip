@@ -286,6 +286,7 @@ struct WalkArgs {
     const double4* mono;
     uint64_t nn;
     const uint64_t* X;
+    const PRec* P;
     const double* mass;
     const uint32_t* perm;
     uint64_t n;
@@ -320,15 +321,24 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ inline uint32_t wave_incl(uint32_t v, int lane)
+// Inclusive scans (sum or maximum) over the 64 lanes of a wave, all lanes
+// active: DPP row shifts by 1, 2, 4 and 8 within each row of 16 lanes
+// (lanes shifted in from outside the row read 0), then the last lane of
+// rows 0 and 2 added into rows 1 and 3, and lane 31 into rows 2 and 3.
+template <bool MAX>
+__device__ inline uint32_t wave_scan(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
+    auto join = [&](int u) { v = MAX ? max(v, (uint32_t)u) : v + (uint32_t)u; };
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));    // row_shr:1
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));    // row_shr:2
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));    // row_shr:4
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));    // row_shr:8
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31 into rows 2, 3
     return v;
 }
+__device__ inline uint32_t wave_incl(uint32_t v) { return wave_scan<false>(v); }
+__device__ inline uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -531,6 +541,7 @@ constexpr int kSegCounts = 3 + NGR_MAX_SPECIES;
 template <int GRID, int TAB, bool EPS0, bool ONE, bool ACC, bool EW = false, bool TIES = false>
 __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
 {
+    constexpr int kBlocks = ACC || EW ? 1 : 3;   // sink blocks a lane can serve
     HIP_DYNAMIC_SHARED(unsigned char, smem);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const uint32_t D = A.D;                // species stride of the node arrays
@@ -623,23 +634,33 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         // A group of at most 32 (16) sinks runs K = 2 (4) copies of itself,
         // one per 32 (16) lanes; copy q takes records q, q + K, q + 2K, ...
         // and the copies' sums are added at the end. Far away massless pads
-        // after the last record give the copies equal trip counts. Groups
-        // that need the periodic wrap run one copy.
-        const uint32_t lk = wrap ? 0u : ns <= 16u ? 2u : ns <= 32u ? 1u : 0u;
+        // after the last record give the copies equal trip counts. A group of
+        // 33 to 48 sinks (table laws, no wrap) runs as three blocks of 16
+        // sinks in K = 4 copies: lane l serves the sinks l mod 16 + 16 m,
+        // m = 0, 1, 2, each over every fourth record, which costs three
+        // quarters of one pass with a sink per lane. Groups that need the
+        // periodic wrap run one copy.
+        const bool blocks = !ACC && !wrap && ns > 32u && ns <= 48u;
+        const uint32_t nblk = blocks ? 3u : 1u;
+        const uint32_t lk = wrap ? 0u : (ns <= 16u || blocks) ? 2u : ns <= 32u ? 1u : 0u;
         const uint32_t K = 1u << lk;
         const uint32_t sink = (uint32_t)lane & ((64u >> lk) - 1u), replica = (uint32_t)lane >> (6u - lk);
         const double4* const rrec = rec + replica;
         // a million boxes away: past every cut-off (the table factor is 0), yet
         // r^2 stays finite in float32 for boxes below ~1e13
         const double4 pad = make_double4(1e6 * bx, 1e6 * bx, 1e6 * bx, 0.0);
-        double ox = 0.0, oy = 0.0, oz = 0.0;
-        if (sink < ns) {
-            uint64_t i = s0 + sink;
-            ox = (double)(int64_t)(A.X[i] - C0) * scale;
-            oy = (double)(int64_t)(A.X[n + i] - C1) * scale;
-            oz = (double)(int64_t)(A.X[2 * n + i] - C2) * scale;
+        double ox[kBlocks], oy[kBlocks], oz[kBlocks], ax[kBlocks], ay[kBlocks], az[kBlocks];
+#pragma unroll
+        for (int m = 0; m < kBlocks; ++m) {
+            ox[m] = oy[m] = oz[m] = ax[m] = ay[m] = az[m] = 0.0;
+            const uint32_t sm = sink + 16u * (uint32_t)m;
+            if ((uint32_t)m < nblk && sm < ns) {
+                const uint64_t i = s0 + sm;
+                ox[m] = (double)(int64_t)(A.X[i] - C0) * scale;
+                oy[m] = (double)(int64_t)(A.X[n + i] - C1) * scale;
+                oz[m] = (double)(int64_t)(A.X[2 * n + i] - C2) * scale;
+            }
         }
-        double ax = 0.0, ay = 0.0, az = 0.0;
         unsigned long long pn_src = 0, pp_src = 0, n_acc = 0, n_leaf = 0;
         const TieBand tband{tie_rc2, tie_band};
         if ((uint32_t)lane < (uint32_t)NGR_MAX_SPECIES) gpn[lane] = 0u;
@@ -649,7 +670,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         double a_min = 0.0;
         if (rel) {
             double am = __builtin_inf();
-            if (sink < ns) am = P.old_acc[A.perm[s0 + sink] - in_off];
+            if ((uint32_t)lane < ns) am = P.old_acc[A.perm[s0 + lane] - in_off];
 #pragma unroll
             for (int d = 32; d > 0; d >>= 1) am = fmin(am, __shfl_xor(am, d, 64));
             a_min = am;
@@ -668,24 +689,36 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             const float to = P.toff_ab[a * Dk + b];
             if (cored_pair(b)) {
                 const double* rrs = recs + replica;
-                if (wrap) eval_cored<GRID, TAB, true, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
-                else eval_cored<GRID, TAB, false, 4>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, ox, oy, oz, ax, ay, az);
+                double &x = ox[0], &y = oy[0], &z = oz[0], &gx = ax[0], &gy = ay[0], &gz = az[0];
+                if (wrap) eval_cored<GRID, TAB, true, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, x, y, z, gx, gy, gz);
+                else if (lk == 0u) eval_cored<GRID, TAB, false, 1>(pp, e2, rec, recs, nrec, tb, core_tab, s_sink, x, y, z, gx, gy, gz);
+                else if (lk == 1u) eval_cored<GRID, TAB, false, 2>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, x, y, z, gx, gy, gz);
+                else eval_cored<GRID, TAB, false, 4>(pp, e2, rrec, rrs, iters, tb, core_tab, s_sink, x, y, z, gx, gy, gz);
                 return;
             }
             if (EW && P.corr) {
                 const uint64_t m = P.corr_n + 1u;
                 const LatticeCorr lc{P.corr + (uint64_t)(a * Dk + b) * m * m * m * 3u, P.corr_n, P.corr_scale};
-                eval_records<GRID, TAB, EPS0, true, 1, true>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, lc);
+                eval_records<GRID, TAB, EPS0, true, 1, true>(pp, e2, to, rec, nrec, tb, ox[0], oy[0], oz[0], ax[0], ay[0],
+                                                             az[0], lc);
                 return;
             }
             const LatticeCorr nolc{nullptr, 0u, 0.0};
+            if (blocks) {
+#pragma unroll
+                for (int m = 0; m < kBlocks; ++m) {
+                    const uint32_t t = eval_records<GRID, TAB, EPS0, false, 4, false, TIES>(
+                        pp, e2, to, rrec, iters, tb, ox[m], oy[m], oz[m], ax[m], ay[m], az[m], nolc, tband);
+                    if (TIES && sink + 16u * (uint32_t)m < ns) nties += t;
+                }
+                return;
+            }
+            double &x = ox[0], &y = oy[0], &z = oz[0], &gx = ax[0], &gy = ay[0], &gz = az[0];
             uint32_t t;
-            if (wrap) t = eval_records<GRID, TAB, EPS0, true, 1, false, TIES>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, nolc, tband);
-            else if (lk == 0u) t = eval_records<GRID, TAB, EPS0, false, 1, false, TIES>(pp, e2, to, rec, nrec, tb, ox, oy, oz, ax, ay, az, nolc, tband);
-            else if (lk == 1u) t = eval_records<GRID, TAB, EPS0, false, 2, false, TIES>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az, nolc, tband);
-            else t = eval_records<GRID, TAB, EPS0, false, 4, false, TIES>(pp, e2, to, rrec, iters, tb, ox, oy, oz, ax, ay, az, nolc, tband);
+            if (wrap) t = eval_records<GRID, TAB, EPS0, true, 1, false, TIES>(pp, e2, to, rec, nrec, tb, x, y, z, gx, gy, gz, nolc, tband);
+            else if (lk == 0u) t = eval_records<GRID, TAB, EPS0, false, 1, false, TIES>(pp, e2, to, rec, nrec, tb, x, y, z, gx, gy, gz, nolc, tband);
+            else if (lk == 1u) t = eval_records<GRID, TAB, EPS0, false, 2, false, TIES>(pp, e2, to, rrec, iters, tb, x, y, z, gx, gy, gz, nolc, tband);
+            else t = eval_records<GRID, TAB, EPS0, false, 4, false, TIES>(pp, e2, to, rrec, iters, tb, x, y, z, gx, gy, gz, nolc, tband);
             if (TIES && sink < ns) nties += t;
         };
 
@@ -751,8 +784,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             };
             // species b's running counts into LDS; its particle total
             auto prep = [&](uint32_t b) -> uint32_t {
-                const uint32_t incl = wave_incl(pick(cnt, b), lane);
-                const uint32_t T = uniform(__shfl(incl, 63, 64));
+                const uint32_t incl = wave_incl(pick(cnt, b));
+                const uint32_t T = lane63(incl);
                 if (T) {
                     scanb[lane + 1] = incl;
                     scanb[0] = 0;              // every lane stores the same value
@@ -761,27 +794,25 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 }
                 return T;
             };
-            uint64_t sx = 0, sy = 0, sz = 0;
-            double sm = 0.0;
+            PRec pr{};
             bool sv = false;
-            // loads of record base + lane of the current species
+            // Loads of record base + lane of the current species. Leaf q holds
+            // the records scanb[q] .. scanb[q + 1] - 1. In the window of 64
+            // records from base, each leaf marks the position of its first
+            // record there (position 0 for the leaf holding base); the running
+            // maximum of the marks is each record's leaf. The second half of
+            // the node buffer is free while leaves are flushed (fewer than 64
+            // nodes are pending), and holds the marks.
+            uint32_t* const mark = pnb + 64;
             auto stage = [&](uint32_t base, uint32_t T) {
+                const uint32_t e = scanb[lane], f = scanb[lane + 1];
+                mark[lane] = 0u;
+                if ((uint32_t)lane < k && e < f && f > base && e < base + 64u) mark[max(e, base) - base] = (uint32_t)lane;
+                wave_sync();
+                const uint32_t q = wave_scan<true>(mark[lane]);
                 const uint32_t r = base + lane;
                 sv = r < T;
-                if (sv) {
-                    // leaf q with scanb[q] <= r < scanb[q+1]
-                    uint32_t lo2 = 0, hi2 = k;
-                    while (hi2 - lo2 > 1) {
-                        uint32_t mid = (lo2 + hi2) >> 1;
-                        if (scanb[mid] <= r) lo2 = mid;
-                        else hi2 = mid;
-                    }
-                    const uint64_t j = pst[lo2] + (r - scanb[lo2]);
-                    sx = A.X[j];
-                    sy = A.X[n + j];
-                    sz = A.X[2 * n + j];
-                    sm = A.mass[j];
-                }
+                if (sv) pr = A.P[pst[q] + (r - scanb[q])];
             };
             uint32_t b = 0, T = 0;
             for (; b < Dk; ++b) {
@@ -795,9 +826,14 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                 const uint32_t nrec = min(64u, T - base);
                 const bool cp = cored_pair(b);
                 if (sv) {
-                    rec[lane] = make_double4((double)(int64_t)(sx - C0) * scale, (double)(int64_t)(sy - C1) * scale,
-                                             (double)(int64_t)(sz - C2) * scale, Ga[b] * sm);
-                    if (cp) recs[lane] = ((cmask >> b) & 1u) ? sm * inv4pib : 0.0;
+                    // offsets from the group centre in box units (the box is 1):
+                    // the high part's difference is exact, the low part rounds it once
+                    double ex = pr.hx - cf0, ey = pr.hy - cf1, ez = pr.hz - cf2;
+                    ex -= rint(ex);
+                    ey -= rint(ey);
+                    ez -= rint(ez);
+                    rec[lane] = make_double4(ex + (double)pr.lx, ey + (double)pr.ly, ez + (double)pr.lz, Ga[b] * pr.m);
+                    if (cp) recs[lane] = ((cmask >> b) & 1u) ? pr.m * inv4pib : 0.0;
                 }
                 if (K > 1u && (uint32_t)lane < 3u) {
                     rec[nrec + lane] = pad;
@@ -890,8 +926,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             n_acc += (uint32_t)__popcll(macc);
             n_leaf += (uint32_t)__popcll(mleaf);
             const uint32_t myc = (dec == kOpen) ? nc : 0u;
-            const uint32_t incl = wave_incl(myc, lane);
-            const uint32_t tot = uniform(__shfl(incl, 63, 64));
+            const uint32_t incl = wave_incl(myc);
+            const uint32_t tot = lane63(incl);
             if (sp + tot > A.stack_cap) {
                 overflow = true;
                 break;
@@ -923,22 +959,39 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
             if (npn) flush_nodes(npn);
             if (npp) flush_leaves(npp);
         }
-        // fold the copies' sums into lanes 0 .. 64/K - 1 (fixed order)
-        if (K == 4u) {
-            ax += __shfl_xor(ax, 16, 64);
-            ay += __shfl_xor(ay, 16, 64);
-            az += __shfl_xor(az, 16, 64);
+        // fold the copies' sums (fixed order); every copy then holds the
+        // total, so lane l = c + 16 q of a blocked group keeps block q's sink
+        // c + 16 q, i.e. sink l, like the other modes
+#pragma unroll
+        for (int m = 0; m < kBlocks; ++m) {
+            if ((uint32_t)m >= nblk) break;
+            if (K == 4u) {
+                ax[m] += __shfl_xor(ax[m], 16, 64);
+                ay[m] += __shfl_xor(ay[m], 16, 64);
+                az[m] += __shfl_xor(az[m], 16, 64);
+            }
+            if (K >= 2u) {
+                ax[m] += __shfl_xor(ax[m], 32, 64);
+                ay[m] += __shfl_xor(ay[m], 32, 64);
+                az[m] += __shfl_xor(az[m], 32, 64);
+            }
         }
-        if (K >= 2u) {
-            ax += __shfl_xor(ax, 32, 64);
-            ay += __shfl_xor(ay, 32, 64);
-            az += __shfl_xor(az, 32, 64);
+        double fx = ax[0], fy = ay[0], fz = az[0];
+        if (kBlocks > 1 && blocks) {
+            const uint32_t q = (uint32_t)lane >> 4;
+#pragma unroll
+            for (int m = 1; m < kBlocks; ++m)
+                if (q == (uint32_t)m) {
+                    fx = ax[m];
+                    fy = ay[m];
+                    fz = az[m];
+                }
         }
         if ((uint32_t)lane < ns) {
             const uint64_t p = A.perm[s0 + lane] - in_off;
-            acc[p] = ax;
-            acc[nbx + p] = ay;
-            acc[2 * nbx + p] = az;
+            acc[p] = fx;
+            acc[nbx + p] = fy;
+            acc[2 * nbx + p] = fz;
         }
         const unsigned long long pn = pn_src * ns, pp = pp_src * ns - ns;
         unsigned long long gties = 0;
@@ -1477,6 +1530,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     A.nn = t.nn;
     A.X = t.X;
     A.mass = t.mass;
+    A.P = t.P;
     A.perm = t.perm;
     A.n = t.n;
     A.gstart = g.start;

@@ -114,6 +114,20 @@ def test_group_sizes(ctx, Ng):
     full_parity(ctx, synth.clustered_problem(9000, 3, 7, ntab=512), group_size=Ng)
 
 
+def test_every_lane_mapping(ctx):
+    """Groups of 64 sinks run with one sink per lane (49 to 64 sinks), as
+    three blocks of 16 sinks over a quarter of the records each (33 to 48),
+    and as two or four copies (17 to 32, at most 16). A clustered box holds
+    all four kinds; every stage equals the oracle, near ties included."""
+    p = synth.clustered_problem(30000, 3, 12, ntab=512)
+    T = oracle.Tree.of(p)
+    ns = T.group_arrays()["count"]
+    kinds = [int(np.count_nonzero((ns > lo) & (ns <= hi))) for lo, hi in ((0, 16), (16, 32), (32, 48), (48, 64))]
+    print(f"groups by lane mapping (<=16, 17-32, 33-48, 49-64): {kinds}")
+    assert min(kinds) > 0
+    full_parity(ctx, p)
+
+
 def test_zero_softening(ctx):
     p = synth.uniform_problem(3001, 2, 8, ntab=512)
     p.eps = 0.0
