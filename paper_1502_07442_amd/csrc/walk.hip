@@ -635,7 +635,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         // one per 32 (16) lanes; copy q takes records q, q + K, q + 2K, ...
         // and the copies' sums are added at the end. Far away massless pads
         // after the last record give the copies equal trip counts. A group of
-        // 33 to 48 sinks (table laws, no wrap) runs as three blocks of 16
+        // 33 to 48 sinks (table laws: a launch holds one law kind, and no
+        // wrap) runs as three blocks of 16
         // sinks in K = 4 copies: lane l serves the sinks l mod 16 + 16 m,
         // m = 0, 1, 2, each over every fourth record, which costs three
         // quarters of one pass with a sink per lane. Groups that need the
@@ -1337,22 +1338,20 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
     return oval;
 }
 
-void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
-                const std::vector<LawTables>& tables, const std::vector<double*>& accv, uint64_t* group_counts_dev,
-                WalkOut& out, bool count_ties)
+// One launch over the boxes with part[k] set; adds their counts and times to
+// out (the other boxes' segments are marked done before the launch).
+static void walk_launch(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
+                        const std::vector<LawTables>& tables, const std::vector<double*>& accv,
+                        uint64_t* group_counts_dev, WalkOut& out, bool count_ties, const std::vector<char>& part)
 {
-    out = WalkOut{};
     const uint32_t nbox = t.nbox, D = t.D;
-    out.box_pp.assign(nbox, 0);
-    out.box_pn.assign(nbox, 0);
-    out.box_pnb.assign((size_t)nbox * NGR_MAX_SPECIES, 0);
-    if (t.n == 0 || g.ng == 0) {
-        if (count_ties) out.ties = 0;
-        return;
-    }
+    bool any = false;
+    for (uint32_t q = 0; q < g.nseg; ++q) any |= part[q / D] && g.first[q + 1] > g.first[q];
+    if (!any) return;
     const uint32_t grid = laws[0].grid;
     bool eps0 = false, acc_law = false, ew = false;
     for (uint32_t k = 0; k < nbox; ++k) {
+        if (!part[k]) continue;
         acc_law |= laws[k].kind == NGR_LAW_ACCUMULATOR;
         ew |= laws[k].corr != nullptr;
     }
@@ -1388,6 +1387,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     uint32_t pair_max = 0, value_max = 0;
     for (uint32_t k = 0; k < nbox; ++k) {
         if (laws[k].grid != grid) fail(NGR_EINVAL, "the boxes of one call must share the table grid");
+        if (!part[k]) continue;
         for (uint32_t ab = 0; ab < laws[k].D * laws[k].D; ++ab) eps0 |= laws[k].eps_ab[ab] == 0.0;
         pair_max = std::max(pair_max, table_bytes(kPair, laws[k].D, laws[k].ntab));
         value_max = std::max(value_max, table_bytes(kValue, laws[k].D, laws[k].ntab));
@@ -1486,7 +1486,7 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     const uint32_t nseg = g.nseg;
     std::vector<uint32_t> sched;
     for (uint32_t q = 0; q < nseg; ++q)
-        if (g.first[q + 1] > g.first[q]) sched.push_back(q);
+        if (part[q / D] && g.first[q + 1] > g.first[q]) sched.push_back(q);
     std::stable_sort(sched.begin(), sched.end(), [&](uint32_t x, uint32_t y) {
         return g.first[x + 1] - g.first[x] > g.first[y + 1] - g.first[y];
     });
@@ -1504,6 +1504,8 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
     {
         std::vector<uint32_t> host((size_t)nseg + 2 + (nseg + 1) + nsched, 0);
         host[nseg] = std::min<uint32_t>((uint32_t)blocks, nsched);   // cursor: entries the first workgroups take
+        for (uint32_t q = 0; q < nseg; ++q)   // another launch's segments start with their queue spent
+            if (!part[q / D]) host[q] = g.first[q + 1] - g.first[q];
         for (uint32_t q = 0; q <= nseg; ++q) host[(size_t)nseg + 2 + q] = (uint32_t)g.first[q];
         for (uint32_t q = 0; q < nsched; ++q) host[(size_t)nseg + 2 + nseg + 1 + q] = sched[q];
         HIP_CHECK(hipMemsetAsync(seg_counts, 0, cnt_bytes, ctx.stream));
@@ -1638,14 +1640,41 @@ void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<
         nties += c[2];
         for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) out.box_pnb[(size_t)(q / D) * NGR_MAX_SPECIES + b] += c[3 + b];
     }
+    if (ties) out.ties = nties;
+    out.ms_walk += ms;
+    out.ms_order += ms_order;
+}
+
+void walk_force(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
+                const std::vector<LawTables>& tables, const std::vector<double*>& accv, uint64_t* group_counts_dev,
+                WalkOut& out, bool count_ties)
+{
+    out = WalkOut{};
+    const uint32_t nbox = t.nbox;
+    out.box_pp.assign(nbox, 0);
+    out.box_pn.assign(nbox, 0);
+    out.box_pnb.assign((size_t)nbox * NGR_MAX_SPECIES, 0);
+    if (t.n == 0 || g.ng == 0) {
+        if (count_ties) out.ties = 0;
+        return;
+    }
+    // A launch holds one law kind. A batch that mixes accumulator and table
+    // laws walks each kind in a launch of its own, so every box runs the
+    // kernel, and so the lane mapping, of its single-box call.
+    bool acc = false, table = false;
+    for (uint32_t k = 0; k < nbox; ++k) (laws[k].kind == NGR_LAW_ACCUMULATOR ? acc : table) = true;
+    std::vector<char> part(nbox, 1);
+    if (acc && table) {
+        for (uint32_t k = 0; k < nbox; ++k) part[k] = laws[k].kind == NGR_LAW_ACCUMULATOR;
+        walk_launch(ctx, t, g, laws, tables, accv, group_counts_dev, out, count_ties, part);
+        for (uint32_t k = 0; k < nbox; ++k) part[k] = !part[k];
+    }
+    walk_launch(ctx, t, g, laws, tables, accv, group_counts_dev, out, count_ties, part);
     for (uint32_t k = 0; k < nbox; ++k) {
         out.pp += out.box_pp[k];
         out.pn += out.box_pn[k];
         for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b) out.pnb[b] += out.box_pnb[(size_t)k * NGR_MAX_SPECIES + b];
     }
-    if (ties) out.ties = nties;
-    out.ms_walk = ms;
-    out.ms_order = ms_order;
 }
 
 }  // namespace ngr

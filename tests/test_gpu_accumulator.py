@@ -117,25 +117,30 @@ def test_tracking_matters(ctx):
 
 
 def test_batch_mixed_law_kinds(ctx):
-    """A table-law box and accumulator boxes in one call: each bitwise equal
-    to its single-box call, counts equal to the oracle's."""
+    """Table-law boxes and accumulator boxes in one call: each bitwise equal
+    to its single-box call, counts equal to the oracle's. The call walks each
+    law kind in a launch of its own; the second table-law box has groups of
+    33 to 48 sinks, which the table-law walk runs as blocks of 16 sinks."""
     import torch
-    probs = [synth.clustered_problem(6000, 2, 31, grid=synth.GRID_R2, ntab=512),
-             synth.accumulator_problem(9000, 32, ntab=512),
-             synth.accumulator_problem(5000, 33, D=3, cored=(0, 2), ntab=512)]
+    probs = [(synth.clustered_problem(6000, 2, 31, grid=synth.GRID_R2, ntab=512), 32),
+             (synth.accumulator_problem(9000, 32, ntab=512), 32),
+             (synth.accumulator_problem(5000, 33, D=3, cored=(0, 2), ntab=512), 32),
+             (synth.clustered_problem(30000, 3, 12, grid=synth.GRID_R2, ntab=512), 64)]
+    ns = oracle.Tree.of(probs[3][0], group_size=64).group_arrays()["count"]
+    assert np.count_nonzero((ns > 32) & (ns <= 48)) > 0
     boxes, accs = [], []
-    for p in probs:
+    for p, gs in probs:
         acc = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
         boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut,
-                                  eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=32,
-                                  accumulator=p.accumulator, **device_inputs(p)))
+                                  eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=gs,
+                                  accumulator=getattr(p, "accumulator", None), **device_inputs(p)))
         accs.append(acc)
     _, pb = ngr.batch_build_force(ctx, boxes, per_box=True)
-    for p, acc, st in zip(probs, accs, pb):
+    for (p, gs), acc, st in zip(probs, accs, pb):
         a = acc.cpu().numpy()
-        a1, st1, _, _ = gpu_solve(ctx, p, group_size=32)
+        a1, st1, _, _ = gpu_solve(ctx, p, group_size=gs)
         assert np.array_equal(a1, a), p.name
-        ao, so, co, _ = oracle.Tree.of(p, group_size=32).force(oracle.law_of(p))
+        ao, so, co, _ = oracle.Tree.of(p, group_size=gs).force(oracle.law_of(p))
         assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"]), p.name
         assert force_gate(a, ao, so)[0], p.name
 
