@@ -685,9 +685,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         auto eval = [&](uint32_t b, uint32_t nrec) {
             const unsigned char* tb = tsm + (TAB == kPair ? 8u : 4u) * b * tstride;
             const uint32_t iters = (nrec + K - 1u) >> lk;
-            // the pair's own softening (section 2: D^2 softenings)
-            const double e2 = P.eps2_ab[a * Dk + b];
-            const float to = P.toff_ab[a * Dk + b];
+            // the pair's own softening (section 2: D^2 softenings); the pair
+            // index is wave-uniform, so its address arithmetic stays scalar
+            const uint32_t ab = uniform(a * Dk + b);
+            const double e2 = P.eps2_ab[ab];
+            const float to = P.toff_ab[ab];
             if (cored_pair(b)) {
                 const double* rrs = recs + replica;
                 double &x = ox[0], &y = oy[0], &z = oz[0], &gx = ax[0], &gy = ay[0], &gz = az[0];
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     d1 -= rint(d1);
                     d2 -= rint(d2);
                     const uint32_t slot = (uint32_t)__popcll(m & lt);
-                    rec[slot] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[b] * r.w);
+                    rec[slot] = make_double4(d0 * bx, d1 * bx, d2 * bx, Ga[uniform(b)] * r.w);
                     if (cp) {
                         // a monopole of N_perp bodies: each of mass M / N_perp when tracked
                         double body = r.w;
@@ -833,7 +835,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     ex -= rint(ex);
                     ey -= rint(ey);
                     ez -= rint(ez);
-                    rec[lane] = make_double4(ex + (double)pr.lx, ey + (double)pr.ly, ez + (double)pr.lz, Ga[b] * pr.m);
+                    rec[lane] = make_double4(ex + (double)pr.lx, ey + (double)pr.ly, ez + (double)pr.lz,
+                                             Ga[uniform(b)] * pr.m);
                     if (cp) recs[lane] = ((cmask >> b) & 1u) ? pr.m * inv4pib : 0.0;
                 }
                 if (K > 1u && (uint32_t)lane < 3u) {
