@@ -86,8 +86,16 @@ __device__ inline uint64_t hilbert60(uint32_t x, uint32_t y, uint32_t z)
 // or Peano-Hilbert); and counts each species of the box (the counts give its
 // species segments).
 // Per-box flags and counts take one global atomic per workgroup.
-__global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64_t* __restrict__ Xin,
-                       uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, double* __restrict__ mass_cat,
+// One particle in input order between the ingest and the reordering: the
+// lattice coordinates and the mass together, so that the reordering reads
+// one 32-byte record per particle.
+struct alignas(32) InRec {
+    uint64_t x, y, z;
+    double m;
+};
+
+__global__ void ingest(const BoxInDev* __restrict__ boxes, InRec* __restrict__ rin,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ idx,
                        uint16_t* __restrict__ boxid, uint32_t* __restrict__ flags,
                        unsigned long long* __restrict__ counts)
 {
@@ -125,15 +133,17 @@ __global__ void ingest(const BoxInDev* __restrict__ boxes, uint64_t ntot, uint64
             for (int a = 0; a < 3; ++a) X[a] = B.lattice[a * B.n + i];
         }
         const uint64_t g = B.off + i;
-        Xin[g] = X[0];
-        Xin[ntot + g] = X[1];
-        Xin[2 * ntot + g] = X[2];
+        InRec r;
+        r.x = X[0];
+        r.y = X[1];
+        r.z = X[2];
+        r.m = m;
+        rin[g] = r;
         const uint64_t mo = B.key_order == NGR_KEY_HILBERT
                                 ? hilbert60((uint32_t)(X[0] >> 44), (uint32_t)(X[1] >> 44), (uint32_t)(X[2] >> 44))
                                 : (spread3(X[0] >> 44) << 2) | (spread3(X[1] >> 44) << 1) | spread3(X[2] >> 44);
         keys[g] = ((uint64_t)(s & 0xfu) << kKeyBits) | mo;
         idx[g] = (uint32_t)g;
-        mass_cat[g] = m;
         if (boxid) boxid[g] = (uint16_t)k;
     }
     for (uint32_t b = 0; b < NGR_MAX_SPECIES; ++b)
@@ -183,15 +193,14 @@ __global__ void gather_keys(uint64_t n, const uint32_t* __restrict__ perm, const
 
 // The single reordering of the particle data into sorted order: the
 // lattice coordinates and masses, and the walk's split records.
-__global__ void gather_particles(uint64_t n, const uint32_t* __restrict__ perm, const uint64_t* __restrict__ Xin,
-                                 const double* __restrict__ min, uint64_t* __restrict__ Xout,
-                                 double* __restrict__ mout, PRec* __restrict__ Pout)
+__global__ void gather_particles(uint64_t n, const uint32_t* __restrict__ perm, const InRec* __restrict__ rin,
+                                 uint64_t* __restrict__ Xout, double* __restrict__ mout, PRec* __restrict__ Pout)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t p = perm[i];
-    const uint64_t x = Xin[p], y = Xin[n + p], z = Xin[2 * n + p];
-    const double m = min[p];
+    const InRec q = rin[perm[i]];
+    const uint64_t x = q.x, y = q.y, z = q.z;
+    const double m = q.m;
     Xout[i] = x;
     Xout[n + i] = y;
     Xout[2 * n + i] = z;
@@ -513,12 +522,10 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
     ctx.to_device(t.boff_dev, t.boff.data(), (nbox + 1) * sizeof(uint64_t));
     std::vector<uint64_t> counts((size_t)nbox * NGR_MAX_SPECIES, 0);
     std::vector<uint32_t> flags(nbox, 0);
-    uint64_t* Xin = nullptr;
-    double* mass_cat = nullptr;
+    InRec* rin = nullptr;
     uint16_t* boxid = nullptr;
     if (n) {
-        Xin = static_cast<uint64_t*>(ctx.alloc(3 * n * sizeof(uint64_t)));
-        mass_cat = static_cast<double*>(ctx.alloc(n * sizeof(double)));
+        rin = static_cast<InRec*>(ctx.alloc(n * sizeof(InRec)));
         if (nbox > 1) boxid = static_cast<uint16_t*>(ctx.alloc(n * sizeof(uint16_t)));
         BoxInDev* bin_dev = static_cast<BoxInDev*>(ctx.alloc(nbox * sizeof(BoxInDev)));
         uint32_t* flags_dev = static_cast<uint32_t*>(ctx.alloc(nbox * sizeof(uint32_t)));
@@ -532,8 +539,8 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
         // about four workgroups per CU over all boxes, at least one per box
         const uint64_t per_box = std::max<uint64_t>(1, (4ull * ctx.num_cu + nbox - 1) / nbox);
         const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(nmax, 256), per_box));
-        hipLaunchKernelGGL(ingest, dim3(gx, nbox), dim3(256), 0, ctx.stream, bin_dev, n, Xin, t.keys, t.perm, mass_cat,
-                           boxid, flags_dev, counts_dev);
+        hipLaunchKernelGGL(ingest, dim3(gx, nbox), dim3(256), 0, ctx.stream, bin_dev, rin, t.keys, t.perm, boxid,
+                           flags_dev, counts_dev);
         LAUNCH_CHECK("ingest");
         mark(1);
         ctx.to_host(flags.data(), flags_dev, nbox * sizeof(uint32_t));
@@ -545,8 +552,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
     for (uint32_t k = 0; k < nbox; ++k) {
         if (!flags[k]) continue;
         const std::string where = nbox > 1 ? "box " + std::to_string(k) + ": " : "";
-        ctx.release(Xin);
-        ctx.release(mass_cat);
+        ctx.release(rin);
         ctx.release(boxid);
         if (flags[k] & kBadSpecies) fail(NGR_EINVAL, where + "a species id is >= D");
         if (flags[k] & kBadMass) fail(NGR_EINVAL, where + "a mass is negative or not finite");
@@ -587,13 +593,12 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
             ctx.release(kb);
             ctx.release(keys0);
         }
-        hipLaunchKernelGGL(gather_particles, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, Xin, mass_cat,
-                           t.X, t.mass, t.P);
+        hipLaunchKernelGGL(gather_particles, dim3(blocks_for(n, 256)), dim3(256), 0, ctx.stream, n, t.perm, rin, t.X,
+                           t.mass, t.P);
         LAUNCH_CHECK("gather_particles");
         ctx.release(ktmp);
         ctx.release(vtmp);
-        ctx.release(Xin);
-        ctx.release(mass_cat);
+        ctx.release(rin);
         ctx.release(boxid);
     }
 

@@ -2,7 +2,9 @@
 // pairs, 8 bits per pass. Every pass: a per-tile digit histogram, one
 // exclusive scan over the digit-major histogram table, and a scatter in which
 // each tile ranks its keys digit by digit in input order (wave-wide ballots
-// find the lanes sharing a digit), which keeps the sort stable.
+// find the lanes sharing a digit), which keeps the sort stable. The ranked
+// tile is first laid out in LDS in digit order, then written out so that each
+// digit's run of the tile goes to consecutive addresses.
 #include "ngr_internal.hpp"
 
 namespace ngr {
@@ -33,12 +35,30 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
                                                           const uint32_t* __restrict__ vin,
                                                           uint64_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout, uint64_t n, int shift,
-                                                          const uint32_t* __restrict__ offsets, uint32_t tiles)
+                                                          const uint32_t* __restrict__ offsets,
+                                                          const uint32_t* __restrict__ counts, uint32_t tiles)
 {
-    __shared__ uint32_t base[kDigits];
+    __shared__ uint32_t base[kDigits];      // running tile-local position of each digit
+    __shared__ uint32_t first[kDigits];     // tile-local start of each digit's run
     __shared__ uint32_t wcount[kThreads / 64][kDigits];
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    base[tid] = offsets[(uint64_t)tid * tiles + blockIdx.x];
+    // tile-local starts: exclusive scan of the tile's digit counts
+    {
+        const uint32_t c = counts[(uint64_t)tid * tiles + blockIdx.x];
+        wcount[0][tid] = c;
+        __syncthreads();
+        for (int d = 1; d < kDigits; d <<= 1) {
+            const uint32_t u = tid >= d ? wcount[0][tid - d] : 0u;
+            __syncthreads();
+            wcount[0][tid] += u;
+            __syncthreads();
+        }
+        first[tid] = wcount[0][tid] - c;
+        base[tid] = wcount[0][tid] - c;
+        __syncthreads();
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     for (int r = 0; r < kRounds; ++r) {
@@ -72,11 +92,21 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
         }
         __syncthreads();
         if (valid) {
-            uint32_t pos = wcount[wave][digit] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            const uint32_t pos = wcount[wave][digit] + rank;   // tile-local, digit order
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
+    }
+    // write-out: consecutive threads take consecutive entries of the digit-ordered
+    // tile, so each digit's run lands on consecutive global positions
+    const uint32_t valid_n = (uint32_t)min<uint64_t>((uint64_t)kTile, n - tile0);
+    for (uint32_t j = tid; j < valid_n; j += kThreads) {
+        const uint64_t key = skey[j];
+        const uint32_t digit = (uint32_t)((key >> shift) & 0xff);
+        const uint64_t pos = (uint64_t)offsets[(uint64_t)digit * tiles + blockIdx.x] + (j - first[digit]);
+        kout[pos] = key;
+        vout[pos] = sval[j];
     }
 }
 
@@ -87,7 +117,9 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
 {
     if (n <= 1) return;
     const uint32_t tiles = (uint32_t)((n + kTile - 1) / kTile);
-    uint32_t* hist = static_cast<uint32_t*>(ctx.alloc((size_t)kDigits * tiles * sizeof(uint32_t)));
+    // per tile and digit: the counts, and their exclusive scan (digit-major)
+    uint32_t* hist = static_cast<uint32_t*>(ctx.alloc((size_t)2 * kDigits * tiles * sizeof(uint32_t)));
+    uint32_t* offs = hist + (size_t)kDigits * tiles;
     uint64_t* ka = keys;
     uint32_t* va = vals;
     uint64_t* kb = keys_tmp;
@@ -97,8 +129,9 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
         int shift = 8 * p;
         hipLaunchKernelGGL(digit_histogram, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, n, shift, hist, tiles);
         LAUNCH_CHECK("digit_histogram");
-        scan_exclusive(ctx, hist, hist, (uint64_t)kDigits * tiles, nullptr);
-        hipLaunchKernelGGL(digit_scatter, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, va, kb, vb, n, shift, hist, tiles);
+        scan_exclusive(ctx, hist, offs, (uint64_t)kDigits * tiles, nullptr);
+        hipLaunchKernelGGL(digit_scatter, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, va, kb, vb, n, shift, offs, hist,
+                           tiles);
         LAUNCH_CHECK("digit_scatter");
         std::swap(ka, kb);
         std::swap(va, vb);
