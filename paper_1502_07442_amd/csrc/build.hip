@@ -360,14 +360,16 @@ __global__ void node_counts(uint64_t nn, const uint32_t* __restrict__ node_box, 
 }
 
 // Monopoles of one level (section 2.2), one thread per (node, species b).
-// A leaf sums its species-b particles directly, relative to the cell corner
-// so that the differences are exact integers; an internal node combines the
+// A leaf sums its species-b particles directly, relative to the cell corner:
+// from the split records, the high part minus the corner is exact and adding
+// the low part rounds once, so each offset is the integer lattice difference
+// converted to float64 (in units of the box). An internal node combines the
 // monopoles of its children. Centres are kept as fractions of the box.
-__global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t D, uint64_t nn, uint64_t n,
+__global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t D, uint64_t nn,
                                const uint4* __restrict__ cell, const int32_t* __restrict__ first_child,
                                const uint8_t* __restrict__ n_child, const uint32_t* __restrict__ start,
-                               const uint32_t* __restrict__ count, const uint64_t* __restrict__ X,
-                               const double* __restrict__ mass, double4* __restrict__ mono)
+                               const uint32_t* __restrict__ count, const PRec* __restrict__ P,
+                               double4* __restrict__ mono)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_level * D) return;
@@ -376,20 +378,18 @@ __global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t 
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     double4 out;
     if (n_child[i] == 0) {
-        uint4 c = cell[i];
-        uint64_t cx = (uint64_t)c.x << 44, cy = (uint64_t)c.y << 44, cz = (uint64_t)c.z << 44;
+        const uint4 c = cell[i];
+        const double cx = (double)c.x * 0x1p-20, cy = (double)c.y * 0x1p-20, cz = (double)c.z * 0x1p-20;
         uint64_t j0 = start[i * D + b], j1 = j0 + count[i * D + b];
         for (uint64_t j = j0; j < j1; ++j) {
-            double m = mass[j];
+            const PRec q = P[j];
+            const double m = q.m;
             M += m;
-            sx += m * (double)(X[j] - cx);
-            sy += m * (double)(X[n + j] - cy);
-            sz += m * (double)(X[2 * n + j] - cz);
+            sx += m * ((q.hx - cx) + (double)q.lx);
+            sy += m * ((q.hy - cy) + (double)q.ly);
+            sz += m * ((q.hz - cz) + (double)q.lz);
         }
-        const double s64 = 0x1p-64;
-        out = M > 0.0 ? make_double4(((double)cx + sx / M) * s64, ((double)cy + sy / M) * s64,
-                                     ((double)cz + sz / M) * s64, M)
-                      : make_double4(0.0, 0.0, 0.0, 0.0);
+        out = M > 0.0 ? make_double4(cx + sx / M, cy + sy / M, cz + sz / M, M) : make_double4(0.0, 0.0, 0.0, 0.0);
     } else {
         uint64_t c0 = (uint64_t)first_child[i], c1 = c0 + n_child[i];
         for (uint64_t c = c0; c < c1; ++c) {
@@ -702,9 +702,8 @@ void compute_monopoles(Context& ctx, Tree& t)
     for (int lvl = (int)t.depth; lvl >= 0; --lvl) {
         uint64_t lb = t.level_start[lvl], nl = t.level_start[lvl + 1] - lb;
         if (!nl) continue;
-        hipLaunchKernelGGL(monopole_level, dim3(blocks_for(nl * D, 256)), dim3(256), 0, ctx.stream, lb, nl, D, t.nn, t.n, t.cell,
-                                                                         t.first_child, t.n_child, t.start,
-                                                                         t.count, t.X, t.mass, t.mono);
+        hipLaunchKernelGGL(monopole_level, dim3(blocks_for(nl * D, 256)), dim3(256), 0, ctx.stream, lb, nl, D, t.nn,
+                           t.cell, t.first_child, t.n_child, t.start, t.count, t.P, t.mono);
         LAUNCH_CHECK("monopole_level");
     }
     t.has_monopoles = true;
