@@ -526,15 +526,16 @@ def build_roofline(st, n):
     """Achieved HBM bandwidth of the build phases on their algorithmic bytes
     (device time of each phase from the library's events, host read-backs
     between levels included): ingest (read position 24 B, species 1 B, mass
-    8 B; write lattice 24 B, key 8 B, index 4 B, mass 8 B), the sort (eight
-    8-bit passes, each reading and writing key and index, 24 B, and reading
-    the key again for the histogram, 8 B) with the one reordering (read the
-    index 4 B, gather lattice and mass 32 B, write them 32 B), and the
-    monopoles (read every particle's lattice and mass once, 32 B, plus
-    32 B per node and species read and written)."""
+    8 B; write the lattice-and-mass record 32 B, key 8 B, index 4 B), the
+    sort (eight 8-bit passes, each reading and writing key and index, 24 B,
+    and reading the key again for the histogram, 8 B) with the one
+    reordering (read the index 4 B and one 32-B record; write lattice and
+    mass 32 B and the walk's split record 48 B), and the monopoles (read
+    every particle's split record once, 48 B, plus 32 B per node and
+    species read and written)."""
     ingest = 77.0 * n
-    sort = (8 * 32.0 + 68.0) * n
-    mono = 32.0 * n + 2 * 32.0 * st["n_nodes"] * 6
+    sort = (8 * 32.0 + 116.0) * n
+    mono = 48.0 * n + 2 * 32.0 * st["n_nodes"] * 6
     gbps = lambda b, ms: b / (ms * 1e-3) / 1e9 if ms > 0 else None
     return {"ingest_gbps": gbps(ingest, st["ms_build_ingest"]), "sort_and_gather_gbps": gbps(sort, st["ms_build_sort"]),
             "monopoles_gbps": gbps(mono, st["ms_monopoles"]), "peak_gbps": 8000.0,

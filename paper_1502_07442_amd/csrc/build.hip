@@ -248,10 +248,13 @@ __device__ inline uint64_t lower_bound(const uint64_t* __restrict__ keys, uint64
     return lo;
 }
 
-// One thread per (node of this level, octant): the octant's particles of each
-// species are found by binary search inside the node's species range (the
-// range is sorted by key). Nodes holding more than B particles below level 20
-// split; a non-empty octant becomes a child.
+// One thread per (node of this level, octant): the start of the octant's
+// particles of each species is found by binary search inside the node's
+// species range (the range is sorted by key). The octant ends where the next
+// one starts (the next thread, as a node's eight octants are consecutive lanes
+// of one wave), the last at the end of the range, as every key of the range
+// carries the node's prefix. Nodes holding more than B particles below level
+// 20 split; a non-empty octant becomes a child.
 __global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl, uint32_t D,
                             const uint32_t* __restrict__ leaf_size, const uint32_t* __restrict__ node_box,
                             const uint64_t* __restrict__ keys, const uint64_t* __restrict__ prefix,
@@ -259,31 +262,76 @@ __global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl
                             uint32_t* __restrict__ cstart, uint32_t* __restrict__ ccount,
                             uint32_t* __restrict__ flags)
 {
-    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_level * 8) return;
-    uint64_t p = level_begin + t / 8;
-    uint32_t o = (uint32_t)(t % 8);
-    const uint32_t B = leaf_size[node_box[p]];
-    uint64_t total = 0;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_level * 8) return;   // whole nodes: the block size is a multiple of 8
+    const uint64_t p = level_begin + t / 8;
+    const uint32_t o = (uint32_t)(t % 8);
+    uint32_t total = 0;
     for (uint32_t b = 0; b < D; ++b) total += count[p * D + b];
-    if (total <= B || lvl >= (uint32_t)kLevels) {
-        flags[t] = 0;
+    // every lane runs the species loop below (the exchange needs its neighbour)
+    const bool split = total > leaf_size[node_box[p]] && lvl < (uint32_t)kLevels;
+    const uint32_t sh = kKeyBits - 3 * (lvl + 1);
+    const uint64_t klo = (prefix[p] * 8 + o) << sh;
+    uint32_t tot = 0;
+    for (uint32_t b = 0; b < D; ++b) {
+        const uint32_t lo = start[p * D + b], hi = lo + count[p * D + b];
+        const uint32_t a0 = split ? (uint32_t)lower_bound(keys, lo, hi, ((uint64_t)b << kKeyBits) + klo) : lo;
+        const uint32_t next = __shfl_down(a0, 1);
+        const uint32_t a1 = o == 7 ? hi : next;
+        if (split) {
+            cstart[t * D + b] = a0;
+            ccount[t * D + b] = a1 - a0;
+            tot += a1 - a0;
+        }
+    }
+    flags[t] = split && tot > 0;
+}
+
+// The same split for a level of few nodes, one wave per node: lane 8·o + b
+// searches where octant o starts in the node's species-b range, so the
+// searches of a node run side by side rather than one after another (at the
+// top levels each search spans millions of keys). An octant ends where the
+// next one starts, the last at the end of the range, as every key of the range
+// carries the node's prefix. Same outputs as split_level.
+__global__ __launch_bounds__(256) void split_level_wave(uint64_t level_begin, uint64_t n_level, uint32_t lvl,
+                                                        uint32_t D, const uint32_t* __restrict__ leaf_size,
+                                                        const uint32_t* __restrict__ node_box,
+                                                        const uint64_t* __restrict__ keys,
+                                                        const uint64_t* __restrict__ prefix,
+                                                        const uint32_t* __restrict__ start,
+                                                        const uint32_t* __restrict__ count,
+                                                        uint32_t* __restrict__ cstart, uint32_t* __restrict__ ccount,
+                                                        uint32_t* __restrict__ flags)
+{
+    const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= n_level) return;   // a whole wave leaves together
+    const uint32_t lane = threadIdx.x & 63u, o = lane >> 3, b = lane & 7u;
+    const uint64_t p = level_begin + w;
+    const bool real = b < D;
+    const uint32_t lo = real ? start[p * D + b] : 0u;
+    const uint32_t cnt = real ? count[p * D + b] : 0u;
+    // the node's particle count: each species' count once, from the lanes of octant 0
+    uint32_t total = o == 0 ? cnt : 0u;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) total += __shfl_xor(total, m);
+    const uint64_t t = w * 8 + o;
+    if (total <= leaf_size[node_box[p]] || lvl >= (uint32_t)kLevels) {   // uniform over the wave
+        if (b == 0) flags[t] = 0;
         return;
     }
     const uint32_t sh = kKeyBits - 3 * (lvl + 1);
-    const uint64_t cp = prefix[p] * 8 + o;
-    const uint64_t klo = cp << sh, khi = (cp + 1) << sh;
-    uint64_t tot = 0;
-    for (uint32_t b = 0; b < D; ++b) {
-        uint64_t lo = start[p * D + b], hi = lo + count[p * D + b];
-        uint64_t sb = (uint64_t)b << kKeyBits;
-        uint64_t a0 = lower_bound(keys, lo, hi, sb + klo);
-        uint64_t a1 = lower_bound(keys, a0, hi, sb + khi);
-        cstart[t * D + b] = (uint32_t)a0;
-        ccount[t * D + b] = (uint32_t)(a1 - a0);
-        tot += a1 - a0;
+    const uint64_t klo = (prefix[p] * 8 + o) << sh;
+    const uint32_t a0 = real ? (uint32_t)lower_bound(keys, lo, (uint64_t)lo + cnt, ((uint64_t)b << kKeyBits) + klo) : 0u;
+    const uint32_t next = __shfl_down(a0, 8);
+    const uint32_t a1 = o == 7 ? lo + cnt : next;
+    if (real) {
+        cstart[t * D + b] = a0;
+        ccount[t * D + b] = a1 - a0;
     }
-    flags[t] = tot > 0;
+    uint32_t c = real ? a1 - a0 : 0u;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) c += __shfl_xor(c, m);
+    if (b == 0) flags[t] = c > 0;
 }
 
 // Write the children found by split_level (in key order, after all
@@ -295,7 +343,7 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
                               const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ ccount,
                               uint8_t* level, uint64_t* prefix, int32_t* parent, int32_t* first_child,
                               uint8_t* n_child, uint4* cell, uint32_t* start, uint32_t* count,
-                              uint32_t* node_box, const uint64_t* __restrict__ X, uint64_t n)
+                              uint32_t* node_box, const PRec* __restrict__ P)
 {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_level * 8) return;
@@ -326,9 +374,13 @@ __global__ void emit_children(uint64_t level_begin, uint64_t n_level, uint64_t n
             found = true;
         }
     }
+    // the high part of a split record is the lattice word with its low bits
+    // cleared, exactly, so it gives back the word's top lvl + 1 bits
+    const PRec q = P[j];
     const uint32_t sh = 64u - (lvl + 1u), up = (uint32_t)kLevels - (lvl + 1u);
-    cell[c] = make_uint4((uint32_t)(X[j] >> sh) << up, (uint32_t)(X[n + j] >> sh) << up,
-                         (uint32_t)(X[2 * n + j] >> sh) << up, lvl + 1);
+    cell[c] = make_uint4((uint32_t)((uint64_t)(q.hx * 0x1p64) >> sh) << up,
+                         (uint32_t)((uint64_t)(q.hy * 0x1p64) >> sh) << up,
+                         (uint32_t)((uint64_t)(q.hz * 0x1p64) >> sh) << up, lvl + 1);
 }
 
 // Number of leaves (nodes without children), over a bounded grid with one
@@ -407,6 +459,11 @@ __global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t 
 }
 
 inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)((work + threads - 1) / threads); }
+
+// The top levels are split one wave per node, down to the first level of more
+// than this many nodes (below it ranges are short and one thread per octant is
+// faster).
+constexpr uint64_t kWaveSplitNodes = 1u << 19;
 
 template <class T>
 void grow(Context& ctx, T*& p, uint64_t old_n, uint64_t new_n)
@@ -625,6 +682,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
     uint32_t* total_dev = reinterpret_cast<uint32_t*>(leaves + 1);
     HIP_CHECK(hipMemsetAsync(leaves, 0, 2 * sizeof(unsigned long long), ctx.stream));
     uint32_t depth = 0;
+    bool wave_split = true;   // the top levels, down to the first one of many nodes
     for (uint32_t lvl = 0; lvl <= (uint32_t)kLevels; ++lvl) {
         uint64_t lb = t.level_start[lvl], nl = t.level_start[lvl + 1] - lb;
         if (nl == 0) break;
@@ -634,9 +692,16 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
         uint32_t* offs = fl + slots;
         uint32_t* cst = static_cast<uint32_t*>(ctx.alloc(slots * D * sizeof(uint32_t) * 2));
         uint32_t* ccn = cst + slots * D;
-        hipLaunchKernelGGL(split_level, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, lvl, D, leaf_dev,
-                           t.node_box, t.keys, t.prefix, t.start, t.count, cst, ccn, fl);
-        LAUNCH_CHECK("split_level");
+        wave_split = wave_split && nl <= kWaveSplitNodes;
+        if (wave_split) {
+            hipLaunchKernelGGL(split_level_wave, dim3(blocks_for(nl * 64, 256)), dim3(256), 0, ctx.stream, lb, nl, lvl, D,
+                               leaf_dev, t.node_box, t.keys, t.prefix, t.start, t.count, cst, ccn, fl);
+            LAUNCH_CHECK("split_level_wave");
+        } else {
+            hipLaunchKernelGGL(split_level, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, lvl, D,
+                               leaf_dev, t.node_box, t.keys, t.prefix, t.start, t.count, cst, ccn, fl);
+            LAUNCH_CHECK("split_level");
+        }
         scan_exclusive(ctx, fl, offs, slots, total_dev);
         uint64_t next_word = 0;
         ctx.read_words(&next_word, total_dev, 1);
@@ -645,7 +710,7 @@ void build_forest(Context& ctx, const std::vector<BoxIn>& boxes, Tree& t, bool t
         grow_nodes(ctx, t, nb + next);
         hipLaunchKernelGGL(emit_children, dim3(blocks_for(slots, 256)), dim3(256), 0, ctx.stream, lb, nl, nb, lvl, D, fl,
                            offs, cst, ccn, t.level, t.prefix, t.parent, t.first_child, t.n_child, t.cell, t.start,
-                           t.count, t.node_box, t.X, t.n);
+                           t.count, t.node_box, t.P);
         LAUNCH_CHECK("emit_children");
         ctx.release(fl);
         ctx.release(cst);

@@ -1,9 +1,10 @@
 // Stable least-significant-digit radix sort of (uint64 key, uint32 value)
 // pairs, 8 bits per pass. Every pass: a per-tile digit histogram, one
-// exclusive scan over the digit-major histogram table, and a scatter in which
-// each tile ranks its keys digit by digit in input order (wave-wide ballots
-// find the lanes sharing a digit), which keeps the sort stable. The ranked
-// tile is first laid out in LDS in digit order, then written out so that each
+// exclusive scan over the digit-major histogram table, and a scatter. In the
+// scatter each wave loads its share of the tile at once and ranks it in input
+// order (wave-wide ballots find the lanes sharing a digit), which keeps the
+// sort stable; the waves' digit counts are then combined once. The ranked
+// tile is laid out in LDS in digit order, then written out so that each
 // digit's run of the tile goes to consecutive addresses.
 #include "ngr_internal.hpp"
 
@@ -35,77 +36,94 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
                                                           const uint32_t* __restrict__ vin,
                                                           uint64_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout, uint64_t n, int shift,
-                                                          const uint32_t* __restrict__ offsets,
-                                                          const uint32_t* __restrict__ counts, uint32_t tiles)
+                                                          const uint32_t* __restrict__ offsets, uint32_t tiles)
 {
-    __shared__ uint32_t base[kDigits];      // running tile-local position of each digit
-    __shared__ uint32_t first[kDigits];     // tile-local start of each digit's run
-    __shared__ uint32_t wcount[kThreads / 64][kDigits];
+    constexpr int kWaves = kThreads / 64;
+    __shared__ uint32_t wcount[kWaves][kDigits];   // per wave: digit counts, then the wave's start per digit
+    __shared__ uint32_t first[kDigits];            // tile-local start of each digit's run
+    __shared__ uint32_t wsum[kWaves];
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sval[kTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // tile-local starts: exclusive scan of the tile's digit counts
-    {
-        const uint32_t c = counts[(uint64_t)tid * tiles + blockIdx.x];
-        wcount[0][tid] = c;
-        __syncthreads();
-        for (int d = 1; d < kDigits; d <<= 1) {
-            const uint32_t u = tid >= d ? wcount[0][tid - d] : 0u;
-            __syncthreads();
-            wcount[0][tid] += u;
-            __syncthreads();
-        }
-        first[tid] = wcount[0][tid] - c;
-        base[tid] = wcount[0][tid] - c;
-        __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kDigits / 64; ++j) wcount[wave][lane + 64 * j] = 0;
+    // a wave owns kRounds x 64 consecutive keys of the tile; all its loads are issued before the ranking
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
+    const uint64_t w0 = tile0 + (uint64_t)wave * (kRounds * 64) + lane;
+    uint64_t key[kRounds];
+    uint32_t val[kRounds], rank[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint64_t i = w0 + (uint64_t)r * 64;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0u;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
+    // wave-local ranking in input order: lanes sharing a digit are found with
+    // ballots; the lowest of them advances the wave's count of that digit
+#pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        uint64_t i = tile0 + (uint64_t)r * kThreads + tid;
-        bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0;
-        uint32_t val = valid ? vin[i] : 0;
-        uint32_t digit = (uint32_t)((key >> shift) & 0xff);
+        const bool valid = w0 + (uint64_t)r * 64 < n;
+        const uint32_t digit = (uint32_t)((key[r] >> shift) & 0xff);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            uint64_t b = __ballot((digit >> bit) & 1u);
+            const uint64_t b = __ballot((digit >> bit) & 1u);
             peers &= ((digit >> bit) & 1u) ? b : ~b;
         }
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        uint32_t cnt = (uint32_t)__popcll(peers);
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) wcount[w][tid] = 0;
-        __syncthreads();
-        if (valid && rank == 0) wcount[wave][digit] = cnt;
-        __syncthreads();
-        {
-            uint32_t run = base[tid];
-#pragma unroll
-            for (int w = 0; w < kThreads / 64; ++w) {
-                uint32_t c = wcount[w][tid];
-                wcount[w][tid] = run;
-                run += c;
-            }
-            base[tid] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = wcount[wave][digit] + rank;   // tile-local, digit order
-            skey[pos] = key;
-            sval[pos] = val;
-        }
-        __syncthreads();
+        const uint32_t pre = (uint32_t)__popcll(peers & lt);
+        const uint32_t before = wcount[wave][digit];
+        __builtin_amdgcn_wave_barrier();
+        rank[r] = before + pre;
+        if (valid && pre == 0) wcount[wave][digit] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    // thread d: the tile's count of digit d, its tile-local start (a scan over
+    // the digits: shuffles within a wave, wave totals through LDS) and the
+    // start of each wave's run of d
+    {
+        uint32_t c[kWaves], tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            c[w] = wcount[w][tid];
+            tot += c[w];
+        }
+        uint32_t inc = tot;
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) {
+            const uint32_t u = __shfl_up(inc, s);
+            if (lane >= s) inc += u;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - tot;
+        for (int w = 0; w < wave; ++w) run += wsum[w];
+        first[tid] = run;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            wcount[w][tid] = run;
+            run += c[w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (w0 + (uint64_t)r * 64 < n) {
+            const uint32_t pos = wcount[wave][(uint32_t)((key[r] >> shift) & 0xff)] + rank[r];   // tile-local, digit order
+            skey[pos] = key[r];
+            sval[pos] = val[r];
+        }
+    }
+    __syncthreads();
     // write-out: consecutive threads take consecutive entries of the digit-ordered
     // tile, so each digit's run lands on consecutive global positions
     const uint32_t valid_n = (uint32_t)min<uint64_t>((uint64_t)kTile, n - tile0);
     for (uint32_t j = tid; j < valid_n; j += kThreads) {
-        const uint64_t key = skey[j];
-        const uint32_t digit = (uint32_t)((key >> shift) & 0xff);
+        const uint64_t k = skey[j];
+        const uint32_t digit = (uint32_t)((k >> shift) & 0xff);
         const uint64_t pos = (uint64_t)offsets[(uint64_t)digit * tiles + blockIdx.x] + (j - first[digit]);
-        kout[pos] = key;
+        kout[pos] = k;
         vout[pos] = sval[j];
     }
 }
@@ -130,7 +148,7 @@ void radix_sort_pairs(Context& ctx, uint64_t* keys, uint32_t* vals, uint64_t* ke
         hipLaunchKernelGGL(digit_histogram, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, n, shift, hist, tiles);
         LAUNCH_CHECK("digit_histogram");
         scan_exclusive(ctx, hist, offs, (uint64_t)kDigits * tiles, nullptr);
-        hipLaunchKernelGGL(digit_scatter, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, va, kb, vb, n, shift, offs, hist,
+        hipLaunchKernelGGL(digit_scatter, dim3(tiles), dim3(kThreads), 0, ctx.stream, ka, va, kb, vb, n, shift, offs,
                            tiles);
         LAUNCH_CHECK("digit_scatter");
         std::swap(ka, kb);
