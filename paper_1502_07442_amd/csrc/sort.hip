@@ -40,13 +40,14 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
 {
     constexpr int kWaves = kThreads / 64;
     __shared__ uint32_t wcount[kWaves][kDigits];   // per wave: digit counts, then the wave's start per digit
-    __shared__ uint32_t first[kDigits];            // tile-local start of each digit's run
+    __shared__ uint32_t dest_base[kDigits];         // per digit: global start of its run minus the tile-local start
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sval[kTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int j = 0; j < kDigits / 64; ++j) wcount[wave][lane + 64 * j] = 0;
+    const uint32_t gstart = offsets[(uint64_t)tid * tiles + blockIdx.x];   // digit tid's global start for this tile
     // a wave owns kRounds x 64 consecutive keys of the tile; all its loads are issued before the ranking
     const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
     const uint64_t w0 = tile0 + (uint64_t)wave * (kRounds * 64) + lane;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
         __syncthreads();
         uint32_t run = inc - tot;
         for (int w = 0; w < wave; ++w) run += wsum[w];
-        first[tid] = run;
+        dest_base[tid] = gstart - run;   // modulo 2^32; every position is below 2^32
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
             wcount[w][tid] = run;
@@ -119,10 +120,10 @@ __global__ __launch_bounds__(kThreads) void digit_scatter(const uint64_t* __rest
     // write-out: consecutive threads take consecutive entries of the digit-ordered
     // tile, so each digit's run lands on consecutive global positions
     const uint32_t valid_n = (uint32_t)min<uint64_t>((uint64_t)kTile, n - tile0);
+#pragma unroll 4
     for (uint32_t j = tid; j < valid_n; j += kThreads) {
         const uint64_t k = skey[j];
-        const uint32_t digit = (uint32_t)((k >> shift) & 0xff);
-        const uint64_t pos = (uint64_t)offsets[(uint64_t)digit * tiles + blockIdx.x] + (j - first[digit]);
+        const uint64_t pos = dest_base[(uint32_t)((k >> shift) & 0xff)] + j;
         kout[pos] = k;
         vout[pos] = sval[j];
     }
