@@ -41,6 +41,25 @@
 namespace ngr {
 namespace {
 
+// Inclusive scans (sum or maximum) over the 64 lanes of a wave, all lanes
+// active: DPP row shifts by 1, 2, 4 and 8 within each row of 16 lanes
+// (lanes shifted in from outside the row read 0), then the last lane of
+// rows 0 and 2 added into rows 1 and 3, and lane 31 into rows 2 and 3.
+template <bool MAX>
+__device__ inline uint32_t wave_scan(uint32_t v)
+{
+    auto join = [&](int u) { v = MAX ? max(v, (uint32_t)u) : v + (uint32_t)u; };
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));    // row_shr:1
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));    // row_shr:2
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));    // row_shr:4
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));    // row_shr:8
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
+    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31 into rows 2, 3
+    return v;
+}
+__device__ inline uint32_t wave_incl(uint32_t v) { return wave_scan<false>(v); }
+__device__ inline uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+
 // ------------------------------------------------------------- groups ----
 // One thread per (node, species a). For a node holding more than Ng particles
 // of species a (Ng of the node's box): a leaf is cut into chunks of Ng; an
@@ -118,24 +137,29 @@ __global__ void finish_groups(uint64_t ng, uint64_t n, uint32_t nbox, const uint
         }
         return;
     }
-    if (lane == 0) {
+    // per axis, wave-wide maxima of k + 1 and of ~k (the complement of the
+    // minimum); an empty lane holds 0 for both, which changes neither
+    uint32_t nl[3] = {0u, 0u, 0u}, h[3] = {0u, 0u, 0u};
+    if (s + lane < e) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t k = (uint32_t)(X[a * n + s + lane] >> 44);
+            nl[a] = ~k;
+            h[a] = k + 1;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nl[a] = wave_scan<true>(nl[a]);
+        h[a] = wave_scan<true>(h[a]);
+    }
+    if (lane == 63) {
         gcount[g] = (uint32_t)(e - s);
         gbox[g] = lo;
-    }
-    for (int a = 0; a < 3; ++a) {
-        uint32_t l = 0xffffffffu, h = 0;
-        if (s + lane < e) {
-            const uint32_t k = (uint32_t)(X[a * n + s + lane] >> 44);
-            l = k;
-            h = k + 1;
-        }
-        for (int d = 32; d > 0; d >>= 1) {
-            l = min(l, (uint32_t)__shfl_xor((int)l, d, 64));
-            h = max(h, (uint32_t)__shfl_xor((int)h, d, 64));
-        }
-        if (lane == 0) {
-            glo[a * ng + g] = l;
-            ghi[a * ng + g] = h;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            glo[a * ng + g] = ~nl[a];
+            ghi[a * ng + g] = h[a];
         }
     }
 }
@@ -207,7 +231,9 @@ __global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t D, const uint
         const int32_t x = (int32_t)(X[j] >> (64 - L)), y = (int32_t)(X[n + j] >> (64 - L)),
                       z = (int32_t)(X[2 * n + j] >> (64 - L));
         for (int32_t dx = -kOrderRadius; dx <= kOrderRadius; ++dx)
+#pragma unroll
             for (int32_t dy = -kOrderRadius; dy <= kOrderRadius; ++dy)
+#pragma unroll
                 for (int32_t dz = -kOrderRadius; dz <= kOrderRadius; ++dz) {
                     const uint64_t q = ((uint64_t)((x + dx) & m) << (2 * L)) | ((uint64_t)((y + dy) & m) << L) |
                                        (uint64_t)((z + dz) & m);
@@ -320,25 +346,6 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-
-// Inclusive scans (sum or maximum) over the 64 lanes of a wave, all lanes
-// active: DPP row shifts by 1, 2, 4 and 8 within each row of 16 lanes
-// (lanes shifted in from outside the row read 0), then the last lane of
-// rows 0 and 2 added into rows 1 and 3, and lane 31 into rows 2 and 3.
-template <bool MAX>
-__device__ inline uint32_t wave_scan(uint32_t v)
-{
-    auto join = [&](int u) { v = MAX ? max(v, (uint32_t)u) : v + (uint32_t)u; };
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));    // row_shr:1
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));    // row_shr:2
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));    // row_shr:4
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));    // row_shr:8
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
-    join(__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31 into rows 2, 3
-    return v;
-}
-__device__ inline uint32_t wave_incl(uint32_t v) { return wave_scan<false>(v); }
-__device__ inline uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
