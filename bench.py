@@ -76,8 +76,10 @@ def batched(ngr, synth, nbox=256, reps=3):
     ngr_batch_build_force call (group size chosen by the library), against
     the same boxes looped box by box through the single-box calls on the same
     stream; then the autotuner on the same boxes and the batch at the sizes
-    it chose. Inputs are resident before timing; each call includes the
-    build."""
+    it chose. Inputs, the law tables included, are resident on the device
+    before timing; each call includes the build. The batch with the tables
+    handed over from host memory (copied inside the call) is timed beside it
+    as context."""
     import numpy as np
     import torch
     probs = [synth.batch_box(k) for k in range(nbox)]
@@ -86,27 +88,36 @@ def batched(ngr, synth, nbox=256, reps=3):
     for q in probs:
         inputs.append(dict(species=torch.from_numpy(np.ascontiguousarray(q.species, np.uint8)).to(dev),
                            mass=torch.from_numpy(q.mass).to(dev), pos=torch.from_numpy(q.pos).to(dev)))
+    tabs = [None if q.tables is None else torch.from_numpy(np.ascontiguousarray(q.tables, np.float64)).to(dev)
+            for q in probs]
     accs = [torch.empty((3, q.n), dtype=torch.float64, device=dev) for q in probs]
-    boxes = [ngr.BatchBox(D=q.D, box=q.box, acc=a, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps,
-                          theta=q.theta, r_s=q.r_s, leaf_size=q.leaf_size, group_size=0, **t)
-             for q, t, a in zip(probs, inputs, accs)]
+
+    def make_boxes(tables):
+        return [ngr.BatchBox(D=q.D, box=q.box, acc=a, G=q.G, tables=tb, grid=q.grid, r_cut=q.r_cut, eps=q.eps,
+                             theta=q.theta, r_s=q.r_s, leaf_size=q.leaf_size, group_size=0, **t)
+                for q, t, a, tb in zip(probs, inputs, accs, tables)]
+    boxes = make_boxes(tabs)
     ctx = ngr.Context(0)
-    st = ngr.batch_build_force(ctx, boxes)          # warm-up
-    times = []
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ngr.batch_build_force(ctx, boxes)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t_batch = float(np.median(times))
+
+    def timed_batches(bx):
+        ngr.batch_build_force(ctx, bx)              # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = ngr.batch_build_force(ctx, bx)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), s
+    t_batch, st = timed_batches(boxes)
+    t_host_tables, _ = timed_batches(make_boxes([q.tables for q in probs]))
     inter = st["interactions_pp"] + st["interactions_pn"]
 
     def loop():
-        for q, t, a in zip(probs, inputs, accs):
+        for q, t, a, tb in zip(probs, inputs, accs, tabs):
             tree = ngr.tree_build(ctx, D=q.D, box=q.box, leaf_size=q.leaf_size, **t)
             ngr.compute_monopoles(ctx, tree)
-            ngr.tree_force(ctx, tree, G=q.G, tables=q.tables, grid=q.grid, r_cut=q.r_cut, eps=q.eps, theta=q.theta,
+            ngr.tree_force(ctx, tree, G=q.G, tables=tb, grid=q.grid, r_cut=q.r_cut, eps=q.eps, theta=q.theta,
                            r_s=q.r_s, group_size=0, acc=a)
             ngr.tree_free(ctx, tree)
     loop()                                          # warm-up
@@ -146,6 +157,7 @@ def batched(ngr, synth, nbox=256, reps=3):
                         f"in [0, 0.8], laws of their own", "n_boxes": nbox, "n_particles": st["n_particles"],
             "interactions": inter, "ms_per_batch": t_batch * 1e3, "boxes_per_s": nbox / t_batch,
             "interactions_per_s": inter / t_batch, "walk_ms": st["ms_walk"], "build_ms": st["ms_build"],
+            "ms_per_batch_host_tables": t_host_tables * 1e3,
             "loop_ms": t_loop * 1e3, "loop_boxes_per_s": nbox / t_loop, "speedup_vs_loop": t_loop / t_batch,
             "group_size": "library default (32)",
             "tuned": {"tune_ms": tune["ms"], "classes": tune["classes"], "ms_per_batch": t_tuned * 1e3,

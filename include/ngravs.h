@@ -142,8 +142,9 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
 
 /* Force-law and walk parameters.
  *   G        host, D x D float64, row = sink species a, column = source b
- *   tables   host, D x D x ntab float64 samples of f_ab on `grid`, or NULL
- *            for the Newtonian short-range factor
+ *   tables   host (device with tables_on_device), D x D x ntab float64
+ *            samples of f_ab on `grid`, or NULL for the Newtonian
+ *            short-range factor
  *            erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2) for every pair
  *   ntab     samples per table, >= 2, D * ntab <= NGR_MAX_TABLE
  *   grid     NGR_GRID_R or NGR_GRID_R2; f between samples is the straight
@@ -203,6 +204,10 @@ ngr_status ngr_compute_monopoles(ngr_context* ctx, ngr_tree* tree, int track_cou
  *            times the interpolated correction. Table laws only; periodic
  *            trees only.
  *   corr_n   intervals per axis of the correction tables, 1..512
+ *   tables_on_device  nonzero: `tables` is a device pointer, read in place
+ *            during the call (nothing is copied from the host); its entries
+ *            are checked on the device (NGR_EINVAL if one is not finite).
+ *            Zero: a host pointer, as above.
  */
 typedef struct {
     const double* G;
@@ -223,6 +228,7 @@ typedef struct {
     const double* old_acc;
     const double* lattice_corr;
     uint32_t corr_n;
+    uint32_t tables_on_device;
 } ngr_force_params;
 
 /* Filled by ngr_tree_force (host). An interaction is one evaluation of the

@@ -53,7 +53,7 @@ class ForceParams(C.Structure):
                 ("r_s", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
                 ("group_size", C.c_uint32), ("law", C.c_uint32), ("cored", C.c_uint32), ("beta", C.c_double),
                 ("eps_ab", C.c_void_p), ("opening", C.c_uint32), ("alpha", C.c_double), ("old_acc", C.c_void_p),
-                ("lattice_corr", C.c_void_p), ("corr_n", C.c_uint32)]
+                ("lattice_corr", C.c_void_p), ("corr_n", C.c_uint32), ("tables_on_device", C.c_uint32)]
 
 
 NOT_COUNTED = 2 ** 64 - 1     # NGR_NOT_COUNTED
@@ -263,18 +263,28 @@ def _force_params(D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab=N
     "beta": beta} for the accumulator laws; eps_ab: D x D per-pair softening
     or None; relative: None for the geometric opening test, else {"alpha":
     alpha, "old_acc": device tensor of the previous |a| (n, float64)};
-    lattice_corr: host (D, D, n+1, n+1, n+1, 3) correction tables or None."""
+    lattice_corr: host (D, D, n+1, n+1, n+1, 3) correction tables or None.
+    tables: a host array, or a contiguous float64 device tensor of
+    D x D x ntab samples (read in place by the library)."""
     G = np.ascontiguousarray(G, dtype=np.float64).reshape(D, D)
-    if tables is not None:
+    on_device = tables is not None and bool(getattr(tables, "is_cuda", False))
+    if on_device:
+        if str(tables.dtype) != "torch.float64" or not tables.is_contiguous() or tables.numel() % (D * D):
+            raise ValueError("device tables must be a contiguous float64 tensor of D x D x ntab samples")
+        ntab = tables.numel() // (D * D)
+        tables_ptr = tables.data_ptr()
+    elif tables is not None:
         tables = np.ascontiguousarray(tables, dtype=np.float64).reshape(D, D, -1)
         ntab = tables.shape[-1]
+        tables_ptr = tables.ctypes.data
     law, mask, beta = LAW_TABLE, 0, 0.0
     if accumulator is not None:
         law, beta = LAW_ACCUMULATOR, float(accumulator["beta"])
         for b in accumulator["cored"]:
             mask |= 1 << int(b)
-    fp = ForceParams(G.ctypes.data, None if tables is None else tables.ctypes.data, int(ntab), GRIDS.get(grid, grid),
+    fp = ForceParams(G.ctypes.data, None if tables is None else tables_ptr, int(ntab), GRIDS.get(grid, grid),
                      float(r_s), float(r_cut), float(eps), float(theta), int(group_size), law, mask, beta)
+    fp.tables_on_device = 1 if on_device else 0
     ea = None
     if eps_ab is not None:
         ea = np.ascontiguousarray(eps_ab, dtype=np.float64).reshape(D, D)
@@ -295,7 +305,8 @@ def tree_force(ctx: Context, tree: Tree, *, G, tables, grid, r_cut, eps, theta, 
                group_size: int = 64, ntab: Optional[int] = None, group_counts: bool = False, accumulator=None,
                eps_ab=None, relative=None, lattice_corr=None):
     """ngr_tree_force into the device tensor acc (float64, 3 x n, input order).
-    G (D x D) and tables (D x D x ntab, or None) are host arrays;
+    G (D x D) is a host array; tables (D x D x ntab) a host array, a float64
+    device tensor (read in place), or None;
     accumulator {"cored": [...], "beta": b} selects the accumulator laws.
     Returns the statistics as a dict (and per-group counts when asked)."""
     fp = _force_params(tree.D, G, tables, grid, r_s, r_cut, eps, theta, group_size, ntab, accumulator, eps_ab,
@@ -446,8 +457,9 @@ class PM:
 class BatchBox:
     """One box of a batch: device tensors species (uint8, n), mass (float64,
     n), pos (float64, 3 x n) or lattice (uint64 lattice as int64, 3 x n), and
-    acc (float64, 3 x n, written); host arrays G (D x D) and tables
-    (D x D x ntab, or None); scalars as in tree_build / tree_force.
+    acc (float64, 3 x n, written); host array G (D x D); tables (D x D x
+    ntab) a host array, a float64 device tensor, or None; scalars as in
+    tree_build / tree_force.
     group_size 0 lets the library choose."""
 
     def __init__(self, *, D, box, species, mass, acc, G, tables, grid, r_cut, eps, theta, pos=None, lattice=None,
@@ -494,8 +506,9 @@ class Server:
     def submit(self, *, D, box, species, mass, G, tables, grid, r_cut, eps, theta, dt, steps, pos=None, lattice=None,
                vel=None, leaf_size: int = 16, r_s: float = 0.0, group_size: int = 0, ntab: Optional[int] = None,
                accumulator=None) -> int:
-        """Device tensors species, mass, pos or lattice, vel (or None); host G
-        and tables. The data are copied; returns the request id."""
+        """Device tensors species, mass, pos or lattice, vel (or None); host
+        array G; tables a host array, a float64 device tensor or None. The
+        data are copied; returns the request id."""
         n = int(species.shape[0])
         rq = RequestDesc(Particles(n, D, float(box), _dev(pos), _dev(lattice), _dev(species), _dev(mass)), _dev(vel),
                          TreeParams(leaf_size),

@@ -212,7 +212,7 @@ uint32_t check_force_params(uint32_t D, double box, const ngr_force_params* fp, 
             if (!(std::isfinite(fp->eps_ab[k]) && fp->eps_ab[k] >= 0.0) ||
                 (fp->eps_ab[k] > 0.0 && fp->eps_ab[k] < 1e-12 * box))
                 fail(NGR_EINVAL, where + "eps_ab entries must be finite and 0 or at least 1e-12 box");
-    if (fp->tables)
+    if (fp->tables && !fp->tables_on_device)   // device tables are checked on the device
         for (uint64_t k = 0; k < (uint64_t)D * D * fp->ntab; ++k)
             if (!std::isfinite(fp->tables[k])) fail(NGR_EINVAL, where + "a table entry is not finite");
     return gs;

@@ -222,7 +222,8 @@ struct Law {
     uint32_t D = 0, ntab = 0, grid = 0;
     double G[NGR_MAX_SPECIES * NGR_MAX_SPECIES];
     double r_cut = 0, eps = 0, theta = 0;
-    const double* tables = nullptr;   // host, D x D x ntab samples, or NULL: def for every pair
+    const double* tables = nullptr;   // D x D x ntab samples (host, or device with tables_device), or NULL: def for every pair
+    bool tables_device = false;
     std::vector<double> def;          // host, ntab samples of the Newtonian short-range factor
     uint32_t kind = NGR_LAW_TABLE;    // accumulator laws: cored species mask, beta, N_perp tracking
     uint32_t cored = 0;

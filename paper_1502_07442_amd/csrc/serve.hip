@@ -189,10 +189,13 @@ uint64_t server_submit(Server& s, const ngr_request* rq)
             fail(NGR_ENOMEM, "the request does not fit the server's device memory budget");
         if (s.held_bytes + s.tree_bytes + need + n * kTreeBytesPerParticle > s.budget)
             fail(NGR_ENOMEM, "the server's device memory budget is held by other requests (take finished ones)");
-        if (rq->force.tables) r->tables.assign(rq->force.tables, rq->force.tables + (size_t)D * D * rq->force.ntab);
+        // host tables: a copy kept with the request; device tables are
+        // converted in place below, during this call
+        const bool host_tables = rq->force.tables && !rq->force.tables_on_device;
+        if (host_tables) r->tables.assign(rq->force.tables, rq->force.tables + (size_t)D * D * rq->force.ntab);
         validate_box(ctx, r->in, "");
         make_law(rq->force, D, r->law);
-        r->law.tables = rq->force.tables ? r->tables.data() : nullptr;
+        if (host_tables) r->law.tables = r->tables.data();
         // own copies of the state
         const uint64_t n1 = std::max<uint64_t>(n, 1);
         r->X = static_cast<uint64_t*>(ctx.alloc(3 * n1 * sizeof(uint64_t)));

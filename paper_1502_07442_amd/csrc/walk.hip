@@ -1070,18 +1070,20 @@ inline unsigned blocks_for(uint64_t work, unsigned threads) { return (unsigned)(
 // One box's table conversion: where its FP64 samples are and where its two
 // layouts go.
 struct TableJob {
-    uint64_t raw, pair, value;   // first element in the raw, PAIR and VALUE arrays
+    const double* src;           // the box's float64 samples (device): staged from the host, or the caller's
+    uint64_t pair, value;        // first element in the PAIR and VALUE arrays
     uint32_t pairs, ntab;        // D * D tables of ntab samples
     uint32_t shared;             // 1: one table of ntab samples for every pair
-    uint32_t pad;
+    uint32_t box;
 };
 
 // Both layouts of every table of box blockIdx.y (grid-stride over the box's
 // D * D * ntab entries): PAIR (value, slope to the next sample) with (0, 0)
 // as the last entry; VALUE the samples and a zero pad. Each float is the FP64
-// value (or difference) rounded once.
-__global__ void convert_tables(const TableJob* __restrict__ jobs, const double* __restrict__ raw,
-                               float2* __restrict__ pair, float* __restrict__ value)
+// value (or difference) rounded once. A sample that is not finite lowers
+// *bad_box to the box's index.
+__global__ void convert_tables(const TableJob* __restrict__ jobs, float2* __restrict__ pair,
+                               float* __restrict__ value, uint32_t* __restrict__ bad_box)
 {
     const TableJob J = jobs[blockIdx.y];
     const uint64_t total = (uint64_t)J.pairs * J.ntab;
@@ -1091,7 +1093,8 @@ __global__ void convert_tables(const TableJob* __restrict__ jobs, const double* 
         const uint64_t e = base + threadIdx.x;
         if (e >= total) continue;
         const uint64_t ab = e / J.ntab, k = e % J.ntab;
-        const double* src = raw + J.raw + (J.shared ? 0 : ab * J.ntab);
+        const double* src = J.src + (J.shared ? 0 : ab * J.ntab);
+        if (!isfinite(src[k])) atomicMin(bad_box, J.box);
         pair[J.pair + e] = k + 1 < J.ntab ? make_float2((float)src[k], (float)(src[k + 1] - src[k]))
                                           : make_float2(0.0f, 0.0f);
         value[J.value + ab * (J.ntab + 1) + k] = (float)src[k];
@@ -1183,6 +1186,7 @@ void make_law(const ngr_force_params& fp, uint32_t D, Law& law)
     law.theta = fp.theta;
     for (uint32_t k = 0; k < D * D; ++k) law.G[k] = fp.G[k];
     law.tables = fp.tables;
+    law.tables_device = fp.tables && fp.tables_on_device;
     law.kind = fp.law;
     law.cored = fp.law == NGR_LAW_ACCUMULATOR ? fp.cored : 0u;
     law.beta = fp.beta;
@@ -1212,42 +1216,65 @@ void* upload_tables(Context& ctx, const std::vector<Law>& laws, std::vector<LawT
 {
     const uint32_t nbox = (uint32_t)laws.size();
     std::vector<TableJob> jobs(nbox);
+    std::vector<uint64_t> staged(nbox, 0);   // host samples: their place in the staging array
     uint64_t nraw = 0, np = 0, nv = 0;
     uint32_t max_entries = 0;
+    bool any_device = false;
     for (uint32_t k = 0; k < nbox; ++k) {
         const Law& L = laws[k];
         TableJob& j = jobs[k];
         j.pairs = L.D * L.D;
         j.ntab = L.ntab;
         j.shared = L.tables ? 0u : 1u;
-        j.raw = nraw;
+        j.box = k;
         j.pair = np;
         j.value = nv;
-        nraw += L.tables ? (uint64_t)j.pairs * L.ntab : L.ntab;
+        if (L.tables_device) {
+            any_device = true;
+        } else {
+            staged[k] = nraw;
+            nraw += L.tables ? (uint64_t)j.pairs * L.ntab : L.ntab;
+        }
         np += (uint64_t)j.pairs * L.ntab;
         nv += (uint64_t)j.pairs * (L.ntab + 1);
         max_entries = std::max(max_entries, j.pairs * L.ntab);
     }
-    const size_t raw_bytes = nraw * sizeof(double), job_bytes = nbox * sizeof(TableJob);
+    const size_t raw_bytes = ((nraw * sizeof(double)) + 255) & ~size_t(255), job_bytes = nbox * sizeof(TableJob);
     const size_t pair_bytes = ((np * sizeof(float2)) + 255) & ~size_t(255);
     const size_t value_bytes = ((nv * sizeof(float)) + 255) & ~size_t(255);
     unsigned char* block = static_cast<unsigned char*>(ctx.alloc(pair_bytes + value_bytes));
     float2* pair = reinterpret_cast<float2*>(block);
     float* value = reinterpret_cast<float*>(block + pair_bytes);
-    unsigned char* stage = static_cast<unsigned char*>(ctx.alloc(raw_bytes + job_bytes));
+    unsigned char* stage = static_cast<unsigned char*>(ctx.alloc(raw_bytes + job_bytes + sizeof(uint64_t)));
     double* raw = reinterpret_cast<double*>(stage);
     TableJob* jobs_dev = reinterpret_cast<TableJob*>(stage + raw_bytes);
+    uint32_t* bad_box = reinterpret_cast<uint32_t*>(stage + raw_bytes + job_bytes);   // 8 bytes, 8-aligned
+    for (uint32_t k = 0; k < nbox; ++k) jobs[k].src = laws[k].tables_device ? laws[k].tables : raw + staged[k];
     ctx.sync();
     for (uint32_t k = 0; k < nbox; ++k) {
         const Law& L = laws[k];
+        if (L.tables_device) continue;   // read in place by the conversion
         const double* src = L.tables ? L.tables : L.def.data();
         const size_t cnt = L.tables ? (size_t)jobs[k].pairs * L.ntab : L.ntab;
-        HIP_CHECK(hipMemcpyAsync(raw + jobs[k].raw, src, cnt * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+        HIP_CHECK(hipMemcpyAsync(raw + staged[k], src, cnt * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
     }
     HIP_CHECK(hipMemcpyAsync(jobs_dev, jobs.data(), job_bytes, hipMemcpyHostToDevice, ctx.stream));
+    HIP_CHECK(hipMemsetAsync(bad_box, 0xff, sizeof(uint64_t), ctx.stream));
     const unsigned gx = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_for(max_entries, 256), 64));
-    hipLaunchKernelGGL(convert_tables, dim3(gx, nbox), dim3(256), 0, ctx.stream, jobs_dev, raw, pair, value);
+    hipLaunchKernelGGL(convert_tables, dim3(gx, nbox), dim3(256), 0, ctx.stream, jobs_dev, pair, value, bad_box);
     LAUNCH_CHECK("convert_tables");
+    if (any_device) {
+        // host tables were checked before the call; a device table is checked here
+        uint64_t w = 0;
+        ctx.read_words(&w, bad_box, 1);
+        const uint32_t k = (uint32_t)(w & 0xffffffffu);
+        if (k != 0xffffffffu) {
+            ctx.release(stage);
+            ctx.release(block);
+            fail(NGR_EINVAL, (nbox > 1 ? "box " + std::to_string(k) + ": " : std::string()) +
+                                 "a table entry is not finite");
+        }
+    }
     ctx.sync();                        // the caller's host tables are no longer read after this
     ctx.release(stage);
     out.resize(nbox);

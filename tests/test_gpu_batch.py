@@ -1,6 +1,8 @@
 """Many independent boxes in one call (ngr_batch_build_force): every box's
 accelerations and counts are bitwise those of its single-box calls, its
 counts equal the oracle's and its forces pass the oracle gate."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -31,12 +33,16 @@ def first_particles(p, n):
                                pos=p.pos[:, :n].copy())
 
 
-def run_batch(ctx, probs, group_sizes):
+def run_batch(ctx, probs, group_sizes, device_tables=None):
+    """device_tables: per box, pass its tables as a device tensor (default: host arrays)."""
     import torch
     boxes, accs = [], []
-    for p, gs in zip(probs, group_sizes):
+    for k, (p, gs) in enumerate(zip(probs, group_sizes)):
         acc = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
-        boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=p.tables, grid=p.grid, r_cut=p.r_cut,
+        tab = p.tables
+        if device_tables is not None and device_tables[k] and tab is not None:
+            tab = torch.from_numpy(np.ascontiguousarray(tab, dtype=np.float64)).cuda()
+        boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=tab, grid=p.grid, r_cut=p.r_cut,
                                   eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=gs,
                                   **device_inputs(p)))
         accs.append(acc)
@@ -81,6 +87,48 @@ def test_mixed_boxes_equal_single_box_calls(ctx):
     assert st["n_particles"] == sum(p.n for p in probs)
     for p, acc, b in zip(probs, accs, pb):
         check_box(ctx, p, acc, b)
+
+
+def test_device_tables_equal_host_tables(ctx):
+    """Tables handed over as device tensors (read in place, no host copy)
+    give the bits of the same tables passed as host arrays, in a batch and in
+    a single-box call; a non-finite device sample is refused."""
+    import torch
+    probs = [synth.batch_box(k) for k in range(6)] + [synth.uniform_problem(300, 2, 21, grid=synth.GRID_R2)]
+    print("case 7 boxes, host against device tables (alternate boxes, then all)", flush=True)
+    st_h, pb_h, acc_h = run_batch(ctx, probs, [0] * len(probs))
+    st_d, pb_d, acc_d = run_batch(ctx, probs, [0] * len(probs), device_tables=[k % 2 == 0 for k in range(7)])
+    st_a, pb_a, acc_a = run_batch(ctx, probs, [0] * len(probs), device_tables=[True] * 7)
+    for k in range(len(probs)):
+        assert np.array_equal(acc_h[k], acc_d[k]) and np.array_equal(acc_h[k], acc_a[k]), k
+        for key in STAT_KEYS:
+            assert pb_h[k][key] == pb_d[k][key] == pb_a[k][key], (k, key)
+    p = probs[1]
+    t = device_inputs(p)
+    tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
+    ngr.compute_monopoles(ctx, tree)
+    acc = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
+    dev_tab = torch.from_numpy(np.ascontiguousarray(p.tables, dtype=np.float64)).cuda()
+    st1 = ngr.tree_force(ctx, tree, G=p.G, tables=dev_tab, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                         group_size=pb_h[1]["group_size"], acc=acc)
+    assert np.array_equal(acc.cpu().numpy(), acc_h[1])
+    assert st1["interactions_pp"] == pb_h[1]["interactions_pp"]
+    bad = np.array(p.tables, dtype=np.float64, copy=True)
+    bad.reshape(-1)[bad.size // 2] = float("nan")
+    with pytest.raises(ngr.NgravsError) as e:
+        ngr.tree_force(ctx, tree, G=p.G, tables=torch.from_numpy(bad).cuda(), grid=p.grid, r_cut=p.r_cut,
+                       eps=p.eps, theta=p.theta, group_size=pb_h[1]["group_size"], acc=acc)
+    assert e.value.status == ngr.EINVAL and "not finite" in str(e.value)
+    ngr.tree_free(ctx, tree)
+    probs_bad = [probs[0], dataclasses.replace(probs[1], tables=bad)]
+    with pytest.raises(ngr.NgravsError) as e:
+        run_batch(ctx, probs_bad, [0, 0], device_tables=[True, True])
+    assert e.value.status == ngr.EINVAL and "box 1" in str(e.value) and "not finite" in str(e.value)
+    q = probs[0]
+    with pytest.raises(ValueError):   # device tables must be float64
+        ngr.BatchBox(D=q.D, box=q.box, acc=torch.empty((3, q.n), dtype=torch.float64, device="cuda"), G=q.G,
+                     tables=torch.zeros(q.D * q.D * 8, dtype=torch.float32, device="cuda"), grid=q.grid,
+                     r_cut=q.r_cut, eps=q.eps, theta=q.theta, **device_inputs(q))
 
 
 def test_workload_batch_of_256_boxes(ctx, capsys):

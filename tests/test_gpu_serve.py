@@ -254,3 +254,37 @@ def test_sixteen_requests_alone_and_mixed(ctx):
         alone = run(ctx, [p], [steps[j]])[0]
         for a, b in zip(alone, mix[j]):
             assert np.array_equal(a, b), (p.name, j)
+
+
+def test_device_table_request(ctx):
+    """A request whose tables are a device tensor (converted in place at
+    submit) steps exactly as the same request with host tables; a device
+    table with a non-finite sample is refused at submit."""
+    import torch
+    p = synth.clustered_problem(4096, 3, 5, ntab=512)
+    finals = []
+    for on_device in (False, True):
+        srv = ngr.Server(ctx)
+        tab = torch.from_numpy(np.ascontiguousarray(p.tables, dtype=np.float64)).cuda() if on_device else p.tables
+        rid = srv.submit(D=p.D, box=p.box, G=p.G, tables=tab, grid=p.grid, r_cut=p.r_cut, eps=p.eps, theta=p.theta,
+                         r_s=p.r_s, dt=1e-3, steps=3, leaf_size=p.leaf_size, group_size=p.group_size,
+                         **device_inputs(p))
+        del tab                               # the request no longer reads the caller's tables
+        for _ in range(10):
+            if srv.status(rid)[0] == ngr.FINISHED:
+                break
+            srv.tick()
+        assert srv.status(rid)[0] == ngr.FINISHED
+        finals.append(take(srv, rid, p.n))
+        srv.close()
+    for a, b in zip(*finals):
+        assert np.array_equal(a, b)
+    bad = np.array(p.tables, dtype=np.float64, copy=True)
+    bad.reshape(-1)[7] = float("inf")
+    srv = ngr.Server(ctx)
+    with pytest.raises(ngr.NgravsError) as e:
+        srv.submit(D=p.D, box=p.box, G=p.G, tables=torch.from_numpy(bad).cuda(), grid=p.grid, r_cut=p.r_cut,
+                   eps=p.eps, theta=p.theta, r_s=p.r_s, dt=1e-3, steps=3, leaf_size=p.leaf_size,
+                   group_size=p.group_size, **device_inputs(p))
+    assert e.value.status == ngr.EINVAL and "not finite" in str(e.value)
+    srv.close()
