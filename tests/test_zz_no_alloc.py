@@ -22,7 +22,9 @@ def ctx():
     c.close()
 
 
-def both(ctx, p):
+def both(ctx, p, device_tables=False):
+    """ngr_tree_force with host tables, and ngr_tree_force_noalloc with the
+    same tables as host arrays or (device_tables) as a device tensor."""
     import torch
     t = device_inputs(p)
     tree = ngr.tree_build(ctx, D=p.D, box=p.box, leaf_size=p.leaf_size, **t)
@@ -32,6 +34,8 @@ def both(ctx, p):
                   group_size=p.group_size, r_s=p.r_s)
         a_ref = torch.empty((3, p.n), dtype=torch.float64, device="cuda")
         st_ref = ngr.tree_force(ctx, tree, acc=a_ref, **kw)
+        if device_tables:
+            kw["tables"] = torch.from_numpy(np.ascontiguousarray(p.tables, dtype=np.float64)).cuda()
         a_na = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
         st_na = ngr.tree_force_noalloc(ctx, tree, acc=a_na, **kw)
         return a_ref.cpu().numpy(), st_ref, a_na.cpu().numpy(), st_na
@@ -39,9 +43,9 @@ def both(ctx, p):
         ngr.tree_free(ctx, tree)
 
 
-def check(ctx, p):
-    print(f"case {p.name} n={p.n} D={p.D}", flush=True)
-    a_ref, st_ref, a_na, st_na = both(ctx, p)
+def check(ctx, p, device_tables=False):
+    print(f"case {p.name} n={p.n} D={p.D} device tables {device_tables}", flush=True)
+    a_ref, st_ref, a_na, st_na = both(ctx, p, device_tables)
     assert np.array_equal(a_ref, a_na)
     for k in ("interactions_pp", "interactions_pn", "n_groups", "group_size", "interactions_pn_species"):
         assert st_ref[k] == st_na[k], k
@@ -51,6 +55,13 @@ def check(ctx, p):
 def test_two_calls_second_smaller(ctx):
     check(ctx, synth.clustered_problem(2 ** 17, 6, 21))
     check(ctx, synth.clustered_problem(3000, 2, 22, ntab=512, grid="r"))
+
+
+def test_device_tables(ctx):
+    """Tables handed over as a device tensor: the static scratch stages none
+    of them, and the result is the host-table call's, bit for bit."""
+    check(ctx, synth.clustered_problem(20000, 4, 26, ntab=1024), device_tables=True)
+    check(ctx, synth.clustered_problem(3000, 2, 27, ntab=512, grid="r"), device_tables=True)
 
 
 def test_accumulator_laws_and_softening_zero(ctx):
