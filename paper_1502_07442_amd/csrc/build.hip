@@ -433,6 +433,7 @@ __global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t 
         const uint4 c = cell[i];
         const double cx = (double)c.x * 0x1p-20, cy = (double)c.y * 0x1p-20, cz = (double)c.z * 0x1p-20;
         uint64_t j0 = start[i * D + b], j1 = j0 + count[i * D + b];
+#pragma unroll 4
         for (uint64_t j = j0; j < j1; ++j) {
             const PRec q = P[j];
             const double m = q.m;
@@ -443,14 +444,20 @@ __global__ void monopole_level(uint64_t level_begin, uint64_t n_level, uint32_t 
         }
         out = M > 0.0 ? make_double4(cx + sx / M, cy + sy / M, cz + sz / M, M) : make_double4(0.0, 0.0, 0.0, 0.0);
     } else {
-        uint64_t c0 = (uint64_t)first_child[i], c1 = c0 + n_child[i];
-        for (uint64_t c = c0; c < c1; ++c) {
-            double4 r = mono[b * nn + c];
-            if (r.w > 0.0) {
-                M += r.w;
-                sx += r.w * r.x;
-                sy += r.w * r.y;
-                sz += r.w * r.z;
+        // at most eight children: their records are loaded together, then
+        // added in child order
+        const uint64_t c0 = (uint64_t)first_child[i];
+        const uint32_t nc = n_child[i];
+        double4 r[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) r[k] = k < nc ? mono[b * nn + c0 + k] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            if (r[k].w > 0.0) {
+                M += r[k].w;
+                sx += r[k].w * r[k].x;
+                sy += r[k].w * r[k].y;
+                sz += r[k].w * r[k].z;
             }
         }
         out = M > 0.0 ? make_double4(sx / M, sy / M, sz / M, M) : make_double4(0.0, 0.0, 0.0, 0.0);
