@@ -268,23 +268,25 @@ __global__ void split_level(uint64_t level_begin, uint64_t n_level, uint32_t lvl
     const uint32_t o = (uint32_t)(t % 8);
     uint32_t total = 0;
     for (uint32_t b = 0; b < D; ++b) total += count[p * D + b];
-    // every lane runs the species loop below (the exchange needs its neighbour)
-    const bool split = total > leaf_size[node_box[p]] && lvl < (uint32_t)kLevels;
+    // a node's eight lanes leave together, so a lane's neighbour in the
+    // exchange below (the next octant of the same node) is always active
+    if (total <= leaf_size[node_box[p]] || lvl >= (uint32_t)kLevels) {
+        flags[t] = 0;
+        return;
+    }
     const uint32_t sh = kKeyBits - 3 * (lvl + 1);
     const uint64_t klo = (prefix[p] * 8 + o) << sh;
     uint32_t tot = 0;
     for (uint32_t b = 0; b < D; ++b) {
         const uint32_t lo = start[p * D + b], hi = lo + count[p * D + b];
-        const uint32_t a0 = split ? (uint32_t)lower_bound(keys, lo, hi, ((uint64_t)b << kKeyBits) + klo) : lo;
+        const uint32_t a0 = (uint32_t)lower_bound(keys, lo, hi, ((uint64_t)b << kKeyBits) + klo);
         const uint32_t next = __shfl_down(a0, 1);
         const uint32_t a1 = o == 7 ? hi : next;
-        if (split) {
-            cstart[t * D + b] = a0;
-            ccount[t * D + b] = a1 - a0;
-            tot += a1 - a0;
-        }
+        cstart[t * D + b] = a0;
+        ccount[t * D + b] = a1 - a0;
+        tot += a1 - a0;
     }
-    flags[t] = split && tot > 0;
+    flags[t] = tot > 0;
 }
 
 // The same split for a level of few nodes, one wave per node: lane 8·o + b

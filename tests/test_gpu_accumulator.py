@@ -120,7 +120,8 @@ def test_batch_mixed_law_kinds(ctx):
     """Table-law boxes and accumulator boxes in one call: each bitwise equal
     to its single-box call, counts equal to the oracle's. The call walks each
     law kind in a launch of its own; the second table-law box has groups of
-    33 to 48 sinks, which the table-law walk runs as blocks of 16 sinks."""
+    33 to 48 sinks, which the table-law walk runs as blocks of 16 sinks. The
+    tables handed over as device tensors give the same bits."""
     import torch
     probs = [(synth.clustered_problem(6000, 2, 31, grid=synth.GRID_R2, ntab=512), 32),
              (synth.accumulator_problem(9000, 32, ntab=512), 32),
@@ -143,6 +144,19 @@ def test_batch_mixed_law_kinds(ctx):
         ao, so, co, _ = oracle.Tree.of(p, group_size=gs).force(oracle.law_of(p))
         assert (st["interactions_pp"], st["interactions_pn"]) == (co["pp"], co["pn"]), p.name
         assert force_gate(a, ao, so)[0], p.name
+    # the same call with every box's tables handed over as a device tensor
+    dev_boxes, dev_accs = [], []
+    for p, gs in probs:
+        acc = torch.full((3, p.n), float("nan"), dtype=torch.float64, device="cuda")
+        tab = torch.from_numpy(np.ascontiguousarray(p.tables, dtype=np.float64)).cuda()
+        dev_boxes.append(ngr.BatchBox(D=p.D, box=p.box, acc=acc, G=p.G, tables=tab, grid=p.grid, r_cut=p.r_cut,
+                                      eps=p.eps, theta=p.theta, r_s=p.r_s, leaf_size=p.leaf_size, group_size=gs,
+                                      accumulator=getattr(p, "accumulator", None), **device_inputs(p)))
+        dev_accs.append(acc)
+    _, pbd = ngr.batch_build_force(ctx, dev_boxes, per_box=True)
+    for (p, _), a_h, a_d, s_h, s_d in zip(probs, accs, dev_accs, pb, pbd):
+        assert torch.equal(a_h, a_d), p.name
+        assert (s_h["interactions_pp"], s_h["interactions_pn"]) == (s_d["interactions_pp"], s_d["interactions_pn"])
 
 
 @pytest.mark.parametrize("bad", [dict(beta=0.0), dict(beta=float("nan")), dict(cored=[2]), dict(law=2)])
