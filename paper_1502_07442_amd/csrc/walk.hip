@@ -174,13 +174,16 @@ __global__ void segment_firsts(uint32_t k, const uint64_t* __restrict__ pos, con
 }
 
 // ------------------------------------------------------- group order ----
-// The walk hands out each segment's groups heaviest first, estimated from the
-// particle density around each group: particles per cell of a level-L grid
-// of the group's box (cells at least r_cut wide), summed over the 5 x 5 x 5
-// cells around the group's first particle. Cells of level L carry the total
+// The walk hands out each segment's groups heaviest first. A group's cost is
+// estimated as the number of particles within reach of its box times the
+// share of a wave pass its sinks take: the particles are counted on a level-L
+// grid of the group's simulation box (cells at least r_cut wide) over the
+// cells that the group's bounding box covers, grown by one cell on every
+// side; the share is 1/4, 1/2, 3/4 or 1 for groups of at most 16, 32, 48 or
+// 64 sinks (the lane mappings of the walk). Cells of level L carry the total
 // count of their node; particles of leaves above level L are counted one by
-// one.
-constexpr int kOrderRadius = 2;
+// one. The grid is then turned into a summed-volume table, so that any block
+// of cells costs eight reads.
 
 __global__ void density_grid(uint64_t nodes, uint32_t D, const uint32_t* __restrict__ Lbox,
                              const uint64_t* __restrict__ Hoff, const uint32_t* __restrict__ node_box,
@@ -211,39 +214,104 @@ __global__ void density_grid(uint64_t nodes, uint32_t D, const uint32_t* __restr
     }
 }
 
-// Sort key of every group: its segment, then the density bucket descending
-// (half-octave steps of the neighbourhood count); value: the group index.
-__global__ void group_order_keys(uint64_t ng, uint64_t n, uint32_t D, const uint32_t* __restrict__ gstart,
-                                 const uint32_t* __restrict__ gbox, const uint32_t* __restrict__ Lbox,
-                                 const uint64_t* __restrict__ Hoff, const uint64_t* __restrict__ keys,
-                                 const uint64_t* __restrict__ X, const uint32_t* __restrict__ Hall,
+// Inclusive prefix sums of every box's grid along one axis (2: z, 1: y, 0: x);
+// after all three the grid is a summed-volume table. One thread per line;
+// Loff[k] is the first line of box k (boxes without a grid have none).
+__global__ void density_prefix(uint64_t lines, uint32_t nbox, uint32_t axis, const uint32_t* __restrict__ Lbox,
+                               const uint64_t* __restrict__ Hoff, const uint64_t* __restrict__ Loff,
+                               uint32_t* __restrict__ Hall)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= lines) return;
+    uint32_t lo = 0, hi = nbox;   // the box: the last k with Loff[k] <= t
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (Loff[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t L = Lbox[lo];
+    const uint64_t li = t - Loff[lo], N = 1ull << L;
+    const uint64_t u = li >> L, w = li & (N - 1);   // the line's two other coordinates
+    uint64_t base, stride;
+    if (axis == 2) {
+        base = (u << (2 * L)) | (w << L);            // (x, y) = (u, w)
+        stride = 1;
+    } else if (axis == 1) {
+        base = (u << (2 * L)) | w;                   // (x, z) = (u, w)
+        stride = N;
+    } else {
+        base = (u << L) | w;                         // (y, z) = (u, w)
+        stride = N * N;
+    }
+    uint32_t* H = Hall + Hoff[lo] + base;
+    uint32_t sum = 0;
+    for (uint64_t i = 0; i < N; ++i) {
+        sum += H[i * stride];
+        H[i * stride] = sum;
+    }
+}
+
+// Sort key of every group: its segment, then the cost bucket descending
+// (half-octave steps of the estimate above); value: the group index.
+__global__ void group_order_keys(uint64_t ng, uint32_t D, const uint32_t* __restrict__ gstart,
+                                 const uint32_t* __restrict__ gcount, const uint32_t* __restrict__ glo,
+                                 const uint32_t* __restrict__ ghi, const uint32_t* __restrict__ gbox,
+                                 const uint32_t* __restrict__ Lbox, const uint64_t* __restrict__ Hoff,
+                                 const uint64_t* __restrict__ keys, const uint32_t* __restrict__ Hall,
                                  uint64_t* __restrict__ okey, uint32_t* __restrict__ oval)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
-    const uint64_t j = gstart[g];
     const uint32_t box = gbox[g];
     const uint32_t L = Lbox[box];
-    uint32_t v = 1;
+    uint64_t v = 1;
     if (L > 0) {
-        const uint32_t* H = Hall + Hoff[box];
-        const int32_t m = (1 << L) - 1;
-        const int32_t x = (int32_t)(X[j] >> (64 - L)), y = (int32_t)(X[n + j] >> (64 - L)),
-                      z = (int32_t)(X[2 * n + j] >> (64 - L));
-        for (int32_t dx = -kOrderRadius; dx <= kOrderRadius; ++dx)
+        const uint32_t* S = Hall + Hoff[box];
+        const uint32_t sh = (uint32_t)kLevels - L;
+        const int32_t N = 1 << L;
+        // per axis, the grown block as one or two cell ranges (periodic wrap)
+        int32_t r0[3][2], r1[3][2], nr[3];
 #pragma unroll
-            for (int32_t dy = -kOrderRadius; dy <= kOrderRadius; ++dy)
-#pragma unroll
-                for (int32_t dz = -kOrderRadius; dz <= kOrderRadius; ++dz) {
-                    const uint64_t q = ((uint64_t)((x + dx) & m) << (2 * L)) | ((uint64_t)((y + dy) & m) << L) |
-                                       (uint64_t)((z + dz) & m);
-                    v += H[q];
+        for (int a = 0; a < 3; ++a) {
+            const int32_t c0 = (int32_t)(glo[a * ng + g] >> sh) - 1, c1 = (int32_t)((ghi[a * ng + g] - 1u) >> sh) + 1;
+            r0[a][1] = r1[a][1] = 0;
+            if (c1 - c0 + 1 >= N) {
+                nr[a] = 1;
+                r0[a][0] = 0;
+                r1[a][0] = N - 1;
+            } else {
+                const int32_t a0 = (c0 + N) & (N - 1), a1 = c1 & (N - 1);
+                if (a0 <= a1) {
+                    nr[a] = 1;
+                    r0[a][0] = a0;
+                    r1[a][0] = a1;
+                } else {
+                    nr[a] = 2;
+                    r0[a][0] = a0;
+                    r1[a][0] = N - 1;
+                    r0[a][1] = 0;
+                    r1[a][1] = a1;
+                }
+            }
+        }
+        auto at = [&](int32_t x, int32_t y, int32_t z) -> uint64_t {
+            return (x < 0 || y < 0 || z < 0) ? 0ull : (uint64_t)S[((uint64_t)x << (2 * L)) | ((uint64_t)y << L) | (uint64_t)z];
+        };
+        for (int i = 0; i < nr[0]; ++i)
+            for (int j = 0; j < nr[1]; ++j)
+                for (int k = 0; k < nr[2]; ++k) {
+                    const int32_t x0 = r0[0][i] - 1, x1 = r1[0][i], y0 = r0[1][j] - 1, y1 = r1[1][j], z0 = r0[2][k] - 1,
+                                  z1 = r1[2][k];
+                    v += at(x1, y1, z1) - at(x0, y1, z1) - at(x1, y0, z1) - at(x1, y1, z0) + at(x0, y0, z1) +
+                         at(x0, y1, z0) + at(x1, y0, z0) - at(x0, y0, z0);
                 }
     }
-    const uint32_t msb = 31u - (uint32_t)__builtin_clz(v);
-    const uint32_t half = msb ? (v >> (msb - 1)) & 1u : 0u;
-    const uint32_t bucket = 2u * msb + half;            // < 64
-    const uint64_t seg = (uint64_t)box * D + (keys[j] >> kKeyBits);
+    const uint32_t ns = gcount[g];
+    v *= ns <= 16u ? 1u : ns <= 32u ? 2u : ns <= 48u ? 3u : 4u;
+    const uint32_t msb = 63u - (uint32_t)__builtin_clzll(v);
+    const uint32_t half = msb ? (uint32_t)(v >> (msb - 1)) & 1u : 0u;
+    const uint32_t bucket = 2u * msb + half;            // < 128
+    const uint64_t seg = (uint64_t)box * D + (keys[gstart[g]] >> kKeyBits);
     okey[g] = (seg << 8) | (255u - bucket);
     oval[g] = (uint32_t)g;
 }
@@ -1361,9 +1429,20 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
         hipLaunchKernelGGL(density_grid, dim3(blocks_for(nodes, 256)), dim3(256), 0, ctx.stream, nodes, t.D, Ld, Hoffd,
                            t.node_box, t.cell, t.n_child, t.start, t.count, t.X, t.n, H);
         LAUNCH_CHECK("density_grid");
+        // the summed-volume table: prefix sums along z, y and x
+        std::vector<uint64_t> Loff(nbox + 1, 0);
+        for (uint32_t k = 0; k < nbox; ++k) Loff[k + 1] = Loff[k] + (L[k] ? (1ull << (2 * L[k])) : 0);
+        uint64_t* Loffd = static_cast<uint64_t*>(ctx.alloc((nbox + 1) * sizeof(uint64_t)));
+        ctx.to_device(Loffd, Loff.data(), (nbox + 1) * sizeof(uint64_t));
+        for (uint32_t axis = 3; axis-- > 0;) {
+            hipLaunchKernelGGL(density_prefix, dim3(blocks_for(Loff[nbox], 256)), dim3(256), 0, ctx.stream, Loff[nbox],
+                               nbox, axis, Ld, Hoffd, Loffd, H);
+            LAUNCH_CHECK("density_prefix");
+        }
+        ctx.release(Loffd);
     }
-    hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.n, t.D, g.start,
-                       g.box, Ld, Hoffd, t.keys, t.X, H, okey, oval);
+    hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.D, g.start,
+                       g.count, g.lo, g.hi, g.box, Ld, Hoffd, t.keys, H, okey, oval);
     LAUNCH_CHECK("group_order_keys");
     int bits = 8;
     while ((1ull << (bits - 8)) < g.nseg) bits += 8;
