@@ -214,6 +214,13 @@ __global__ void density_grid(uint64_t nodes, uint32_t D, const uint32_t* __restr
     }
 }
 
+// A group's estimated work from its cost bucket b (half-octave steps):
+// 2^(b/2), exact for even b and 1.5 times the lower power for odd b.
+__device__ inline unsigned long long bucket_weight(uint32_t b)
+{
+    return (b & 1u) ? (3ull << (b >> 1)) >> 1 : 1ull << (b >> 1);
+}
+
 // Inclusive prefix sums of every box's grid along one axis (2: z, 1: y, 0: x);
 // after all three the grid is a summed-volume table. One thread per line;
 // Loff[k] is the first line of box k (boxes without a grid have none).
@@ -258,7 +265,8 @@ __global__ void group_order_keys(uint64_t ng, uint32_t D, const uint32_t* __rest
                                  const uint32_t* __restrict__ ghi, const uint32_t* __restrict__ gbox,
                                  const uint32_t* __restrict__ Lbox, const uint64_t* __restrict__ Hoff,
                                  const uint64_t* __restrict__ keys, const uint32_t* __restrict__ Hall,
-                                 uint64_t* __restrict__ okey, uint32_t* __restrict__ oval)
+                                 uint64_t* __restrict__ okey, uint32_t* __restrict__ oval,
+                                 uint32_t* __restrict__ gbucket)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
@@ -314,6 +322,27 @@ __global__ void group_order_keys(uint64_t ng, uint32_t D, const uint32_t* __rest
     const uint64_t seg = (uint64_t)box * D + (keys[gstart[g]] >> kKeyBits);
     okey[g] = (seg << 8) | (255u - bucket);
     oval[g] = (uint32_t)g;
+    gbucket[g] = bucket;
+}
+
+// Estimated work of every segment, the sum of its groups' weights: one
+// workgroup per segment (a segment's groups are consecutive).
+__global__ __launch_bounds__(256) void seg_work_init(const uint32_t* __restrict__ seg_first,
+                                                     const uint32_t* __restrict__ gbucket,
+                                                     unsigned long long* __restrict__ seg_work)
+{
+    __shared__ unsigned long long part[256];
+    const uint32_t s = blockIdx.x;
+    const uint32_t g0 = seg_first[s], g1 = seg_first[s + 1];
+    unsigned long long sum = 0;
+    for (uint32_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) sum += bucket_weight(gbucket[g]);
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) seg_work[s] = part[0];
 }
 
 // --------------------------------------------------------------- walk ----
@@ -394,6 +423,8 @@ struct WalkArgs {
     const uint32_t* order;     // group indices: segment by segment, heaviest first
     const uint32_t* seg_first; // nseg + 1: groups of segment s are order[seg_first[s] .. seg_first[s + 1])
     uint32_t* queues;          // nseg: groups of each segment handed out so far
+    unsigned long long* seg_work;   // nseg: estimated work of the groups not yet handed out
+    const uint32_t* gbucket;   // per group: its cost bucket (the queue order's estimate)
     const uint32_t* sched;     // non-empty segments, most groups first
     uint32_t nsched;
     uint32_t* cursor;          // next entry of sched to start
@@ -691,6 +722,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
         const uint32_t ticket = uniform(atomicAdd(queue, lane == 0 ? 1u : 0u));
         if (ticket >= g_count) break;
         const uint32_t g = A.order[g_begin + ticket];
+        // the segment's work left drops by this group's weight; as for the
+        // ticket, every lane executes the atomic (lane 0 subtracts)
+        const unsigned long long wq = bucket_weight(uniform(A.gbucket[g]));
+        atomicAdd(A.seg_work + seg, lane == 0 ? 0ull - wq : 0ull);
         const uint32_t s0 = A.gstart[g], ns = A.gcount[g];
         uint32_t lo[3], hi[3];
         bool wrap = false;
@@ -1093,7 +1128,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
     }
         __syncthreads();                   // every wave is done with this segment's tables and counts
         if (wave == 0) {
-            // next segment: the next one not started, else the one with the most groups left
+            // next segment: the next one not started, else the one with the most
+            // estimated work left (ranked at least 1 while a group is left)
             const uint32_t t = uniform(atomicAdd(A.cursor, lane == 0 ? 1u : 0u));
             uint32_t next = A.nseg;
             if (t < A.nsched) {
@@ -1104,8 +1140,11 @@ __global__ __launch_bounds__(kMaxWaves * 64) void walk_kernel(WalkArgs A)
                     const uint32_t cnt = A.seg_first[q + 1] - A.seg_first[q];
                     const uint32_t h = __hip_atomic_load(A.queues + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     const uint32_t left = cnt - min(h, cnt);
-                    if (left > best) {
-                        best = left;
+                    const unsigned long long wl =
+                        __hip_atomic_load(A.seg_work + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t rank = left ? (uint32_t)min((wl >> 12) + 1ull, 0xffffffffull) : 0u;
+                    if (rank > best) {
+                        best = rank;
                         best_s = q;
                     }
                 }
@@ -1391,7 +1430,8 @@ static const float2* upload_core_table(Context& ctx)
 // Group indices segment by segment, each segment's groups in descending
 // order of the density estimate (ties in tree order). Returns device memory
 // of g.ng entries, to be released by the caller.
-static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws)
+static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, const std::vector<Law>& laws,
+                              uint32_t* gbucket)
 {
     const uint64_t ng = g.ng;
     const uint32_t nbox = t.nbox;
@@ -1442,7 +1482,7 @@ static uint32_t* order_groups(Context& ctx, const Tree& t, const Groups& g, cons
         ctx.release(Loffd);
     }
     hipLaunchKernelGGL(group_order_keys, dim3(blocks_for(ng, 256)), dim3(256), 0, ctx.stream, ng, t.D, g.start,
-                       g.count, g.lo, g.hi, g.box, Ld, Hoffd, t.keys, H, okey, oval);
+                       g.count, g.lo, g.hi, g.box, Ld, Hoffd, t.keys, H, okey, oval, gbucket);
     LAUNCH_CHECK("group_order_keys");
     int bits = 8;
     while ((1ull << (bits - 8)) < g.nseg) bits += 8;
@@ -1636,7 +1676,12 @@ static void walk_launch(Context& ctx, const Tree& t, const Groups& g, const std:
         HIP_CHECK(hipEventCreate(&e2));
         HIP_CHECK(hipEventRecord(e0, ctx.stream));
     }
-    uint32_t* order = order_groups(ctx, t, g, laws);
+    uint32_t* gbucket = static_cast<uint32_t*>(ctx.alloc(std::max<uint64_t>(g.ng, 1) * sizeof(uint32_t)));
+    uint32_t* order = order_groups(ctx, t, g, laws, gbucket);
+    unsigned long long* seg_work =
+        static_cast<unsigned long long*>(ctx.alloc(std::max<uint32_t>(nseg, 1) * sizeof(unsigned long long)));
+    hipLaunchKernelGGL(seg_work_init, dim3(nseg), dim3(256), 0, ctx.stream, seg_first, gbucket, seg_work);
+    LAUNCH_CHECK("seg_work_init");
 
     WalkArgs A{};
     A.cell = t.cell;
@@ -1661,6 +1706,8 @@ static void walk_launch(Context& ctx, const Tree& t, const Groups& g, const std:
     A.order = order;
     A.seg_first = seg_first;
     A.queues = queues;
+    A.seg_work = seg_work;
+    A.gbucket = gbucket;
     A.sched = sched_dev;
     A.nsched = nsched;
     A.cursor = cursor;
@@ -1736,6 +1783,8 @@ static void walk_launch(Context& ctx, const Tree& t, const Groups& g, const std:
     ctx.to_host(&herr, err, sizeof herr);
     ctx.stage("walk: done");
     ctx.release(order);
+    ctx.release(seg_work);
+    ctx.release(gbucket);
     ctx.release(ctl);
     ctx.release(boxes);
     if (corr_dev) ctx.release(corr_dev);
